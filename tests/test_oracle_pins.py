@@ -1,0 +1,462 @@
+"""Pins of the CPU oracle to the paper and to mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: matrices and
+numbers printed in the paper, identities between two printed formulas, exact
+invariants of the scheme (fixed points, conservation, symmetry), and the
+second-order equivalent equations of the Taylor-expansion method (sections 3
+and 8) for the sound speed and the damping of small waves.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import sympy as sp
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")
+
+
+def printed():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def sym_matrix(rows, lam, cp, rho0):
+    L, C, R = sp.symbols("lam cp rho0")
+    M = sp.Matrix([[sp.sympify(x) for x in r] for r in rows])
+    return np.array(M.subs({L: lam, C: cp, R: rho0}).evalf(30), dtype=float)
+
+
+ODD = dict(lam=1.7, cp=2.3, rho0=1.3, gamma=1.31, prandtl=0.71, c0=0.61,
+           s0=0.37, s_e=1.37, s_eps=1.1)
+
+
+def odd_params(**kw):
+    d = dict(ODD)
+    d.update(kw)
+    return oracle.Params(**d)
+
+
+def random_state(rng, n, p, amp=0.05, u=0.05, ds=0.1):
+    """Equilibrium state near (rho0, u=0, s0), then a few steps to leave it."""
+    x = np.arange(n)
+    rho = p.rho0 * (1 + amp * rng.uniform(-1, 1, n))
+    J = rho * u * p.lam * rng.uniform(-1, 1, n)
+    zeta = rho * (p.s0 + ds * p.cp * rng.uniform(-1, 1, n))
+    f = oracle.init(rho, J, zeta, p)
+    # perturb off equilibrium so that the relaxation matters
+    return f * (1 + 1e-3 * rng.uniform(-1, 1, f.shape)) + 0 * x
+
+
+# ---------------------------------------------------------------- matrices --
+
+@pytest.mark.parametrize("lam,cp,rho0", [(1.0, 1.0, 1.0), (1.7, 2.3, 1.3)])
+def test_moment_matrix_is_the_printed_one(lam, cp, rho0):
+    g = printed()["M_D1Q3Q3"]
+    p = oracle.Params(lam=lam, cp=cp, rho0=rho0)
+    M, Minv = oracle.moment_matrix(p)
+    np.testing.assert_allclose(M, sym_matrix(g["rows"], lam, cp, rho0),
+                               rtol=4e-16, atol=0)
+    np.testing.assert_allclose(M @ Minv, np.eye(6), atol=1e-14)
+    # the moments the oracle computes are M f (eqs. moments-conserves and
+    # moments-non-conserves of section 6)
+    rng = np.random.default_rng(0)
+    f = rng.uniform(0, 1, (6, 5))
+    np.testing.assert_allclose(oracle.moments(f, p),
+                               sym_matrix(g["rows"], lam, cp, rho0) @ f,
+                               rtol=1e-15, atol=1e-15)
+
+
+@pytest.mark.parametrize("lam,cp,rho0", [(1.0, 1.0, 1.0), (1.7, 2.3, 1.3)])
+def test_momentum_velocity_tensor_matches_printed_lambda(lam, cp, rho0):
+    # eq. Lambda-general: Lambda = lambda M diag(v) M^-1 must be the matrix
+    # printed as eq. Lambda-d1q3q3 (independent of cp and rho0).
+    p = oracle.Params(lam=lam, cp=cp, rho0=rho0)
+    M, Minv = oracle.moment_matrix(p)
+    v = np.diag([0.0, 1.0, -1.0, 0.0, 1.0, -1.0])
+    Lam = lam * M @ v @ Minv
+    want = sym_matrix(printed()["Lambda_D1Q3Q3"]["rows"], lam, cp, rho0)
+    np.testing.assert_allclose(Lam, want, atol=1e-13)
+    # its (rho, J, e) block is the D1Q3 tensor of eq. tenseur-Lambda
+    idx = [0, 1, 3]
+    want3 = sym_matrix(printed()["Lambda_D1Q3"]["rows"], lam, cp, rho0)
+    np.testing.assert_allclose(Lam[np.ix_(idx, idx)], want3, atol=1e-13)
+
+
+# ---------------------------------------------------- equilibria and EOS --
+
+def _states(rng, p, n=64):
+    rho = p.rho0 * rng.uniform(0.5, 2.0, n)
+    u = p.lam * rng.uniform(-0.3, 0.3, n)
+    s = p.s0 + p.cp * rng.uniform(-0.5, 0.5, n)
+    return rho, rho * u, rho * s, u, s
+
+
+def test_first_order_flux_is_euler_flux():
+    # Section 8: the first-order equivalent momentum flux (2/3) lambda^2 rho
+    # + e_eq / 3 (eq. edp1-d1q3q3) must be rho u^2 + p, the Euler flux of
+    # eq. NS-rho-J-zeta.  A wrong factor in e_eq breaks it.
+    rng = np.random.default_rng(1)
+    p = odd_params()
+    rho, J, zeta, u, s = _states(rng, p)
+    e_eq, psi_eq, eps_eq, pr, T = oracle.equilibria(rho, J, zeta, p)
+    np.testing.assert_allclose(2 / 3 * p.lam**2 * rho + e_eq / 3,
+                               rho * u**2 + pr, rtol=1e-13)
+    # first-order entropy flux psi_eq = zeta u (eq. psi-equilibre)
+    np.testing.assert_allclose(psi_eq, zeta * u, rtol=1e-14)
+
+
+def test_equation_of_state():
+    # Eq. gaz-parfait and section 5: p = rho r T, c^2 = gamma p / rho
+    # = (gamma - 1) cp T; at (rho0, s0) the pressure is p0 with
+    # c0^2 = gamma p0 / rho0 (section 7); isentropic scaling p ~ rho^gamma and
+    # p ~ exp(gamma s / cp) at fixed rho.
+    rng = np.random.default_rng(2)
+    p = odd_params()
+    rho, J, zeta, u, s = _states(rng, p)
+    _, _, _, pr, T = oracle.equilibria(rho, J, zeta, p)
+    np.testing.assert_allclose(p.gamma * pr / rho,
+                               (p.gamma - 1) * p.cp * T, rtol=1e-13)
+    one = np.array([p.rho0])
+    _, _, _, p_ref, _ = oracle.equilibria(one, 0 * one, one * p.s0, p)
+    np.testing.assert_allclose(p_ref, p.rho0 * p.c0**2 / p.gamma, rtol=1e-14)
+    r2 = 1.7 * rho
+    _, _, _, p2, _ = oracle.equilibria(r2, 0 * r2, r2 * s, p)
+    np.testing.assert_allclose(p2 / pr, 1.7**p.gamma, rtol=1e-13)
+    _, _, _, p3, _ = oracle.equilibria(rho, J, zeta + rho * 0.2 * p.cp, p)
+    np.testing.assert_allclose(p3 / pr, np.exp(p.gamma * 0.2), rtol=1e-13)
+
+
+def test_entropy_equilibrium_two_printed_forms_agree():
+    # Eq. eq-energie-entropie-d1q3q3 (log(T/T0) form, used by the oracle)
+    # must equal the polytropic form printed right after it, which contains no
+    # T0; this pins the reading T0 = T(rho0, s0).
+    rng = np.random.default_rng(3)
+    p = odd_params()
+    rho, J, zeta, u, s = _states(rng, p)
+    _, _, eps_eq, pr, T = oracle.equilibria(rho, J, zeta, p)
+    lam2 = p.lam**2
+    poly = (2 * lam2 * (rho * (s - p.s0)
+                        + (1 - 1 / p.gamma) * p.cp * rho * np.log(rho / p.rho0))
+            + (3 * (rho * u**2 + pr) - 2 * lam2 * rho) * s)
+    np.testing.assert_allclose(eps_eq, poly, rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------------------ rates ------
+
+def test_rates_printed_values():
+    g = printed()["linear_wave_run"]
+    # section 7: s_e = 1.9 goes with nu = 6.579e-4 at dx = 1/40 (nu printed
+    # to 4 digits), through eqs. nu-d1q3q3 and henon-d1q3q3
+    s_e = oracle.rate_from_viscosity(g["nu"], 1.0, g["dx"])
+    assert abs(s_e - g["s_e"]) < 1e-4
+    s_psi, s_eps = oracle.coupled_rates(1.9, 1.4, 1.0)
+    assert s_eps == printed()["s_eps"]["value"]
+    # eq. lien-sigma-sigma was chosen so that alpha (section 7, formula
+    # before it) lies in (-2, 1); with the coupling alpha = 3 u0^2 / lambda^2.
+    sig_e, sig_psi = 1 / 1.9 - 0.5, 1 / s_psi - 0.5
+    for u0 in (0.0, 0.15, 0.5):
+        alpha = 3 * (1.4 / 1.0 * sig_e / sig_psi - 2 / 3 + u0**2)
+        assert abs(alpha - 3 * u0**2) < 1e-12
+        lo, hi = (printed()["alpha_stability_interval"][k] for k in ("lo", "hi"))
+        assert lo < alpha < hi
+
+
+# ----------------------------------------------- invariants of the step --
+
+def test_rest_state_is_fixed_point():
+    # At rho = 1, u = 0, s = 0 (lambda = rho0 = cp = 1, c0 = 1/2, gamma = 1.4):
+    # p0 = c0^2 / gamma, e_eq = 3 p0 - 2 = -41/28, and M^-1 gives
+    # f = (1/3 - e/3, 1/3 + e/6, 1/3 + e/6) = (23/28, 5/56, 5/56), g = 0.
+    p = oracle.Params()
+    n = 16
+    f = oracle.init(np.ones(n), np.zeros(n), np.zeros(n), p)
+    want = np.array([23 / 28, 5 / 56, 5 / 56, 0, 0, 0])
+    np.testing.assert_allclose(f, np.repeat(want[:, None], n, 1), atol=1e-16)
+    np.testing.assert_allclose(oracle.step(f, p), f, atol=1e-15, rtol=0)
+
+
+def test_uniform_moving_state_is_fixed_point():
+    p = odd_params()
+    n = 9
+    rho = np.full(n, 1.2 * p.rho0)
+    f = oracle.init(rho, rho * 0.13 * p.lam, rho * 0.4 * p.cp, p)
+    np.testing.assert_allclose(oracle.step(f, p), f, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("source_on", [0, 1])
+def test_conservation_and_entropy_production(source_on):
+    rng = np.random.default_rng(4)
+    p = odd_params(source_on=source_on)
+    f = random_state(rng, 97, p)
+    m0 = oracle.moments(f, p)
+    dz = oracle.source(f, p)
+    g = oracle.step(f, p)
+    m1 = oracle.moments(g, p)
+    # mass and momentum: collision keeps them, streaming permutes
+    np.testing.assert_allclose(m1[0].sum(), m0[0].sum(), rtol=1e-14)
+    np.testing.assert_allclose(m1[1].sum(), m0[1].sum(),
+                               atol=1e-14 * np.abs(m0[1]).sum())
+    # entropy: the total grows by exactly the summed source, which is >= 0
+    assert np.all(dz >= 0)
+    want = m0[2].sum() + (dz.sum() if source_on else 0.0)
+    np.testing.assert_allclose(m1[2].sum(), want,
+                               atol=1e-13 * np.abs(m0[2]).sum() + 1e-15)
+    if source_on:
+        assert dz.sum() > 0
+
+
+def test_mirror_symmetry_and_translation():
+    rng = np.random.default_rng(5)
+    p = odd_params()
+    n = 40
+    f = random_state(rng, n, p)
+
+    def mirror(x):
+        y = x[[0, 2, 1, 3, 5, 4]][:, ::-1]
+        return np.ascontiguousarray(y)
+
+    g1 = oracle.step(mirror(f), p)
+    g2 = mirror(oracle.step(f, p))
+    np.testing.assert_allclose(g1, g2, rtol=1e-13, atol=1e-15)
+    sh = np.roll(f, 7, axis=1)
+    np.testing.assert_array_equal(oracle.step(sh, p),
+                                  np.roll(oracle.step(f, p), 7, axis=1))
+
+
+def test_unit_rates_relax_to_equilibrium():
+    # With s_e = s_psi = s_eps = 1 and no source, the collision replaces the
+    # non-conserved moments by their equilibria, so one step equals the
+    # streaming of the equilibrium populations of the current moments.
+    rng = np.random.default_rng(6)
+    p = odd_params(s_e=1.0, s_psi=1.0, s_eps=1.0, source_on=0)
+    f = random_state(rng, 33, p)
+    m = oracle.moments(f, p)
+    feq = oracle.init(m[0], m[1], m[2], p)
+    want = feq.copy()
+    want[[1, 4]] = np.roll(feq[[1, 4]], 1, axis=1)
+    want[[2, 5]] = np.roll(feq[[2, 5]], -1, axis=1)
+    np.testing.assert_allclose(oracle.step(f, p), want, rtol=1e-14, atol=1e-15)
+
+
+def test_scheme_depends_on_dx_only_through_the_rates():
+    rng = np.random.default_rng(7)
+    p1 = odd_params(dx=1.0)
+    p2 = odd_params(dx=1 / 40)
+    f = random_state(rng, 50, p1)
+    np.testing.assert_allclose(oracle.run(f, 5, p1), oracle.run(f, 5, p2),
+                               rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------ entropy source ---
+
+def test_source_matches_continuous_entropy_production():
+    # dt * sum_j S(x_j) with S = rho nu / T (u')^2 + kappa / T^2 (T')^2
+    # (eq. NS-rho-J-zeta) from analytic derivatives of smooth fields must
+    # match the oracle's discrete source to O(dx^2).
+    n = 512
+    L = 1.0
+    dx = L / n
+    lam = 1.0
+    p = oracle.Params(lam=lam, dx=dx, s_e=1.6, prandtl=0.71, gamma=1.4,
+                      c0=0.5, cp=1.0)
+    x = np.arange(n) * dx
+    k = 2 * np.pi / L
+    rho = 1 + 0.1 * np.sin(k * x)
+    u = 0.05 * np.cos(k * x + 0.3)
+    s = 0.2 * np.sin(k * x + 1.1)
+    f = oracle.init(rho, rho * u, rho * s, p)
+    dz = oracle.source(f, p)
+    # analytic u', T'
+    up = -0.05 * k * np.sin(k * x + 0.3)
+    rhop = 0.1 * k * np.cos(k * x)
+    sp_ = 0.2 * k * np.cos(k * x + 1.1)
+    r = p.cp * (p.gamma - 1) / p.gamma
+    T0 = p.c0**2 / (p.gamma * r)
+    T = T0 * (rho / p.rho0) ** (p.gamma - 1) * np.exp(p.gamma * s / p.cp)
+    Tp = T * ((p.gamma - 1) * rhop / rho + p.gamma * sp_ / p.cp)
+    nu = (1 / p.s_e - 0.5) * lam * dx
+    kappa = rho * nu * p.cp / p.prandtl
+    S = rho * nu / T * up**2 + kappa / T**2 * Tp**2
+    dt = dx / lam
+    np.testing.assert_allclose(dz.sum(), dt * S.sum(), rtol=2e-4)
+    np.testing.assert_allclose(dz, dt * S, rtol=2e-3, atol=2e-4 * dz.max())
+
+
+# ---------------------------------------- linear waves (Taylor expansion) --
+
+def mode_response(p, n, m):
+    f = oracle.init(np.full(n, p.rho0), np.zeros(n), np.full(n, p.rho0 * p.s0), p)
+    j = np.arange(n)
+    ph = np.exp(2j * np.pi * m * j / n)
+    G = np.zeros((6, 6), complex)
+    for c in range(6):
+        dfr = np.zeros((6, n))
+        dfi = np.zeros((6, n))
+        dfr[c] = ph.real
+        dfi[c] = ph.imag
+        _, outr = oracle.step_tlm(f, dfr, np.zeros(3), p)
+        _, outi = oracle.step_tlm(f, dfi, np.zeros(3), p)
+        out = outr + 1j * outi  # response to the complex mode (linearity)
+        G[:, c] = (out * ph.conj()).sum(axis=1) / n
+    return G
+
+
+@pytest.mark.parametrize("pkw", [
+    dict(),
+    dict(gamma=1.3, prandtl=0.71, c0=0.4, s_e=1.5),
+    dict(lam=2.0, c0=0.7, s_e=1.7, prandtl=2.0),
+])
+def test_sound_speed_and_damping_match_equivalent_equations(pkw):
+    """Eigenvalues of the exact linearised step vs. the second-order
+    equivalent equations (eq. edp-ordre-2 with the defects of conservation of
+    section 8; the exact theta_e at u0 = 0 is the one printed in section 7):
+
+      momentum: J_t + c0^2 rho_x + (c0^2/cp) zeta_x = nu (1 - c0^2/lambda^2) J_xx
+      entropy:  zeta_t = (nu/Pr) [(gamma-1) cp rho_xx + (gamma + 3c0^2/(2 lambda^2)) zeta_xx]
+
+    giving sound speed c0, acoustic damping (k^2/2) nu [(1 - c0^2/lambda^2)
+    + (gamma-1)/Pr] and entropy-mode damping k^2 (nu/Pr)(1 + 3 c0^2/(2 lambda^2)),
+    with nu = sigma_e lambda dx, per step (dt = dx/lambda, dx = 1).
+    Agreement is O(k^2) relative."""
+    p = oracle.Params(**pkw)
+    n, m = 256, 1
+    G = mode_response(p, n, m)
+    z = np.linalg.eigvals(G)
+    kap = 2 * np.pi * m / n
+    lam, c0 = p.lam, p.c0
+    sig = 1 / p.s_e - 0.5
+    gac = kap**2 / 2 * sig * ((1 - c0**2 / lam**2) + (p.gamma - 1) / p.prandtl)
+    gs = kap**2 * sig / p.prandtl * (1 + 1.5 * c0**2 / lam**2)
+    speed = c0 / lam  # nodes per step
+    # acoustic pair: |arg z| ~ speed * k
+    ac = [w for w in z if np.abs(w) > 0.99 and abs(np.angle(w)) > 0.5 * speed * kap]
+    assert len(ac) == 2
+    for w in ac:
+        np.testing.assert_allclose(abs(np.angle(w)) / kap, speed, rtol=1e-4)
+        np.testing.assert_allclose(-np.log(abs(w)), gac, rtol=1e-4)
+    ent = [w for w in z if abs(np.angle(w)) < 1e-9 and abs(w) > 0.99]
+    assert len(ent) == 1
+    np.testing.assert_allclose(-np.log(abs(ent[0])), gs, rtol=3e-4)
+    # the three kinetic modes relax at |1 - s| (no advection at k -> 0)
+    kin = sorted(abs(w) for w in z if abs(w) < 0.99)
+    rates = sorted(abs(1 - s) for s in p.rates())
+    np.testing.assert_allclose(kin, rates, atol=5e-3)
+
+
+def test_small_wave_nonlinear_run_follows_linear_modes():
+    """A density wave of amplitude 1e-3 (uniform temperature) run through the
+    nonlinear oracle for 1000 steps keeps to the linear mode evolution to
+    O(amplitude)."""
+    p = oracle.Params()
+    n, a = 256, 1e-3
+    j = np.arange(n)
+    rho = 1 + a * np.sin(2 * np.pi * j / n + 0.7)
+    zeta = rho * (-(p.gamma - 1) / p.gamma * p.cp * np.log(rho))
+    f0 = oracle.init(rho, np.zeros(n), zeta, p)
+    base = oracle.init(np.ones(n), np.zeros(n), np.zeros(n), p)
+    G = mode_response(p, n, 1)
+    z, V = np.linalg.eig(G)
+    ph = np.exp(-2j * np.pi * j / n)
+    F0 = ((f0 - base) * ph).sum(axis=1) / n
+    c = np.linalg.solve(V, F0)
+    f = f0
+    for steps in (100, 400, 500):
+        f = oracle.run(f, steps, p)
+        t = {100: 100, 400: 500, 500: 1000}[steps]
+        Fn = ((f - base) * ph).sum(axis=1) / n
+        pred = V @ (z**t * c)
+        err = np.abs(Fn - pred).max() / np.abs(F0).max()
+        assert err < 5 * a, (t, err)
+
+
+# ------------------------------------------------------ derivatives -----
+
+def test_tangent_linear_step_matches_central_differences():
+    rng = np.random.default_rng(8)
+    p = odd_params()
+    n = 23
+    f = random_state(rng, n, p, amp=0.2, u=0.1, ds=0.3)
+    df = rng.standard_normal((6, n)) * 1e-2
+    dr = rng.standard_normal(3) * 0.1
+    _, tl = oracle.step_tlm(f, df, dr, p)
+    h = 1e-6
+    s = np.array(p.rates())
+
+    def stepped(sign):
+        q = odd_params(s_e=s[0] + sign * h * dr[0], s_psi=s[1] + sign * h * dr[1],
+                       s_eps=s[2] + sign * h * dr[2])
+        return oracle.step(f + sign * h * df, q)
+
+    fd = (stepped(1) - stepped(-1)) / (2 * h)
+    np.testing.assert_allclose(tl, fd, rtol=1e-6, atol=1e-8 * np.abs(fd).max())
+
+
+def test_adjoint_step_is_transpose_of_tangent():
+    rng = np.random.default_rng(9)
+    p = odd_params()
+    n = 19
+    f = random_state(rng, n, p, amp=0.2, u=0.1, ds=0.3)
+    dx_ = rng.standard_normal((6, n))
+    dr = rng.standard_normal(3)
+    ybar = rng.standard_normal((6, n))
+    _, tl = oracle.step_tlm(f, dx_, dr, p)
+    xb, rb = oracle.step_adjoint(f, ybar, p)
+    lhs = (ybar * tl).sum()
+    rhs = (xb * dx_).sum() + rb @ dr
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + np.abs(ybar * tl).sum())
+
+
+def test_init_tangent_and_adjoint():
+    rng = np.random.default_rng(10)
+    p = odd_params()
+    n = 11
+    rho = p.rho0 * rng.uniform(0.7, 1.3, n)
+    J = rho * rng.uniform(-0.2, 0.2, n)
+    zeta = rho * rng.uniform(-0.3, 0.3, n)
+    d = [rng.standard_normal(n) for _ in range(3)]
+    _, df = oracle.init_tlm(rho, J, zeta, *d, p)
+    h = 1e-6
+    fd = (oracle.init(rho + h * d[0], J + h * d[1], zeta + h * d[2], p)
+          - oracle.init(rho - h * d[0], J - h * d[1], zeta - h * d[2], p)) / (2 * h)
+    np.testing.assert_allclose(df, fd, rtol=1e-6, atol=1e-9)
+    fb = rng.standard_normal((6, n))
+    rb, Jb, zb = oracle.init_adjoint(rho, J, zeta, fb, p)
+    lhs = (fb * df).sum()
+    rhs = rb @ d[0] + Jb @ d[1] + zb @ d[2]
+    assert abs(lhs - rhs) < 1e-12 * np.abs(fb * df).sum()
+
+
+@pytest.mark.parametrize("ckpt", [0, 4])
+def test_gradient_matches_directional_and_finite_differences(ckpt):
+    rng = np.random.default_rng(11)
+    p = oracle.Params(s_e=1.7)
+    n, steps = 32, 17
+    j = np.arange(n)
+    rho = 1 + 0.05 * np.sin(2 * np.pi * j / n) + 0.01 * rng.standard_normal(n)
+    J = 0.02 * np.cos(2 * np.pi * j / n)
+    zeta = 0.01 * rng.standard_normal(n)
+    tgt = 1 + 0.03 * np.sin(2 * np.pi * j / n + 1)
+    L, rb, Jb, zb, sb = oracle.gradient(rho, J, zeta, steps, tgt, p, ckpt=ckpt)
+    d = [rng.standard_normal(n) for _ in range(3)]
+    dr = rng.standard_normal(3)
+    L2, dL = oracle.directional(rho, J, zeta, *d, dr, steps, tgt, p)
+    assert L2 == pytest.approx(L, rel=1e-14)
+    adj = rb @ d[0] + Jb @ d[1] + zb @ d[2] + sb @ dr
+    assert adj == pytest.approx(dL, rel=1e-11)
+    # central differences of the forward loss
+    h = 1e-5
+    s = np.array(p.rates())
+
+    def loss_at(sign):
+        q = oracle.Params(s_e=s[0] + sign * h * dr[0], s_psi=s[1] + sign * h * dr[1],
+                          s_eps=s[2] + sign * h * dr[2])
+        f = oracle.init(rho + sign * h * d[0], J + sign * h * d[1],
+                        zeta + sign * h * d[2], q)
+        f = oracle.run(f, steps, q)
+        return oracle.loss(f, tgt, q)[0]
+
+    fd = (loss_at(1) - loss_at(-1)) / (2 * h)
+    assert fd == pytest.approx(dL, rel=1e-6)
