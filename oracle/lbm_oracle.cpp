@@ -9,10 +9,11 @@
 //
 // Readings of the paper taken here (each is listed with its reason in the
 // design notes of the repository):
-//   * T0 = T(rho0, s0), the temperature of the reference state of the EOS
-//     (eq. gaz-parfait); it is the only choice under which the two printed
-//     forms of eps_eq (eq. eq-energie-entropie-d1q3q3 and the polytropic form
-//     that follows it) agree.  p0 = rho0 c0^2 / gamma.
+//   * eps_eq is taken in the polytropic form printed right after eq.
+//     eq-energie-entropie-d1q3q3 (the paper's own specialisation to the EOS
+//     of eq. gaz-parfait).  The general form with log(T/T0) agrees with it
+//     exactly when T0 = T(rho0, s0), the temperature of the reference state;
+//     p0 = rho0 c0^2 / gamma (section 7).
 //   * Step (vii): the source dt*S_j, with S the right-hand side of the third
 //     equation of eq. NS-rho-J-zeta, is added to zeta after the relaxation;
 //     the equilibria use the pre-source zeta.  d_x u and d_x T are centred
@@ -238,10 +239,16 @@ void equilibria(const Ctx& c, const S& rho, const S& J, const S& zeta,
   const orc_params& p = c.p;
   const double l2 = p.lambda * p.lambda;
   if (p.eq_kind == 0) {
-    // Eq. energie-equilibre, eq. psi-equilibre, eq. eq-energie-entropie-d1q3q3.
+    // Eq. energie-equilibre, eq. psi-equilibre, and eq.
+    // eq-energie-entropie-d1q3q3 in the form the paper gives it for the
+    // polytropic gas of eq. gaz-parfait (the formula printed right after it):
+    // eps_eq = 2 lambda^2 [rho (s - s0) + (1 - 1/gamma) cp rho log(rho/rho0)]
+    //          + [3 (rho u^2 + p) - 2 lambda^2 rho] s.
     e_eq = 3.0 * (rho * u * u + pr) - 2.0 * l2 * rho;
     psi_eq = zeta * u;
-    eps_eq = (2.0 * rho * p.cp * l2 / p.gamma) * log(T / c.T0) +
+    eps_eq = 2.0 * l2 *
+                 (rho * (s - p.s0) +
+                  (1.0 - 1.0 / p.gamma) * p.cp * rho * log(rho / p.rho0)) +
              (3.0 * (rho * u * u + pr) - 2.0 * l2 * rho) * s;
   } else {
     // Eq. equilibres-NS-linearise, as printed (units lambda = cp = 1).

@@ -1,0 +1,210 @@
+// C ABI entry points for one periodic lattice (declared in include/lbm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+
+struct lbm_handle {
+  int64_t n;
+  lbm_params p;
+  lbm::Consts c;
+  hipStream_t stream;
+  lbm_tuning tune;
+};
+
+namespace lbm {
+
+int check_tuning(const lbm_tuning* t) {
+  if (!t) return set_err(LBM_EINVAL, "tuning is NULL");
+  if (t->kernel < LBM_KERNEL_AUTO || t->kernel > LBM_KERNEL_BLOCKED)
+    return set_err(LBM_EINVAL, "unknown kernel %d", t->kernel);
+  if (t->kernel == LBM_KERNEL_PLAIN) return LBM_OK;
+  const int P = t->nodes_per_lane, K = t->steps_per_launch;
+  if (P != 2 && P != 4 && P != 8)
+    return set_err(LBM_EINVAL, "nodes_per_lane must be 2, 4 or 8 (got %d)", P);
+  if (K < 1 || 4 * K >= 64 * P)
+    return set_err(LBM_EINVAL, "steps_per_launch must satisfy 1 <= K < 16P");
+  const int w = t->waves_per_group;
+  if (w != 1 && w != 2 && w != 4)
+    return set_err(LBM_EINVAL, "waves_per_group must be 1, 2 or 4");
+  return LBM_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_coupled_rates(double s_e, double gamma, double prandtl, double* s_psi,
+                      double* s_eps, double* ds_psi_ds_e) {
+  if (!s_psi || !s_eps)
+    return set_err(LBM_EINVAL, "s_psi and s_eps must not be NULL");
+  if (!(std::isfinite(s_e) && s_e > 0.0 && s_e < 2.0))
+    return set_err(LBM_EINVAL, "s_e must lie in (0, 2)");
+  if (!(std::isfinite(gamma) && gamma > 1.0) ||
+      !(std::isfinite(prandtl) && prandtl > 0.0))
+    return set_err(LBM_EINVAL, "gamma must be > 1 and prandtl > 0");
+  const double k = 1.5 * gamma / prandtl;
+  const double sigma_e = 1.0 / s_e - 0.5;
+  const double sp = 1.0 / (k * sigma_e + 0.5);
+  *s_psi = sp;
+  *s_eps = 1.5;
+  if (ds_psi_ds_e) *ds_psi_ds_e = k * (sp / s_e) * (sp / s_e);
+  return LBM_OK;
+}
+
+int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream) {
+  if (!h) return set_err(LBM_EINVAL, "handle pointer is NULL");
+  *h = nullptr;
+  if (n < 3) return set_err(LBM_EINVAL, "lattice needs n >= 3 nodes (got %lld)",
+                            (long long)n);
+  if (n > (int64_t(1) << 40)) return set_err(LBM_EINVAL, "n too large");
+  Consts c;
+  int rc = make_consts(p, &c);
+  if (rc) return rc;
+  lbm_handle* x = new lbm_handle;
+  x->n = n;
+  x->p = *p;
+  x->c = c;
+  x->stream = (hipStream_t)stream;
+  x->tune = lbm_tuning{LBM_KERNEL_BLOCKED, 8, 8, 4};
+  *h = x;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle* h) { delete h; }
+
+int lbm_set_stream(lbm_handle* h, void* stream) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  h->stream = (hipStream_t)stream;
+  return LBM_OK;
+}
+
+int lbm_set_params(lbm_handle* h, const lbm_params* p) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  Consts c;
+  int rc = make_consts(p, &c);
+  if (rc) return rc;
+  h->p = *p;
+  h->c = c;
+  return LBM_OK;
+}
+
+size_t lbm_workspace_bytes(const lbm_handle* h, int kind) {
+  if (!h) return 0;
+  if (kind == LBM_WS_STEP)
+    return (size_t)(6 * h->n + (int64_t)diag_ws_doubles()) * sizeof(double);
+  return 0;
+}
+
+int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  int rc = check_tuning(t);
+  if (rc) return rc;
+  h->tune = *t;
+  if (h->tune.kernel == LBM_KERNEL_AUTO) h->tune.kernel = LBM_KERNEL_BLOCKED;
+  return LBM_OK;
+}
+
+int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t) {
+  if (!h || !t) return set_err(LBM_EINVAL, "NULL argument");
+  *t = h->tune;
+  return LBM_OK;
+}
+
+int lbm_set_equilibrium(lbm_handle* h, const double* rho, const double* J,
+                        const double* zeta, double* f) {
+  if (!h || !rho || !J || !zeta || !f)
+    return set_err(LBM_EINVAL, "NULL argument");
+  return launch_equilibrium(h->c, rho, J, zeta, f, h->n, h->stream);
+}
+
+int lbm_moments(lbm_handle* h, const double* f, double* m) {
+  if (!h || !f || !m) return set_err(LBM_EINVAL, "NULL argument");
+  if (overlaps(f, 48 * h->n, m, 48 * h->n))
+    return set_err(LBM_EINVAL, "f and m overlap");
+  return launch_moments(h->c, f, m, h->n, h->stream);
+}
+
+int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
+             int64_t nsteps) {
+  if (!h || !f || !ws) return set_err(LBM_EINVAL, "NULL argument");
+  if (nsteps < 0) return set_err(LBM_EINVAL, "nsteps must be >= 0");
+  const int64_t n = h->n;
+  const size_t sbytes = (size_t)(6 * n) * sizeof(double);
+  if (ws_bytes < lbm_workspace_bytes(h, LBM_WS_STEP))
+    return set_err(LBM_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes,
+                   lbm_workspace_bytes(h, LBM_WS_STEP));
+  if (((uintptr_t)f | (uintptr_t)ws) & 7)
+    return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
+  if (overlaps(f, sbytes, ws, ws_bytes))
+    return set_err(LBM_EINVAL, "f and ws overlap");
+  if (nsteps == 0) return LBM_OK;
+  double* a = f;
+  double* b = (double*)ws;
+  int rc = LBM_OK;
+  int64_t launches = 0;
+  if (h->tune.kernel == LBM_KERNEL_PLAIN) {
+    for (int64_t t = 0; t < nsteps && !rc; ++t) {
+      rc = launch_step_plain(h->c, a, b, n, h->stream);
+      std::swap(a, b);
+      ++launches;
+    }
+  } else {
+    const int K = h->tune.steps_per_launch;
+    int64_t L = (nsteps + K - 1) / K;
+    // An even number of launches leaves the result in f without a copy.
+    if ((L & 1) && nsteps > L) ++L;
+    const int64_t base = nsteps / L, extra = nsteps % L;
+    for (int64_t i = 0; i < L && !rc; ++i) {
+      const int k = (int)(base + (i < extra ? 1 : 0));
+      rc = launch_step_tile(h->c, a, b, n, h->tune.nodes_per_lane, k,
+                            h->tune.waves_per_group, h->stream);
+      std::swap(a, b);
+      ++launches;
+    }
+  }
+  if (rc) return rc;
+  if (launches & 1)
+    rc = hip_check(hipMemcpyAsync(f, ws, sbytes, hipMemcpyDeviceToDevice,
+                                  h->stream),
+                   "hipMemcpyAsync");
+  return rc;
+}
+
+int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,
+                    double out[8]) {
+  if (!h || !f || !ws || !out) return set_err(LBM_EINVAL, "NULL argument");
+  if (ws_bytes < lbm_workspace_bytes(h, LBM_WS_STEP))
+    return set_err(LBM_EWORKSPACE, "workspace too small");
+  double* scratch = (double*)ws + 6 * h->n;
+  int rc = launch_diagnostics(h->c, f, h->n, scratch, h->stream);
+  if (rc) return rc;
+  rc = hip_check(hipMemcpyAsync(out, scratch, 8 * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream),
+                 "hipMemcpyAsync");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  if (out[6] > 0 || out[7] > 0)
+    return set_err(LBM_ENONFINITE,
+                   "state holds %g non-finite values and %g nodes with rho<=0 "
+                   "or T<=0",
+                   out[6], out[7]);
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+"""Thin ctypes binding of ``liblbm.so`` (C ABI declared in include/lbm.h).
+
+Argument marshalling only: every step of the scheme runs in the library's HIP
+kernels.  Device memory comes from torch tensors (float64, CUDA/HIP device);
+calls enqueue on torch's current stream.  If the built library is missing the
+import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_EWORKSPACE, LBM_ENONFINITE, LBM_ENOTSUP = \
+    0, -1, -2, -3, -4, -5
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
+WS_STEP = 0
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in (
+        "lam", "rho0", "cp", "gamma", "prandtl", "c0", "s0",
+        "s_e", "s_psi", "s_eps", "u0_lin", "s0_lin")] + [
+        ("source_on", ctypes.c_int32), ("eq_kind", ctypes.c_int32)]
+
+
+class CTuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("nodes_per_lane", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+_d = ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "lbm_last_error": ([], ctypes.c_char_p),
+            "lbm_coupled_rates": ([_d, _d, _d, _dp, _dp, _dp], ctypes.c_int),
+            "lbm_init": ([ctypes.POINTER(_vp), _i64, ctypes.POINTER(CParams), _vp],
+                         ctypes.c_int),
+            "lbm_destroy": ([_vp], None),
+            "lbm_set_stream": ([_vp, _vp], ctypes.c_int),
+            "lbm_set_params": ([_vp, ctypes.POINTER(CParams)], ctypes.c_int),
+            "lbm_workspace_bytes": ([_vp, ctypes.c_int], _sz),
+            "lbm_set_tuning": ([_vp, ctypes.POINTER(CTuning)], ctypes.c_int),
+            "lbm_get_tuning": ([_vp, ctypes.POINTER(CTuning)], ctypes.c_int),
+            "lbm_set_equilibrium": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "lbm_step": ([_vp, _vp, _vp, _sz, _i64], ctypes.c_int),
+            "lbm_moments": ([_vp, _vp, _vp], ctypes.c_int),
+            "lbm_diagnostics": ([_vp, _vp, _vp, _sz, _dp], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != LBM_OK:
+        msg = lib().lbm_last_error().decode()
+        raise LBMError(rc, msg)
+
+
+def coupled_rates(s_e: float, gamma: float = 1.4, prandtl: float = 1.0):
+    """(s_psi, s_eps, d s_psi / d s_e) of the section-7 coupling."""
+    a, b, c = _d(), _d(), _d()
+    check(lib().lbm_coupled_rates(s_e, gamma, prandtl, ctypes.byref(a),
+                                  ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+@dataclass
+class Params:
+    lam: float = 1.0
+    rho0: float = 1.0
+    cp: float = 1.0
+    gamma: float = 1.4
+    prandtl: float = 1.0
+    c0: float = 0.5
+    s0: float = 0.0
+    s_e: float = 1.9
+    s_psi: float | None = None  # None: coupled to s_e
+    s_eps: float = 1.5
+    u0_lin: float = 0.0
+    s0_lin: float = 0.0
+    source_on: int = 1
+    eq_kind: int = 0
+
+    def c(self) -> CParams:
+        s_psi = self.s_psi
+        if s_psi is None:
+            s_psi = coupled_rates(self.s_e, self.gamma, self.prandtl)[0]
+        return CParams(self.lam, self.rho0, self.cp, self.gamma, self.prandtl,
+                       self.c0, self.s0, self.s_e, s_psi, self.s_eps,
+                       self.u0_lin, self.s0_lin, int(self.source_on),
+                       int(self.eq_kind))
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_ptr(t: torch.Tensor, numel: int | None = None, name: str = "tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float64 and t.dtype != torch.uint8:
+        raise ValueError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+class Lattice:
+    """One periodic lattice of n nodes.  State tensors are float64 (6, n)."""
+
+    def __init__(self, n: int, params: Params | None = None, stream=None):
+        self.n = int(n)
+        self.params = params or Params()
+        self._h = _vp()
+        cp = self.params.c()
+        check(lib().lbm_init(ctypes.byref(self._h), self.n, ctypes.byref(cp),
+                             _vp(_stream_ptr(stream))))
+        self.ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lbm_destroy(h)
+            self._h = None
+
+    def set_stream(self, stream=None):
+        check(lib().lbm_set_stream(self._h, _vp(_stream_ptr(stream))))
+
+    def set_params(self, params: Params):
+        cp = params.c()
+        check(lib().lbm_set_params(self._h, ctypes.byref(cp)))
+        self.params = params
+
+    def workspace_bytes(self, kind: int = WS_STEP) -> int:
+        return int(lib().lbm_workspace_bytes(self._h, kind))
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        nb = self.workspace_bytes(WS_STEP)
+        if self.ws is None or self.ws.numel() * 8 < nb:
+            self.ws = torch.empty((nb + 7) // 8, dtype=torch.float64,
+                                  device=device)
+        return self.ws
+
+    def set_tuning(self, kernel=KERNEL_BLOCKED, nodes_per_lane=8,
+                   steps_per_launch=8, waves_per_group=4):
+        t = CTuning(kernel, nodes_per_lane, steps_per_launch, waves_per_group)
+        check(lib().lbm_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = CTuning()
+        check(lib().lbm_get_tuning(self._h, ctypes.byref(t)))
+        return dict(kernel=t.kernel, nodes_per_lane=t.nodes_per_lane,
+                    steps_per_launch=t.steps_per_launch,
+                    waves_per_group=t.waves_per_group)
+
+    def equilibrium(self, rho, J, zeta, out: torch.Tensor | None = None):
+        n = self.n
+        f = out if out is not None else torch.empty(
+            (6, n), dtype=torch.float64, device=rho.device)
+        check(lib().lbm_set_equilibrium(
+            self._h, _dev_ptr(rho, n, "rho"), _dev_ptr(J, n, "J"),
+            _dev_ptr(zeta, n, "zeta"), _dev_ptr(f, 6 * n, "f")))
+        return f
+
+    def step(self, f: torch.Tensor, nsteps: int, ws: torch.Tensor | None = None):
+        """Advances f in place by nsteps time steps."""
+        ws = ws if ws is not None else self.workspace(f.device)
+        check(lib().lbm_step(self._h, _dev_ptr(f, 6 * self.n, "f"),
+                             _dev_ptr(ws, None, "ws"), ws.numel() * 8,
+                             int(nsteps)))
+        return f
+
+    def moments(self, f: torch.Tensor) -> torch.Tensor:
+        m = torch.empty_like(f)
+        check(lib().lbm_moments(self._h, _dev_ptr(f, 6 * self.n, "f"),
+                                _dev_ptr(m, 6 * self.n, "m")))
+        return m
+
+    def diagnostics(self, f: torch.Tensor, ws: torch.Tensor | None = None,
+                    raise_nonfinite: bool = False):
+        ws = ws if ws is not None else self.workspace(f.device)
+        out = (ctypes.c_double * 8)()
+        rc = lib().lbm_diagnostics(self._h, _dev_ptr(f, 6 * self.n, "f"),
+                                   _dev_ptr(ws, None, "ws"), ws.numel() * 8,
+                                   out)
+        if rc != LBM_OK and (rc != LBM_ENONFINITE or raise_nonfinite):
+            check(rc)
+        return list(out)

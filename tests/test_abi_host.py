@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/lbm.h declares, and rejects bad arguments before any
+HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1802_02369_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_coupled_rates_host():
+    s_psi, s_eps, d = lbm.coupled_rates(1.9, 1.4, 1.0)
+    # sigma_psi = 1.5 gamma / Pr sigma_e (section 7)
+    assert 1 / s_psi - 0.5 == pytest.approx(1.5 * 1.4 * (1 / 1.9 - 0.5), rel=1e-14)
+    assert s_eps == 1.5
+    h = 1e-6
+    fd = (lbm.coupled_rates(1.9 + h)[0] - lbm.coupled_rates(1.9 - h)[0]) / (2 * h)
+    assert d == pytest.approx(fd, rel=1e-8)
+    with pytest.raises(lbm.LBMError):
+        lbm.coupled_rates(2.0)
+    with pytest.raises(lbm.LBMError):
+        lbm.coupled_rates(1.0, gamma=1.0)
+
+
+def _init(n, **kw):
+    p = lbm.Params(**kw).c() if "s_psi" in kw else lbm.Params(s_psi=1.0, **kw).c()
+    h = ctypes.c_void_p()
+    rc = lbm.lib().lbm_init(ctypes.byref(h), n, ctypes.byref(p), None)
+    return rc, h
+
+
+@pytest.mark.parametrize("n,kw", [
+    (2, {}),
+    (0, {}),
+    (16, dict(s_e=2.0)),
+    (16, dict(s_e=0.0)),
+    (16, dict(s_eps=-1.0)),
+    (16, dict(gamma=1.0)),
+    (16, dict(cp=0.0)),
+    (16, dict(c0=-0.5)),
+    (16, dict(prandtl=float("nan"))),
+    (16, dict(source_on=2)),
+    (16, dict(eq_kind=3)),
+    (16, dict(eq_kind=1, lam=2.0)),
+])
+def test_init_rejects_bad_arguments(n, kw):
+    rc, h = _init(n, **kw)
+    assert rc == lbm.LBM_EINVAL
+    assert not h.value
+    assert lbm.lib().lbm_last_error()
+
+
+def test_init_and_workspace_and_tuning_host():
+    rc, h = _init(1000)
+    assert rc == lbm.LBM_OK and h.value
+    L = lbm.lib()
+    nb = L.lbm_workspace_bytes(h, lbm.WS_STEP)
+    assert nb >= 6 * 1000 * 8
+    assert L.lbm_workspace_bytes(None, lbm.WS_STEP) == 0
+    for bad in [(lbm.KERNEL_BLOCKED, 3, 4, 4), (lbm.KERNEL_BLOCKED, 4, 64, 4),
+                (lbm.KERNEL_BLOCKED, 4, 0, 4), (lbm.KERNEL_BLOCKED, 8, 4, 3),
+                (7, 8, 4, 4)]:
+        t = lbm.CTuning(*bad)
+        assert L.lbm_set_tuning(h, ctypes.byref(t)) == lbm.LBM_EINVAL
+    t = lbm.CTuning(lbm.KERNEL_BLOCKED, 4, 15, 2)
+    assert L.lbm_set_tuning(h, ctypes.byref(t)) == lbm.LBM_OK
+    t2 = lbm.CTuning()
+    assert L.lbm_get_tuning(h, ctypes.byref(t2)) == lbm.LBM_OK
+    assert (t2.nodes_per_lane, t2.steps_per_launch, t2.waves_per_group) == (4, 15, 2)
+    # step argument validation fails before touching the device
+    assert L.lbm_step(h, None, None, 0, 1) == lbm.LBM_EINVAL
+    assert L.lbm_step(h, ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20), 8,
+                      1) == lbm.LBM_EWORKSPACE
+    assert L.lbm_step(h, ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 8),
+                      nb, 1) == lbm.LBM_EINVAL  # overlap
+    assert L.lbm_step(h, ctypes.c_void_p(4096), ctypes.c_void_p(1 << 30), nb,
+                      -1) == lbm.LBM_EINVAL
+    # nsteps = 0 is a no-op that never touches memory
+    assert L.lbm_step(h, ctypes.c_void_p(4096), ctypes.c_void_p(1 << 30), nb,
+                      0) == lbm.LBM_OK
+    L.lbm_destroy(h)

@@ -130,18 +130,21 @@ def test_equation_of_state():
 
 
 def test_entropy_equilibrium_two_printed_forms_agree():
-    # Eq. eq-energie-entropie-d1q3q3 (log(T/T0) form, used by the oracle)
-    # must equal the polytropic form printed right after it, which contains no
-    # T0; this pins the reading T0 = T(rho0, s0).
+    # The oracle evaluates the polytropic form printed after eq.
+    # eq-energie-entropie-d1q3q3; it must equal the general form
+    # (2 rho cp lambda^2 / gamma) log(T/T0) + [3(rho u^2 + p) - 2 lambda^2 rho] s
+    # with T from the oracle's EOS and T0 = T(rho0, s0).  This pins the
+    # reading of T0 and the transcription of both printed forms.
     rng = np.random.default_rng(3)
     p = odd_params()
     rho, J, zeta, u, s = _states(rng, p)
     _, _, eps_eq, pr, T = oracle.equilibria(rho, J, zeta, p)
+    one = np.array([p.rho0])
+    T0 = oracle.equilibria(one, 0 * one, one * p.s0, p)[4][0]
     lam2 = p.lam**2
-    poly = (2 * lam2 * (rho * (s - p.s0)
-                        + (1 - 1 / p.gamma) * p.cp * rho * np.log(rho / p.rho0))
-            + (3 * (rho * u**2 + pr) - 2 * lam2 * rho) * s)
-    np.testing.assert_allclose(eps_eq, poly, rtol=1e-12, atol=1e-14)
+    general = ((2 * rho * p.cp * lam2 / p.gamma) * np.log(T / T0)
+               + (3 * (rho * u**2 + pr) - 2 * lam2 * rho) * s)
+    np.testing.assert_allclose(eps_eq, general, rtol=1e-12, atol=1e-14)
 
 
 # ------------------------------------------------------------ rates ------
