@@ -85,7 +85,7 @@ typedef struct lbm_tuning {
   int32_t kernel;          /* LBM_KERNEL_* */
   int32_t nodes_per_lane;  /* P: contiguous nodes per lane (blocked kernel) */
   int32_t steps_per_launch;/* K: time steps per launch (blocked kernel) */
-  int32_t waves_per_group; /* wavefronts per workgroup (blocked kernel) */
+  int32_t waves_per_group; /* wavefronts per tile (blocked kernel) */
 } lbm_tuning;
 
 /* ----------------------------------------------------------------- misc */
@@ -114,15 +114,19 @@ int lbm_set_params(lbm_handle* h, const lbm_params* p);
 
 /* Workspace kinds. */
 enum {
-  LBM_WS_STEP = 0 /* lbm_step and lbm_diagnostics: a second state plus
-                     reduction scratch */
+  LBM_WS_STEP = 0, /* lbm_step, lbm_diagnostics (and the batch forms): a
+                      second state plus tables and reduction scratch */
+  LBM_WS_TUNE = 1  /* lbm_autotune / lbm_batch_autotune: LBM_WS_STEP for
+                      every candidate shape plus a copy of the state */
 };
 /* Bytes of caller workspace that calls of the given kind need (0 on a bad
  * handle). */
 size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
 
-/* Kernel selection.  lbm_set_tuning validates the shape (P in {2,4,8},
- * 1 <= K, 4K < 64P, waves_per_group in {1,2,4,8}). */
+/* Kernel selection.  lbm_set_tuning validates the shape (P in {2,4},
+ * 1 <= K, 4K < 64 P waves_per_group, waves_per_group in {1,2,4,8}).
+ * The blocked kernel gives each workgroup of waves_per_group wavefronts a
+ * tile of 64 P waves_per_group nodes held in registers for K steps. */
 int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);
 int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
 
@@ -151,6 +155,62 @@ int lbm_moments(lbm_handle* h, const double* f, double* m);
  * (out is still filled). */
 int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,
                     double out[8]);
+
+/* Autotuner (synchronising).  Times the blocked kernel on the caller's state
+ * f for probe_steps time steps with each candidate shape (P in {2,4}, waves
+ * per tile in {2,4,8}, K in {8,12,16,24,32}, halo recomputation at most a
+ * quarter of the tile) plus the one-step kernel, keeps the fastest, and
+ * restores f.  ws: lbm_workspace_bytes(h, LBM_WS_TUNE) bytes.  cache_path
+ * (may be NULL) names a JSON file mapping "<gfx arch>/<kind>/<size class>"
+ * to the chosen shape; a hit skips the timing, a miss adds the entry.  The
+ * chosen shape becomes the handle's tuning and is returned in *out (may be
+ * NULL). */
+int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
+                 int64_t probe_steps, const char* cache_path, lbm_tuning* out);
+
+/* ------------------------------------------------- batches of lattices */
+
+/* A batch of n_inst independent periodic lattices of different lengths and
+ * constants, advanced together (the paper runs one lattice at a time; the
+ * batch is a throughput form of the same algorithm, lattice by lattice).
+ * offsets (host, n_inst+1 int64, offsets[0] = 0, lengths offsets[i+1] -
+ * offsets[i] >= 3) place lattice i at [offsets[i], offsets[i+1]) of every
+ * array of a batch state of 6 * n_total doubles, n_total = offsets[n_inst]
+ * (array k of the state is doubles [k*n_total, (k+1)*n_total)).  params
+ * (host, n_inst records) are validated as in lbm_init.  Both are copied. */
+int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
+                   const lbm_params* params, void* stream);
+void lbm_batch_destroy(lbm_batch* b);
+int lbm_batch_set_stream(lbm_batch* b, void* stream);
+int lbm_batch_set_tuning(lbm_batch* b, const lbm_tuning* t);
+int lbm_batch_get_tuning(const lbm_batch* b, lbm_tuning* t);
+/* Total nodes n_total of the batch (0 on a bad handle). */
+int64_t lbm_batch_total_nodes(const lbm_batch* b);
+size_t lbm_batch_workspace_bytes(const lbm_batch* b, int kind);
+/* Uploads the per-lattice constants, offsets and the tile table of the
+ * current tuning into ws (synchronising).  Required before the calls below
+ * whenever ws, the tuning or the constants change. */
+int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes);
+/* Equilibrium initialisation of every lattice from device arrays rho, J,
+ * zeta of n_total doubles (batch layout). */
+int lbm_batch_set_equilibrium(lbm_batch* b, const double* rho, const double* J,
+                              const double* zeta, double* f, void* ws,
+                              size_t ws_bytes);
+/* Advances every lattice of the batch state f (device, 6*n_total doubles) by
+ * nsteps time steps, in place.  With use_graph = 1 the launches are captured
+ * once into a hipGraph (re-captured when f, ws, nsteps or the tuning change)
+ * and replayed with one hipGraphLaunch on the stream. */
+int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
+                  int64_t nsteps, int use_graph);
+/* Per-lattice diagnostics (synchronising): out (host, 8*n_inst doubles) gets
+ * the eight values of lbm_diagnostics for each lattice.  Returns
+ * LBM_ENONFINITE if any lattice has a non-finite or non-physical node. */
+int lbm_batch_diagnostics(lbm_batch* b, const double* f, void* ws,
+                          size_t ws_bytes, double* out);
+/* Autotuner of the batch (as lbm_autotune; calls lbm_batch_prepare). */
+int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
+                       int64_t probe_steps, const char* cache_path,
+                       lbm_tuning* out);
 
 #ifdef __cplusplus
 }

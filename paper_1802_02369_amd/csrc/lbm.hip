@@ -205,85 +205,260 @@ __global__ __launch_bounds__(kPlainBlock) void k_step_plain(
   fout[5 * n + jl] = gm;
 }
 
-// K time steps of one register-resident tile per wavefront (see the file
-// header).  Tile t stores nodes [t*OUT, t*OUT + OUT) with OUT = 64P - 4K and
-// loads nodes [t*OUT - 2K, t*OUT + OUT + 2K) (periodic).
+// K time steps of one register-resident tile per workgroup (see the file
+// header).  The workgroup has WG wavefronts; wavefront w owns the 64P nodes
+// [w*64P, (w+1)*64P) of the tile, lane l of it the P consecutive nodes
+// starting at w*64P + l*P.  Tile t stores nodes [t*OUT, t*OUT + OUT) with
+// OUT = 64*P*WG - 4K and loads nodes [t*OUT - 2K, t*OUT + OUT + 2K)
+// (periodic).
+//
+// Global memory is touched only at the start and the end of the launch, and
+// always coalesced: node i of a wavefront's segment travels through that
+// wavefront's LDS buffer between the coalesced order (lane l handles
+// i = k*64 + l) and the register order (lane l owns i = l*P + k).  The LDS
+// index i + i/P pads one double per lane row so that both orders are free of
+// bank conflicts.  Staging is private to a wavefront (wave_barrier only).
 template <int P>
-__global__ __launch_bounds__(256) void k_step_tile(Consts c,
-                                                   const double* __restrict__ fin,
-                                                   double* __restrict__ fout,
-                                                   int64_t n, int K,
-                                                   int64_t ntiles) {
-  const int lane = threadIdx.x & 63;
-  const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (tile >= ntiles) return;  // uniform over the wavefront
-  constexpr int W = 64 * P;
-  const int H = 2 * K;
-  const int OUT = W - 2 * H;
-  const int64_t start = tile * OUT - H;
-  double f[6][P];
-  const bool inside = start >= 0 && start + W <= n;
-  if (inside) {
-    const double* src = fin + start + lane * P;
+__device__ __forceinline__ int lds_idx(int i) {
+  return i + i / P;
+}
+
+__device__ __forceinline__ int64_t wrap_near(int64_t x, int64_t n, bool small) {
+  if (small) return lbm::wrap_mod(x, n);
+  return x < 0 ? x + n : (x >= n ? x - n : x);
+}
+
+// Arrays of a lattice of length L are at fin + q*S (S >= L, the array
+// stride of the state the lattice lives in).
+template <int P>
+__device__ __forceinline__ void tile_load(const double* __restrict__ fin,
+                                          int64_t S, int64_t n, int64_t start,
+                                          bool inside, bool small, int lane,
+                                          double* lds, double (&f)[6][P]) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-#pragma unroll
-      for (int k = 0; k < P; ++k) f[q][k] = src[q * n + k];
-  } else {
+  for (int q = 0; q < 6; ++q) {
+    const double* src = fin + (int64_t)q * S;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-      const int64_t g = lbm::wrap_mod(start + lane * P + k, n);
-#pragma unroll
-      for (int q = 0; q < 6; ++q) f[q][k] = fin[q * n + g];
+      const int i = k * 64 + lane;
+      const int64_t g = inside ? start + i : wrap_near(start + i, n, small);
+      lds[lds_idx<P>(i)] = src[g];
     }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < P; ++k) f[q][k] = lds[lds_idx<P>(lane * P + k)];
+    __builtin_amdgcn_wave_barrier();
   }
-  for (int step = 0; step < K; ++step) {
-    double u[P], T[P], rw[P], w[P];
+}
+
+// Stores the nodes of this wavefront's segment whose tile index lies in
+// [lo, hi) and whose global index is below n.
+template <int P>
+__device__ __forceinline__ void tile_store(double* __restrict__ fout,
+                                           int64_t S, int64_t n, int64_t start,
+                                           int lo, int hi, int lane, double* lds,
+                                           const double (&f)[6][P]) {
 #pragma unroll
-    for (int k = 0; k < P; ++k)
-      lbm::collide_local(c, f[0][k], f[1][k], f[2][k], f[3][k], f[4][k],
-                         f[5][k], u[k], T[k], rw[k], w[k]);
-    const double uL = lbm::from_left(u[P - 1]), TL = lbm::from_left(T[P - 1]);
-    const double uR = lbm::from_right(u[0]), TR = lbm::from_right(T[0]);
+  for (int q = 0; q < 6; ++q) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) lds[lds_idx<P>(lane * P + k)] = f[q][k];
+    __builtin_amdgcn_wave_barrier();
+    double* dst = fout + (int64_t)q * S;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-      const double ul = k == 0 ? uL : u[k - 1];
-      const double tl = k == 0 ? TL : T[k - 1];
-      const double ur = k == P - 1 ? uR : u[k + 1];
-      const double tr = k == P - 1 ? TR : T[k + 1];
-      const double add = lbm::source_g(c, rw[k], w[k], ul, ur, tl, tr);
-      f[3][k] += add;
-      f[4][k] += add;
-      f[5][k] += add;
+      const int i = k * 64 + lane;
+      const int64_t g = start + i;
+      if (i >= lo && i < hi && g < n) dst[g] = lds[lds_idx<P>(i)];
     }
-    // (viii) streaming: + populations move one node right, - one node left.
-    const double fpL = lbm::from_left(f[1][P - 1]);
-    const double gpL = lbm::from_left(f[4][P - 1]);
-    const double fmR = lbm::from_right(f[2][0]);
-    const double gmR = lbm::from_right(f[5][0]);
-#pragma unroll
-    for (int k = P - 1; k > 0; --k) {
-      f[1][k] = f[1][k - 1];
-      f[4][k] = f[4][k - 1];
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Values exchanged between neighbouring wavefronts of a workgroup each step:
+// [0..1] u, T of the last node of the wavefront, [2..3] u, T of its first
+// node, [4..5] f+*, g+* of its last node, [6..7] f-*, g-* of its first node.
+struct Boundary {
+  double v[8];
+};
+
+// One time step of a register tile.  The source of node k needs u, T of k-1
+// and k+1, so the collisions run in the order P-1, 0, 1, ..., P-2 and each
+// source is applied as soon as its right neighbour exists; only a window of
+// three nodes' (u, T) stays live besides the populations.  With WG > 1 the
+// first and last lanes of a wavefront take their outside neighbours from the
+// adjacent wavefronts through LDS (two workgroup barriers per step; each
+// slot of `bnd` is written and read between the same pair of barriers).
+template <int P, int WG>
+__device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
+                                          Boundary* bnd, int lane, int wave) {
+  double uA, TA, rwA, wA;  // node P-1, collided first
+  lbm::collide_local(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
+                     f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
+  double um, Tm, rwm, wm;  // node k (the one whose source is next)
+  __builtin_amdgcn_sched_barrier(0);
+  lbm::collide_local(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0], f[5][0],
+                     um, Tm, rwm, wm);
+  if (WG > 1) {
+    if (lane == 63) {
+      bnd[wave].v[0] = uA;
+      bnd[wave].v[1] = TA;
     }
-    f[1][0] = fpL;
-    f[4][0] = gpL;
-#pragma unroll
-    for (int k = 0; k < P - 1; ++k) {
-      f[2][k] = f[2][k + 1];
-      f[5][k] = f[5][k + 1];
+    if (lane == 0) {
+      bnd[wave].v[2] = um;
+      bnd[wave].v[3] = Tm;
     }
-    f[2][P - 1] = fmR;
-    f[5][P - 1] = gmR;
+    __syncthreads();
+  }
+  double ul = lbm::from_left(uA), Tl = lbm::from_left(TA);
+  double uR = lbm::from_right(um), TR = lbm::from_right(Tm);
+  if (WG > 1) {
+    if (lane == 0 && wave > 0) {
+      ul = bnd[wave - 1].v[0];
+      Tl = bnd[wave - 1].v[1];
+    }
+    if (lane == 63 && wave < WG - 1) {
+      uR = bnd[wave + 1].v[2];
+      TR = bnd[wave + 1].v[3];
+    }
   }
 #pragma unroll
   for (int k = 0; k < P; ++k) {
-    const int i = lane * P + k;
-    const int64_t g = start + i;
-    if (i >= H && i < W - H && g < n) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) fout[q * n + g] = f[q][k];
+    double ur, Tr, rwr = 0.0, wr = 0.0;
+    // Keep the scheduler from interleaving the collisions of different
+    // nodes: that would hold several nodes' temporaries live at once.
+    __builtin_amdgcn_sched_barrier(0);
+    if (k + 1 < P - 1) {
+      lbm::collide_local(c, f[0][k + 1], f[1][k + 1], f[2][k + 1], f[3][k + 1],
+                         f[4][k + 1], f[5][k + 1], ur, Tr, rwr, wr);
+    } else if (k + 1 == P - 1) {
+      ur = uA;
+      Tr = TA;
+      rwr = rwA;
+      wr = wA;
+    } else {
+      ur = uR;
+      Tr = TR;
     }
+    const double add = lbm::source_g(c, rwm, wm, ul, ur, Tl, Tr);
+    f[3][k] += add;
+    f[4][k] += add;
+    f[5][k] += add;
+    ul = um;
+    Tl = Tm;
+    um = ur;
+    Tm = Tr;
+    rwm = rwr;
+    wm = wr;
+  }
+  // (viii) streaming: + populations move one node right, - one node left.
+  double fpL = lbm::from_left(f[1][P - 1]);
+  double gpL = lbm::from_left(f[4][P - 1]);
+  double fmR = lbm::from_right(f[2][0]);
+  double gmR = lbm::from_right(f[5][0]);
+  if (WG > 1) {
+    if (lane == 63) {
+      bnd[wave].v[4] = f[1][P - 1];
+      bnd[wave].v[5] = f[4][P - 1];
+    }
+    if (lane == 0) {
+      bnd[wave].v[6] = f[2][0];
+      bnd[wave].v[7] = f[5][0];
+    }
+    __syncthreads();
+    if (lane == 0 && wave > 0) {
+      fpL = bnd[wave - 1].v[4];
+      gpL = bnd[wave - 1].v[5];
+    }
+    if (lane == 63 && wave < WG - 1) {
+      fmR = bnd[wave + 1].v[6];
+      gmR = bnd[wave + 1].v[7];
+    }
+  }
+#pragma unroll
+  for (int k = P - 1; k > 0; --k) {
+    f[1][k] = f[1][k - 1];
+    f[4][k] = f[4][k - 1];
+  }
+  f[1][0] = fpL;
+  f[4][0] = gpL;
+#pragma unroll
+  for (int k = 0; k < P - 1; ++k) {
+    f[2][k] = f[2][k + 1];
+    f[5][k] = f[5][k + 1];
+  }
+  f[2][P - 1] = fmR;
+  f[5][P - 1] = gmR;
+}
+
+// Tile t of a lattice of n nodes (array stride S) starting at lattice index
+// `start` = t*OUT - H, OUT = W - 2H: load, K <= H/2 steps, store of the
+// interior [H, W - H) (one step has radius 2, so K steps need H >= 2K).
+template <int P, int WG>
+__device__ __forceinline__ void tile_run(const Consts& c,
+                                         const double* __restrict__ fin,
+                                         double* __restrict__ fout, int64_t S,
+                                         int64_t n, int64_t start, int H,
+                                         int K) {
+  constexpr int WW = 64 * P;
+  constexpr int W = WG * WW;
+  __shared__ double stage[WG * (WW + 64)];
+  __shared__ Boundary bnd[WG];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double* lds = stage + wave * (WW + 64);
+  const int64_t wstart = start + wave * WW;
+  const bool inside = start >= 0 && start + W <= n;
+  const bool small = n < W;
+  double f[6][P];
+  tile_load<P>(fin, S, n, wstart, inside, small, lane, lds, f);
+  for (int step = 0; step < K; ++step) tile_step<P, WG>(c, f, bnd, lane, wave);
+  // tile indices [H, W - H) are valid; in this wavefront's numbering:
+  tile_store<P>(fout, S, n, wstart, H - wave * WW, W - H - wave * WW, lane,
+                lds, f);
+}
+
+template <int P, int WG>
+__global__ __launch_bounds__(64 * WG) void k_step_tile(
+    Consts c, const double* __restrict__ fin, double* __restrict__ fout,
+    int64_t n, int K, int64_t ntiles) {
+  const int64_t tile = blockIdx.x;
+  if (tile >= ntiles) return;  // uniform over the workgroup
+  const int OUT = 64 * P * WG - 4 * K;
+  tile_run<P, WG>(c, fin, fout, n, n, tile * OUT - 2 * K, 2 * K, K);
+}
+
+// Batched form: workgroup b advances tile tiles[b].t of lattice tiles[b].inst,
+// which occupies [offs[inst], offs[inst+1]) of every array of a state of
+// array stride S, with that lattice's own constants.  The tiling (halo H,
+// OUT = W - 2H) is fixed by the tile table; a launch runs K <= H/2 steps.
+template <int P, int WG>
+__global__ __launch_bounds__(64 * WG) void k_batch_tile(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const lbm::TileRef* __restrict__ tiles, const double* __restrict__ fin,
+    double* __restrict__ fout, int64_t S, int H, int K, int64_t ntiles) {
+  const int64_t b = blockIdx.x;
+  if (b >= ntiles) return;  // uniform over the workgroup
+  const lbm::TileRef tr = tiles[b];
+  const int64_t off = offs[tr.inst];
+  const int64_t n = offs[tr.inst + 1] - off;
+  const Consts c = cs[tr.inst];
+  const int OUT = 64 * P * WG - 2 * H;
+  tile_run<P, WG>(c, fin + off, fout + off, S, n, (int64_t)tr.t * OUT - H, H,
+                  K);
+}
+
+// One workgroup per lattice of a batch: equilibrium populations.
+__global__ __launch_bounds__(256) void k_batch_equilibrium(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const double* __restrict__ rho, const double* __restrict__ J,
+    const double* __restrict__ zeta, double* __restrict__ f, int64_t S) {
+  const int inst = blockIdx.x;
+  const Consts c = cs[inst];
+  for (int64_t j = offs[inst] + threadIdx.x; j < offs[inst + 1]; j += 256) {
+    double v[6];
+    lbm::equilibrium(c, rho[j], J[j], zeta[j], v);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) f[k * S + j] = v[k];
   }
 }
 
@@ -349,6 +524,41 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_final(
   if (threadIdx.x < 8) out[threadIdx.x] = s[0][threadIdx.x];
 }
 
+// Per-lattice diagnostics of a batch, one workgroup per lattice, fixed tree
+// order; out[8*inst + k] as in lbm_diagnostics.
+__global__ __launch_bounds__(kDiagBlock) void k_batch_diag(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const double* __restrict__ f, int64_t S, double* __restrict__ out) {
+  __shared__ double s[kDiagBlock][8];
+  const int inst = blockIdx.x;
+  const Consts c = cs[inst];
+  double a[8] = {0, 0, 0, 0, INFINITY, INFINITY, 0, 0};
+  for (int64_t j = offs[inst] + threadIdx.x; j < offs[inst + 1];
+       j += kDiagBlock) {
+    const double f0 = f[j], fp = f[S + j], fm = f[2 * S + j];
+    const double g0 = f[3 * S + j], gp = f[4 * S + j], gm = f[5 * S + j];
+    const double v[6] = {f0, fp, fm, g0, gp, gm};
+    double nf = 0;
+    for (int k = 0; k < 6; ++k) nf += isfinite(v[k]) ? 0.0 : 1.0;
+    const double rho = lbm::density(c, f0, fp, fm);
+    const double J = c.mJ * (fp - fm);
+    const double zeta = c.mz * (g0 + (gp + gm));
+    double u, s_, X, T;
+    lbm::thermo(c, rho, J, zeta, u, s_, X, T);
+    const double p = rho * c.r * T;
+    const double b[8] = {rho, J, zeta, p / c.gm1 + 0.5 * J * u,
+                         rho, T, nf, (rho > 0.0 && T > 0.0) ? 0.0 : 1.0};
+    diag_combine(a, b);
+  }
+  for (int k = 0; k < 8; ++k) s[threadIdx.x][k] = a[k];
+  __syncthreads();
+  for (int w = kDiagBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) diag_combine(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) out[8 * inst + threadIdx.x] = s[0][threadIdx.x];
+}
+
 }  // namespace
 
 // ----------------------------------------------------- launch helpers ---
@@ -372,28 +582,38 @@ int launch_step_plain(const Consts& c, const double* fin, double* fout,
   return hip_check(hipGetLastError(), "k_step_plain");
 }
 
-int64_t tile_out(int P, int K) { return 64 * P - 4 * K; }
+int64_t tile_out(int P, int K, int wg) { return 64 * P * wg - 4 * K; }
+
+template <int P, int WG>
+static void launch_tile_t(const Consts& c, const double* fin, double* fout,
+                          int64_t n, int K, hipStream_t s) {
+  const int64_t ntiles = cdiv(n, tile_out(P, K, WG));
+  hipLaunchKernelGGL((k_step_tile<P, WG>), dim3((unsigned)ntiles),
+                     dim3(64 * WG), 0, s, c, fin, fout, n, K, ntiles);
+}
+
+template <int P>
+static int launch_tile_p(const Consts& c, const double* fin, double* fout,
+                         int64_t n, int K, int wg, hipStream_t s) {
+  switch (wg) {
+    case 1: launch_tile_t<P, 1>(c, fin, fout, n, K, s); break;
+    case 2: launch_tile_t<P, 2>(c, fin, fout, n, K, s); break;
+    case 4: launch_tile_t<P, 4>(c, fin, fout, n, K, s); break;
+    case 8: launch_tile_t<P, 8>(c, fin, fout, n, K, s); break;
+    default: return set_err(LBM_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+  }
+  return LBM_OK;
+}
 
 int launch_step_tile(const Consts& c, const double* fin, double* fout,
                      int64_t n, int P, int K, int wpg, hipStream_t s) {
-  const int64_t ntiles = cdiv(n, tile_out(P, K));
-  const dim3 grid((unsigned)cdiv(ntiles, wpg)), block(64 * wpg);
+  int rc;
   switch (P) {
-    case 2:
-      hipLaunchKernelGGL(k_step_tile<2>, grid, block, 0, s, c, fin, fout, n, K,
-                         ntiles);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_step_tile<4>, grid, block, 0, s, c, fin, fout, n, K,
-                         ntiles);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_step_tile<8>, grid, block, 0, s, c, fin, fout, n, K,
-                         ntiles);
-      break;
-    default:
-      return set_err(LBM_EINVAL, "nodes_per_lane must be 2, 4 or 8");
+    case 2: rc = launch_tile_p<2>(c, fin, fout, n, K, wpg, s); break;
+    case 4: rc = launch_tile_p<4>(c, fin, fout, n, K, wpg, s); break;
+    default: return set_err(LBM_EINVAL, "nodes_per_lane must be 2 or 4");
   }
+  if (rc) return rc;
   return hip_check(hipGetLastError(), "k_step_tile");
 }
 
@@ -416,6 +636,56 @@ int launch_moments(const Consts& c, const double* f, double* m, int64_t n,
   hipLaunchKernelGGL(k_moments, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s,
                      c, f, m, n);
   return hip_check(hipGetLastError(), "k_moments");
+}
+
+template <int P, int WG>
+static void launch_batch_t(const Consts* cs, const int64_t* offs,
+                           const TileRef* tiles, int64_t ntiles,
+                           const double* fin, double* fout, int64_t S, int H,
+                           int K, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_tile<P, WG>), dim3((unsigned)ntiles),
+                     dim3(64 * WG), 0, s, cs, offs, tiles, fin, fout, S, H, K,
+                     ntiles);
+}
+
+int launch_batch_tile(const Consts* cs, const int64_t* offs,
+                      const TileRef* tiles, int64_t ntiles, const double* fin,
+                      double* fout, int64_t S, int P, int H, int K, int wg,
+                      hipStream_t s) {
+  if (ntiles <= 0) return LBM_OK;
+  if (K < 1 || 2 * K > H || 2 * H >= 64 * P * wg)
+    return set_err(LBM_EINVAL, "bad batched tile geometry H=%d K=%d", H, K);
+#define LBM_BATCH_CASE(PP, WW)                                              \
+  if (P == PP && wg == WW) {                                                \
+    launch_batch_t<PP, WW>(cs, offs, tiles, ntiles, fin, fout, S, H, K, s); \
+    return hip_check(hipGetLastError(), "k_batch_tile");                    \
+  }
+  LBM_BATCH_CASE(2, 1)
+  LBM_BATCH_CASE(2, 2)
+  LBM_BATCH_CASE(2, 4)
+  LBM_BATCH_CASE(2, 8)
+  LBM_BATCH_CASE(4, 1)
+  LBM_BATCH_CASE(4, 2)
+  LBM_BATCH_CASE(4, 4)
+  LBM_BATCH_CASE(4, 8)
+#undef LBM_BATCH_CASE
+  return set_err(LBM_EINVAL, "unsupported tile shape P=%d waves=%d", P, wg);
+}
+
+int launch_batch_equilibrium(const Consts* cs, const int64_t* offs,
+                             int64_t n_inst, const double* rho, const double* J,
+                             const double* zeta, double* f, int64_t S,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_equilibrium, dim3((unsigned)n_inst), dim3(256), 0,
+                     s, cs, offs, rho, J, zeta, f, S);
+  return hip_check(hipGetLastError(), "k_batch_equilibrium");
+}
+
+int launch_batch_diag(const Consts* cs, const int64_t* offs, int64_t n_inst,
+                      const double* f, int64_t S, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_diag, dim3((unsigned)n_inst), dim3(kDiagBlock), 0,
+                     s, cs, offs, f, S, out);
+  return hip_check(hipGetLastError(), "k_batch_diag");
 }
 
 }  // namespace lbm

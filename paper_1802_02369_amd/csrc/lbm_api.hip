@@ -5,17 +5,10 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "lbm_internal.hpp"
-
-struct lbm_handle {
-  int64_t n;
-  lbm_params p;
-  lbm::Consts c;
-  hipStream_t stream;
-  lbm_tuning tune;
-};
 
 namespace lbm {
 
@@ -25,17 +18,38 @@ int check_tuning(const lbm_tuning* t) {
     return set_err(LBM_EINVAL, "unknown kernel %d", t->kernel);
   if (t->kernel == LBM_KERNEL_PLAIN) return LBM_OK;
   const int P = t->nodes_per_lane, K = t->steps_per_launch;
-  if (P != 2 && P != 4 && P != 8)
-    return set_err(LBM_EINVAL, "nodes_per_lane must be 2, 4 or 8 (got %d)", P);
-  if (K < 1 || 4 * K >= 64 * P)
-    return set_err(LBM_EINVAL, "steps_per_launch must satisfy 1 <= K < 16P");
+  if (P != 2 && P != 4)
+    return set_err(LBM_EINVAL, "nodes_per_lane must be 2 or 4 (got %d)", P);
   const int w = t->waves_per_group;
-  if (w != 1 && w != 2 && w != 4)
-    return set_err(LBM_EINVAL, "waves_per_group must be 1, 2 or 4");
+  if (w != 1 && w != 2 && w != 4 && w != 8)
+    return set_err(LBM_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+  if (K < 1 || 4 * K >= 64 * P * w)
+    return set_err(LBM_EINVAL,
+                   "steps_per_launch must satisfy 1 <= K < 16 P waves_per_group");
   return LBM_OK;
 }
 
-static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+std::vector<int> split_steps(int64_t nsteps, int K) {
+  std::vector<int> out;
+  if (nsteps <= 0 || K < 1) return out;
+  int64_t L = (nsteps + K - 1) / K;
+  if ((L & 1) && nsteps > L) ++L;
+  const int64_t base = nsteps / L, extra = nsteps % L;
+  for (int64_t i = 0; i < L; ++i) out.push_back((int)(base + (i < extra ? 1 : 0)));
+  return out;
+}
+
+std::vector<lbm_tuning> tuning_candidates() {
+  std::vector<lbm_tuning> v;
+  const int Ps[] = {2, 4}, Ws[] = {2, 4, 8}, Ks[] = {8, 12, 16, 24, 32};
+  for (int P : Ps)
+    for (int W : Ws)
+      for (int K : Ks)
+        if (16 * K <= 64 * P * W) v.push_back(lbm_tuning{LBM_KERNEL_BLOCKED, P, K, W});
+  return v;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
   return x < y + nb && y < x + na;
 }
@@ -80,7 +94,7 @@ int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream) {
   x->p = *p;
   x->c = c;
   x->stream = (hipStream_t)stream;
-  x->tune = lbm_tuning{LBM_KERNEL_BLOCKED, 8, 8, 4};
+  x->tune = lbm_tuning{LBM_KERNEL_BLOCKED, 2, 16, 8};
   *h = x;
   return LBM_OK;
 }
@@ -107,6 +121,8 @@ size_t lbm_workspace_bytes(const lbm_handle* h, int kind) {
   if (!h) return 0;
   if (kind == LBM_WS_STEP)
     return (size_t)(6 * h->n + (int64_t)diag_ws_doubles()) * sizeof(double);
+  if (kind == LBM_WS_TUNE)
+    return (size_t)(12 * h->n + (int64_t)diag_ws_doubles()) * sizeof(double);
   return 0;
 }
 
@@ -164,15 +180,11 @@ int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
       ++launches;
     }
   } else {
-    const int K = h->tune.steps_per_launch;
-    int64_t L = (nsteps + K - 1) / K;
     // An even number of launches leaves the result in f without a copy.
-    if ((L & 1) && nsteps > L) ++L;
-    const int64_t base = nsteps / L, extra = nsteps % L;
-    for (int64_t i = 0; i < L && !rc; ++i) {
-      const int k = (int)(base + (i < extra ? 1 : 0));
+    for (int k : split_steps(nsteps, h->tune.steps_per_launch)) {
       rc = launch_step_tile(h->c, a, b, n, h->tune.nodes_per_lane, k,
                             h->tune.waves_per_group, h->stream);
+      if (rc) break;
       std::swap(a, b);
       ++launches;
     }

@@ -40,14 +40,23 @@ struct Consts {
   int32_t pad;
 };
 
+// One tile of a batched launch: tile t of lattice inst.
+struct TileRef {
+  int32_t inst;
+  int32_t t;
+};
+
 // rho = rho0 f0 + rho0 f+ + rho0 f-, summed in the order of the first row of
 // eq. M-d1q3q3 without contraction.  X contains (gamma-1) ln rho, so a one-ulp
 // change of rho moves eps_eq by ~1e-16 in absolute terms; a fixed order keeps
 // rho reproducible across implementations.
 __device__ __forceinline__ double density(const Consts& c, double f0, double fp,
                                           double fm) {
-  return __dadd_rn(__dadd_rn(__dmul_rn(c.rho0, f0), __dmul_rn(c.rho0, fp)),
-                   __dmul_rn(c.rho0, fm));
+#pragma clang fp contract(off)
+  const double a = c.rho0 * f0;
+  const double b = c.rho0 * fp;
+  const double d = c.rho0 * fm;
+  return (a + b) + d;
 }
 
 // Thermodynamics from conserved moments: u, T and w = 1/T, plus X = ln(T/T0).

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_EWORKSPACE, LBM_ENONFINITE, LBM_ENOTSUP = \
     0, -1, -2, -3, -4, -5
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
-WS_STEP = 0
+WS_STEP, WS_TUNE = 0, 1
 
 
 class LBMError(RuntimeError):
@@ -73,6 +73,25 @@ def lib():
             "lbm_step": ([_vp, _vp, _vp, _sz, _i64], ctypes.c_int),
             "lbm_moments": ([_vp, _vp, _vp], ctypes.c_int),
             "lbm_diagnostics": ([_vp, _vp, _vp, _sz, _dp], ctypes.c_int),
+            "lbm_autotune": ([_vp, _vp, _vp, _sz, _i64, ctypes.c_char_p,
+                              ctypes.POINTER(CTuning)], ctypes.c_int),
+            "lbm_batch_init": ([ctypes.POINTER(_vp), _i64,
+                                ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(CParams), _vp], ctypes.c_int),
+            "lbm_batch_destroy": ([_vp], None),
+            "lbm_batch_set_stream": ([_vp, _vp], ctypes.c_int),
+            "lbm_batch_set_tuning": ([_vp, ctypes.POINTER(CTuning)], ctypes.c_int),
+            "lbm_batch_get_tuning": ([_vp, ctypes.POINTER(CTuning)], ctypes.c_int),
+            "lbm_batch_total_nodes": ([_vp], _i64),
+            "lbm_batch_workspace_bytes": ([_vp, ctypes.c_int], _sz),
+            "lbm_batch_prepare": ([_vp, _vp, _sz], ctypes.c_int),
+            "lbm_batch_set_equilibrium": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz],
+                                          ctypes.c_int),
+            "lbm_batch_run": ([_vp, _vp, _vp, _sz, _i64, ctypes.c_int],
+                              ctypes.c_int),
+            "lbm_batch_diagnostics": ([_vp, _vp, _vp, _sz, _dp], ctypes.c_int),
+            "lbm_batch_autotune": ([_vp, _vp, _vp, _sz, _i64, ctypes.c_char_p,
+                                    ctypes.POINTER(CTuning)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -211,6 +230,19 @@ class Lattice:
                                 _dev_ptr(m, 6 * self.n, "m")))
         return m
 
+    def autotune(self, f: torch.Tensor, probe_steps: int = 64,
+                 cache_path: str | None = None) -> dict:
+        """Times the candidate tile shapes on f (restored afterwards) and
+        keeps the fastest; see lbm_autotune."""
+        nb = self.workspace_bytes(WS_TUNE)
+        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=f.device)
+        t = CTuning()
+        check(lib().lbm_autotune(self._h, _dev_ptr(f, 6 * self.n, "f"),
+                                 _dev_ptr(ws), nb, int(probe_steps),
+                                 cache_path.encode() if cache_path else None,
+                                 ctypes.byref(t)))
+        return self.get_tuning()
+
     def diagnostics(self, f: torch.Tensor, ws: torch.Tensor | None = None,
                     raise_nonfinite: bool = False):
         ws = ws if ws is not None else self.workspace(f.device)
@@ -221,3 +253,105 @@ class Lattice:
         if rc != LBM_OK and (rc != LBM_ENONFINITE or raise_nonfinite):
             check(rc)
         return list(out)
+
+
+class Batch:
+    """Independent periodic lattices of ragged lengths advanced together.
+
+    offsets: int64 sequence of n_inst + 1 boundaries (host); params: one
+    Params per lattice.  States are float64 tensors (6, n_total)."""
+
+    def __init__(self, offsets, params, stream=None):
+        import numpy as np
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.n_inst = len(self.offsets) - 1
+        self.params = list(params)
+        if len(self.params) != self.n_inst:
+            raise ValueError("need one Params per lattice")
+        arr = (CParams * self.n_inst)(*[p.c() for p in self.params])
+        self._h = _vp()
+        check(lib().lbm_batch_init(
+            ctypes.byref(self._h), self.n_inst,
+            self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), arr,
+            _vp(_stream_ptr(stream))))
+        self.n_total = int(lib().lbm_batch_total_nodes(self._h))
+        self.ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lbm_batch_destroy(h)
+            self._h = None
+
+    def set_stream(self, stream=None):
+        check(lib().lbm_batch_set_stream(self._h, _vp(_stream_ptr(stream))))
+
+    def workspace_bytes(self, kind: int = WS_STEP) -> int:
+        return int(lib().lbm_batch_workspace_bytes(self._h, kind))
+
+    def _ensure_ws(self, device, kind=WS_STEP):
+        nb = self.workspace_bytes(kind)
+        if self.ws is None or self.ws.numel() * 8 < nb:
+            self.ws = torch.empty((nb + 7) // 8, dtype=torch.float64,
+                                  device=device)
+        return self.ws
+
+    def set_tuning(self, nodes_per_lane=2, steps_per_launch=16,
+                   waves_per_group=4, device="cuda"):
+        t = CTuning(KERNEL_BLOCKED, nodes_per_lane, steps_per_launch,
+                    waves_per_group)
+        check(lib().lbm_batch_set_tuning(self._h, ctypes.byref(t)))
+        self.prepare(device)
+
+    def get_tuning(self) -> dict:
+        t = CTuning()
+        check(lib().lbm_batch_get_tuning(self._h, ctypes.byref(t)))
+        return dict(kernel=t.kernel, nodes_per_lane=t.nodes_per_lane,
+                    steps_per_launch=t.steps_per_launch,
+                    waves_per_group=t.waves_per_group)
+
+    def prepare(self, device="cuda"):
+        ws = self._ensure_ws(device)
+        check(lib().lbm_batch_prepare(self._h, _dev_ptr(ws), ws.numel() * 8))
+        return ws
+
+    def equilibrium(self, rho, J, zeta, out=None):
+        n = self.n_total
+        ws = self.prepare(rho.device)
+        f = out if out is not None else torch.empty(
+            (6, n), dtype=torch.float64, device=rho.device)
+        check(lib().lbm_batch_set_equilibrium(
+            self._h, _dev_ptr(rho, n, "rho"), _dev_ptr(J, n, "J"),
+            _dev_ptr(zeta, n, "zeta"), _dev_ptr(f, 6 * n, "f"),
+            _dev_ptr(ws), ws.numel() * 8))
+        return f
+
+    def run(self, f: torch.Tensor, nsteps: int, use_graph: bool = True):
+        ws = self.ws
+        if ws is None:
+            ws = self.prepare(f.device)
+        check(lib().lbm_batch_run(self._h, _dev_ptr(f, 6 * self.n_total, "f"),
+                                  _dev_ptr(ws), ws.numel() * 8, int(nsteps),
+                                  1 if use_graph else 0))
+        return f
+
+    def diagnostics(self, f: torch.Tensor, raise_nonfinite: bool = False):
+        import numpy as np
+        ws = self.ws if self.ws is not None else self.prepare(f.device)
+        out = np.zeros(8 * self.n_inst)
+        rc = lib().lbm_batch_diagnostics(
+            self._h, _dev_ptr(f, 6 * self.n_total, "f"), _dev_ptr(ws),
+            ws.numel() * 8, out.ctypes.data_as(_dp))
+        if rc != LBM_OK and (rc != LBM_ENONFINITE or raise_nonfinite):
+            check(rc)
+        return out.reshape(self.n_inst, 8)
+
+    def autotune(self, f: torch.Tensor, probe_steps: int = 32,
+                 cache_path: str | None = None) -> dict:
+        ws = self._ensure_ws(f.device, WS_TUNE)
+        t = CTuning()
+        check(lib().lbm_batch_autotune(
+            self._h, _dev_ptr(f, 6 * self.n_total, "f"), _dev_ptr(ws),
+            ws.numel() * 8, int(probe_steps),
+            cache_path.encode() if cache_path else None, ctypes.byref(t)))
+        return self.get_tuning()

@@ -76,9 +76,9 @@ def test_init_and_workspace_and_tuning_host():
     nb = L.lbm_workspace_bytes(h, lbm.WS_STEP)
     assert nb >= 6 * 1000 * 8
     assert L.lbm_workspace_bytes(None, lbm.WS_STEP) == 0
-    for bad in [(lbm.KERNEL_BLOCKED, 3, 4, 4), (lbm.KERNEL_BLOCKED, 4, 64, 4),
-                (lbm.KERNEL_BLOCKED, 4, 0, 4), (lbm.KERNEL_BLOCKED, 8, 4, 3),
-                (7, 8, 4, 4)]:
+    for bad in [(lbm.KERNEL_BLOCKED, 3, 4, 4), (lbm.KERNEL_BLOCKED, 4, 256, 4),
+                (lbm.KERNEL_BLOCKED, 4, 0, 4), (lbm.KERNEL_BLOCKED, 2, 4, 3),
+                (lbm.KERNEL_BLOCKED, 8, 4, 4), (7, 2, 4, 4)]:
         t = lbm.CTuning(*bad)
         assert L.lbm_set_tuning(h, ctypes.byref(t)) == lbm.LBM_EINVAL
     t = lbm.CTuning(lbm.KERNEL_BLOCKED, 4, 15, 2)

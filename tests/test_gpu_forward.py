@@ -38,14 +38,15 @@ TUNINGS = {
     "plain": dict(kernel=1),
     "p2k1w1": dict(kernel=2, nodes_per_lane=2, steps_per_launch=1, waves_per_group=1),
     "p4k5w2": dict(kernel=2, nodes_per_lane=4, steps_per_launch=5, waves_per_group=2),
-    "p8k8w4": dict(kernel=2, nodes_per_lane=8, steps_per_launch=8, waves_per_group=4),
-    "p8k31w4": dict(kernel=2, nodes_per_lane=8, steps_per_launch=31, waves_per_group=4),
+    "p2k8w4": dict(kernel=2, nodes_per_lane=2, steps_per_launch=8, waves_per_group=4),
+    "p2k31w8": dict(kernel=2, nodes_per_lane=2, steps_per_launch=31, waves_per_group=8),
+    "p4k15w4": dict(kernel=2, nodes_per_lane=4, steps_per_launch=15, waves_per_group=4),
 }
 
 
-def make_lattice(n, po, tuning="p8k8w4"):
+def make_lattice(n, po, tuning="p2k8w4"):
     lat = lbm().Lattice(n, gpu_params(po))
-    t = dict(kernel=2, nodes_per_lane=8, steps_per_launch=8, waves_per_group=4)
+    t = dict(kernel=2, nodes_per_lane=2, steps_per_launch=8, waves_per_group=4)
     t.update(TUNINGS[tuning])
     lat.set_tuning(**t)
     return lat
@@ -82,7 +83,7 @@ def test_one_step(tuning, n):
         assert err < TOL, (pname, err)
 
 
-@pytest.mark.parametrize("tuning", ["plain", "p2k1w1", "p4k5w2", "p8k8w4", "p8k31w4"])
+@pytest.mark.parametrize("tuning", list(TUNINGS))
 @pytest.mark.parametrize("n,steps", [(37, 9), (512, 17), (3001, 40), (700, 2)])
 def test_multi_step(tuning, n, steps):
     rng = np.random.default_rng(7 * n + steps)
@@ -96,7 +97,7 @@ def test_multi_step(tuning, n, steps):
     assert max_err(f.cpu().numpy(), want) < TOL
 
 
-@pytest.mark.parametrize("tuning", ["plain", "p8k8w4"])
+@pytest.mark.parametrize("tuning", ["plain", "p2k8w4"])
 def test_small_config_every_step(tuning):
     """N = 256, amplitude 1e-3, 1000 steps.  At every step: (a) one GPU step
     from the oracle's state of that step matches the oracle's next state to
@@ -157,7 +158,8 @@ def test_large_config_sampled():
     rng = np.random.default_rng(42)
     samples = list(rng.integers(0, n, 48)) + [0, 1, 2, n - 3, n - 2, n - 1]
     out = lat.get_tuning()
-    tile = 64 * out["nodes_per_lane"] - 4 * out["steps_per_launch"]
+    tile = (64 * out["nodes_per_lane"] * out["waves_per_group"]
+            - 4 * out["steps_per_launch"])
     samples += [tile - 1, tile, 5 * tile + 1, (n // tile) * tile]
     fl3 = (fl.rho, fl.J, fl.zeta)
     got = f[:, torch.tensor(samples, device=f.device)].cpu().numpy()
