@@ -168,6 +168,49 @@ int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,
 int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
                  int64_t probe_steps, const char* cache_path, lbm_tuning* out);
 
+/* ----------------------------------------------- gradients (reverse mode)
+ *
+ * Gradients of a final-time loss through nsteps time steps: the forward run
+ * keeps the state every ckpt_every steps (about sqrt(nsteps) is the usual
+ * choice), the reverse sweep recomputes each segment from its checkpoint and
+ * runs the adjoint of the step (streaming, collision, source) backwards.  The
+ * relaxation rates s_e, s_psi, s_eps are independent inputs here (s_e also
+ * sets the viscosity of the source term); a caller that couples s_psi to s_e
+ * (lbm_coupled_rates) applies d s_psi / d s_e itself. */
+
+/* Bytes of the workspace that lbm_forward_ckpt / lbm_adjoint / lbm_loss /
+ * lbm_equilibrium_adjoint / lbm_moments_adjoint use for this nsteps and
+ * ckpt_every (0 on bad arguments): ceil(nsteps/ckpt_every) checkpoints,
+ * min(ckpt_every, nsteps) - 1 recomputed states, one more state and tables. */
+size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
+                                   int64_t ckpt_every);
+/* Advances f (device, 6*n) by nsteps steps in place like lbm_step, keeping
+ * the checkpoints in ws.  Required before the calls below with the same ws,
+ * nsteps and ckpt_every. */
+int lbm_forward_ckpt(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
+                     int64_t nsteps, int64_t ckpt_every);
+/* Reverse sweep (synchronising for rbar).  fbar (device, 6*n): on entry
+ * dL/df(T), on return dL/df(0).  rbar (host, 3): dL/d(s_e, s_psi, s_eps).
+ * use_graph = 1 captures the launch sequence into a hipGraph on first use
+ * (re-captured when ws, nsteps, ckpt_every, fbar or the tuning change). */
+int lbm_adjoint(lbm_handle* h, void* ws, size_t ws_bytes, int64_t nsteps,
+                int64_t ckpt_every, double* fbar, double rbar[3],
+                int use_graph);
+/* L = 1/2 sum_j (rho_j - target_j)^2 of the state f (target: device n
+ * doubles, or NULL for rho0 everywhere); *loss (host, synchronising) and
+ * fbar = dL/df (device, 6*n). */
+int lbm_loss(lbm_handle* h, const double* f, const double* target, void* ws,
+             size_t ws_bytes, double* loss, double* fbar);
+/* Reverse of lbm_set_equilibrium: given fbar = dL/df(0), the adjoints of the
+ * initial fields (device, n doubles each). */
+int lbm_equilibrium_adjoint(lbm_handle* h, const double* rho, const double* J,
+                            const double* zeta, const double* fbar,
+                            double* rho_bar, double* J_bar, double* zeta_bar,
+                            void* ws, size_t ws_bytes);
+/* Reverse of lbm_moments: fbar = M^T mbar (device, 6*n each). */
+int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
+                        void* ws, size_t ws_bytes);
+
 /* ------------------------------------------------- batches of lattices */
 
 /* A batch of n_inst independent periodic lattices of different lengths and
@@ -202,6 +245,10 @@ int lbm_batch_set_equilibrium(lbm_batch* b, const double* rho, const double* J,
  * and replayed with one hipGraphLaunch on the stream. */
 int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
                   int64_t nsteps, int use_graph);
+/* Moments m = M f of every node (device, 6*n_total doubles, moment order as
+ * lbm_moments). */
+int lbm_batch_moments(lbm_batch* b, const double* f, double* m, void* ws,
+                      size_t ws_bytes);
 /* Per-lattice diagnostics (synchronising): out (host, 8*n_inst doubles) gets
  * the eight values of lbm_diagnostics for each lattice.  Returns
  * LBM_ENONFINITE if any lattice has a non-finite or non-physical node. */
@@ -211,6 +258,27 @@ int lbm_batch_diagnostics(lbm_batch* b, const double* f, void* ws,
 int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
                        int64_t probe_steps, const char* cache_path,
                        lbm_tuning* out);
+
+/* Batch forms of the gradient calls: as above, lattice by lattice.  rbar
+ * (device, 3*n_inst) holds dL_i/d(s_e, s_psi, s_eps) of lattice i; loss
+ * (device, n_inst) the per-lattice losses.  Rate gradients are reduced in a
+ * fixed order (deterministic). */
+size_t lbm_batch_adjoint_workspace_bytes(const lbm_batch* b, int64_t nsteps,
+                                         int64_t ckpt_every);
+int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
+                           int64_t nsteps, int64_t ckpt_every);
+int lbm_batch_adjoint(lbm_batch* b, void* ws, size_t ws_bytes, int64_t nsteps,
+                      int64_t ckpt_every, double* fbar, double* rbar,
+                      int use_graph);
+int lbm_batch_loss(lbm_batch* b, const double* f, const double* target,
+                   void* ws, size_t ws_bytes, double* loss, double* fbar);
+int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
+                                  const double* J, const double* zeta,
+                                  const double* fbar, double* rho_bar,
+                                  double* J_bar, double* zeta_bar, void* ws,
+                                  size_t ws_bytes);
+int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
+                              void* ws, size_t ws_bytes);
 
 #ifdef __cplusplus
 }

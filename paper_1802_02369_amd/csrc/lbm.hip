@@ -447,6 +447,25 @@ __global__ __launch_bounds__(64 * WG) void k_batch_tile(
                   K);
 }
 
+// One workgroup per lattice of a batch: moments m = M f (eq. M-d1q3q3).
+__global__ __launch_bounds__(256) void k_batch_moments(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const double* __restrict__ f, double* __restrict__ m, int64_t S) {
+  const int inst = blockIdx.x;
+  const Consts c = cs[inst];
+  for (int64_t j = offs[inst] + threadIdx.x; j < offs[inst + 1]; j += 256) {
+    const double f0 = f[j], fp = f[S + j], fm = f[2 * S + j];
+    const double g0 = f[3 * S + j], gp = f[4 * S + j], gm = f[5 * S + j];
+    const double sf = fp + fm, sg = gp + gm;
+    m[j] = lbm::density(c, f0, fp, fm);
+    m[S + j] = c.mJ * (fp - fm);
+    m[2 * S + j] = c.mz * (g0 + sg);
+    m[3 * S + j] = c.me * (sf - 2.0 * f0);
+    m[4 * S + j] = c.mpsi * (gp - gm);
+    m[5 * S + j] = c.meps * (sg - 2.0 * g0);
+  }
+}
+
 // One workgroup per lattice of a batch: equilibrium populations.
 __global__ __launch_bounds__(256) void k_batch_equilibrium(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
@@ -679,6 +698,13 @@ int launch_batch_equilibrium(const Consts* cs, const int64_t* offs,
   hipLaunchKernelGGL(k_batch_equilibrium, dim3((unsigned)n_inst), dim3(256), 0,
                      s, cs, offs, rho, J, zeta, f, S);
   return hip_check(hipGetLastError(), "k_batch_equilibrium");
+}
+
+int launch_batch_moments(const Consts* cs, const int64_t* offs, int64_t n_inst,
+                         const double* f, double* m, int64_t S, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_moments, dim3((unsigned)n_inst), dim3(256), 0, s,
+                     cs, offs, f, m, S);
+  return hip_check(hipGetLastError(), "k_batch_moments");
 }
 
 int launch_batch_diag(const Consts* cs, const int64_t* offs, int64_t n_inst,

@@ -1,0 +1,720 @@
+// Reverse mode of the coupled D1Q3Q3 time step (Dubois, Graille & Lallemand,
+// arXiv 1802.02369, section 8, steps (i)-(viii)): adjoint kernels, loss and
+// seed, checkpointed forward and reverse drivers, for batches of lattices (a
+// single lattice is a batch of one).  Declared in include/lbm.h.
+//
+// Adjoint of one step, node j, given fbar(t+1) (the gradient with respect to
+// the state after the step):
+//   (viii)^T  fbar*_0(j) = fbar_0(t+1, j), fbar*_+(j) = fbar_+(t+1, j+1),
+//             fbar*_-(j) = fbar_-(t+1, j-1) (same for g);
+//   (vi)^T    adjoints of (rho, J, zeta + dz, e*, psi*, eps*) = M^-T fbar*;
+//   (vii)^T   dz_i = c rho_i w_i [du_i^2 + (cp/Pr) dT_i^2 w_i], w = 1/T,
+//             du_i = u_{i+1} - u_{i-1}, dT_i = T_{i+1} - T_{i-1},
+//             c = (1/s_e - 1/2)/4, depends on u, T of i-1 and i+1: node j
+//             gathers 2 c rho w du zbar and 2 c (cp/Pr) rho w^2 dT zbar from
+//             its two neighbours (the transposed scatter of the forward);
+//   (v)^T, (iv)^T, (ii)^T  the local chain through the relaxation, the
+//             equilibria and the equation of state back to f(t, j);
+//   rates     d/ds_e (relaxation of e and c), d/ds_psi, d/ds_eps.
+// The step has radius 2 in both f(t) and fbar(t+1).  One thread per node,
+// 256-node tiles whose 252 interior nodes are stored; u, T and the gathered
+// terms go through LDS.  Rate partials are summed per tile into a per-tile
+// slot (same workgroup, launches in order: deterministic) and reduced per
+// lattice in tile order at the end.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+
+using lbm::Consts;
+using lbm::TileRef;
+using namespace lbm;
+
+namespace {
+
+constexpr int kAdjBlock = 256;
+constexpr int kAdjOut = kAdjBlock - 4;
+
+__device__ __forceinline__ int64_t wrap_in(int64_t x, int64_t n, bool small) {
+  if (small) return lbm::wrap_mod(x, n);
+  return x < 0 ? x + n : (x >= n ? x - n : x);
+}
+
+// Forward quantities of one node that the reverse sweep reuses.
+struct NodeFwd {
+  double rho, J, zeta, e, psi, eps;
+  double u, s, X, T, w;
+  double e_eq, psi_eq, eps_eq;
+};
+
+__device__ __forceinline__ void node_forward(const Consts& c, double f0,
+                                             double fp, double fm, double g0,
+                                             double gp, double gm, NodeFwd& q) {
+  const double sf = fp + fm, sg = gp + gm;
+  q.rho = lbm::density(c, f0, fp, fm);
+  q.J = c.mJ * (fp - fm);
+  q.e = c.me * (sf - 2.0 * f0);
+  q.zeta = c.mz * (g0 + sg);
+  q.psi = c.mpsi * (gp - gm);
+  q.eps = c.meps * (sg - 2.0 * g0);
+  lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T);
+  q.w = 1.0 / q.T;
+  if (c.eq_kind == 0) {
+    const double p = q.rho * c.r * q.T;
+    q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
+    q.psi_eq = q.zeta * q.u;
+    q.eps_eq = c.eps_c * q.rho * q.X + q.e_eq * q.s;
+  } else {
+    q.e_eq = c.lin[0] * q.rho + c.lin[1] * q.J + c.lin[2] * q.zeta;
+    q.psi_eq = c.lin[3] * q.rho + c.lin[4] * q.J + c.lin[5] * q.zeta;
+    q.eps_eq = c.lin[6] * q.rho + c.lin[7] * q.J + c.lin[8] * q.zeta;
+  }
+}
+
+// Reverse of the equilibria (iv) and of the equation of state, given the
+// adjoints of e_eq, psi_eq, eps_eq and extra adjoints of u and T (from the
+// source); adds to the adjoints of rho, J, zeta.
+__device__ __forceinline__ void equilibria_adjoint(const Consts& c,
+                                                   const NodeFwd& q, double eb,
+                                                   double pb, double xb,
+                                                   double ub, double Tb,
+                                                   double& rb, double& Jb,
+                                                   double& zb) {
+  double sb = 0.0, Xb = 0.0;
+  const double ir = 1.0 / q.rho;
+  if (c.eq_kind == 0) {
+    // eps_eq = eps_c rho X + e_eq s
+    rb += c.eps_c * q.X * xb;
+    Xb += c.eps_c * q.rho * xb;
+    eb += q.s * xb;
+    sb += q.e_eq * xb;
+    // psi_eq = zeta u
+    zb += q.u * pb;
+    ub += q.zeta * pb;
+    // e_eq = 3 (J u + p) - 2 lambda^2 rho, p = rho r T
+    Jb += 3.0 * q.u * eb;
+    ub += 3.0 * q.J * eb;
+    const double pbar = 3.0 * eb;
+    rb -= c.two_l2 * eb;
+    rb += c.r * q.T * pbar;
+    Tb += q.rho * c.r * pbar;
+  } else {
+    rb += c.lin[0] * eb + c.lin[3] * pb + c.lin[6] * xb;
+    Jb += c.lin[1] * eb + c.lin[4] * pb + c.lin[7] * xb;
+    zb += c.lin[2] * eb + c.lin[5] * pb + c.lin[8] * xb;
+  }
+  // T = T0 exp(X), X = (gamma-1) ln(rho/rho0) + gamma s / cp - gamma s0 / cp
+  Xb += q.T * Tb;
+  rb += c.gm1 * ir * Xb;
+  sb += c.gcp * Xb;
+  // u = J / rho, s = zeta / rho
+  Jb += ub * ir;
+  rb -= q.u * ub * ir;
+  zb += sb * ir;
+  rb -= q.s * sb * ir;
+}
+
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const TileRef* __restrict__ tiles, int64_t ntiles,
+    const double* __restrict__ f, const double* __restrict__ fbn,
+    double* __restrict__ fbo, int64_t S, double* __restrict__ rslots) {
+  __shared__ double su[kAdjBlock], sT[kAdjBlock], sA[kAdjBlock], sB[kAdjBlock];
+  __shared__ double red[3][kAdjBlock];
+  const int64_t b = blockIdx.x;
+  if (b >= ntiles) return;  // uniform over the workgroup
+  const TileRef tr = tiles[b];
+  const int64_t off = offs[tr.inst];
+  const int64_t n = offs[tr.inst + 1] - off;
+  const Consts c = cs[tr.inst];
+  const int t = threadIdx.x;
+  const bool small = n < kAdjBlock + 4;
+  const int64_t jl0 = (int64_t)tr.t * kAdjOut - 2 + t;
+  const int64_t j = wrap_in(jl0, n, small);
+  const int64_t jr = j + 1 == n ? 0 : j + 1;
+  const int64_t jm = j == 0 ? n - 1 : j - 1;
+  const double* F = f + off;
+  const double* B = fbn + off;
+  // Phase A: forward recomputation at the node, streamed adjoint.
+  NodeFwd q;
+  node_forward(c, F[j], F[S + j], F[2 * S + j], F[3 * S + j], F[4 * S + j],
+               F[5 * S + j], q);
+  su[t] = q.u;
+  sT[t] = q.T;
+  const double a0 = B[j], ap = B[S + jr], am = B[2 * S + jm];
+  const double b0 = B[3 * S + j], bp = B[4 * S + jr], bm = B[5 * S + jm];
+  __syncthreads();
+  // Phase B: the node's source term and what it sends to its neighbours.
+  double du = 0.0, dT = 0.0;
+  const double Zb = c.ga * (b0 + bp + bm);  // adjoint of zeta + dz
+  if (t >= 1 && t < kAdjBlock - 1) {
+    du = su[t + 1] - su[t - 1];
+    dT = sT[t + 1] - sT[t - 1];
+    sA[t] = 2.0 * c.src_c * q.rho * q.w * du * Zb;
+    sB[t] = 2.0 * c.src_c * c.cPr * q.rho * q.w * q.w * dT * Zb;
+  }
+  __syncthreads();
+  const bool own = t >= 2 && t < kAdjBlock - 2 && jl0 < n;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  if (own) {
+    const double Q = du * du + c.cPr * dT * dT * q.w;
+    double ub = sA[t - 1] - sA[t + 1];
+    double Tb = sB[t - 1] - sB[t + 1] -
+                Zb * c.src_c * q.rho * q.w * q.w *
+                    (du * du + 2.0 * c.cPr * dT * dT * q.w);
+    double rb = Zb * c.src_c * q.w * Q;
+    if (c.src_c != 0.0) r0 -= Zb * 0.25 * q.rho * q.w * Q / (c.s_e * c.s_e);
+    // (vi)^T: adjoints of (rho, J, zeta, e*, psi*, eps*) from fbar*
+    rb += c.fa * (a0 + ap + am);
+    double Jb = c.fc * (ap - am);
+    const double esb = c.fb * (0.5 * (ap + am) - a0);
+    double zb = Zb;
+    const double psisb = c.gc * (bp - bm);
+    const double epssb = c.gb * (0.5 * (bp + bm) - b0);
+    // (v)^T
+    const double eb = (1.0 - c.s_e) * esb;
+    const double psib = (1.0 - c.s_psi) * psisb;
+    const double epsb = (1.0 - c.s_eps) * epssb;
+    r0 += (q.e_eq - q.e) * esb;
+    r1 += (q.psi_eq - q.psi) * psisb;
+    r2 += (q.eps_eq - q.eps) * epssb;
+    // (iv)^T and the equation of state
+    equilibria_adjoint(c, q, c.s_e * esb, c.s_psi * psisb, c.s_eps * epssb,
+                       ub, Tb, rb, Jb, zb);
+    // (ii)^T: fbar(t) = M^T mbar
+    double* O = fbo + off;
+    O[j] = c.rho0 * rb - 2.0 * c.me * eb;
+    O[S + j] = c.rho0 * rb + c.mJ * Jb + c.me * eb;
+    O[2 * S + j] = c.rho0 * rb - c.mJ * Jb + c.me * eb;
+    O[3 * S + j] = c.mz * zb - 2.0 * c.meps * epsb;
+    O[4 * S + j] = c.mz * zb + c.mpsi * psib + c.meps * epsb;
+    O[5 * S + j] = c.mz * zb - c.mpsi * psib + c.meps * epsb;
+  }
+  red[0][t] = r0;
+  red[1][t] = r1;
+  red[2][t] = r2;
+  __syncthreads();
+  for (int w = kAdjBlock / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] += red[0][t + w];
+      red[1][t] += red[1][t + w];
+      red[2][t] += red[2][t + w];
+    }
+    __syncthreads();
+  }
+  if (t < 3) rslots[3 * b + t] += red[t][0];
+}
+
+// fbar of the equilibrium initialisation -> adjoints of rho, J, zeta.
+__global__ __launch_bounds__(256) void k_equilibrium_adjoint(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const double* __restrict__ rho, const double* __restrict__ J,
+    const double* __restrict__ zeta, const double* __restrict__ fb,
+    double* __restrict__ rho_b, double* __restrict__ J_b,
+    double* __restrict__ zeta_b, int64_t S) {
+  const int inst = blockIdx.x;
+  const Consts c = cs[inst];
+  for (int64_t j = offs[inst] + threadIdx.x; j < offs[inst + 1]; j += 256) {
+    NodeFwd q;
+    q.rho = rho[j];
+    q.J = J[j];
+    q.zeta = zeta[j];
+    lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T);
+    if (c.eq_kind == 0) {
+      const double p = q.rho * c.r * q.T;
+      q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
+    }
+    const double a0 = fb[j], ap = fb[S + j], am = fb[2 * S + j];
+    const double b0 = fb[3 * S + j], bp = fb[4 * S + j], bm = fb[5 * S + j];
+    double rb = c.fa * (a0 + ap + am);
+    double Jb = c.fc * (ap - am);
+    double zb = c.ga * (b0 + bp + bm);
+    const double eb = c.fb * (0.5 * (ap + am) - a0);
+    const double pb = c.gc * (bp - bm);
+    const double xb = c.gb * (0.5 * (bp + bm) - b0);
+    equilibria_adjoint(c, q, eb, pb, xb, 0.0, 0.0, rb, Jb, zb);
+    rho_b[j] = rb;
+    J_b[j] = Jb;
+    zeta_b[j] = zb;
+  }
+}
+
+// fbar = M^T mbar (mbar in moment order rho, J, zeta, e, psi, eps).
+__global__ __launch_bounds__(256) void k_moments_adjoint(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const double* __restrict__ mb, double* __restrict__ fb, int64_t S) {
+  const int inst = blockIdx.x;
+  const Consts c = cs[inst];
+  for (int64_t j = offs[inst] + threadIdx.x; j < offs[inst + 1]; j += 256) {
+    const double rb = mb[j], Jb = mb[S + j], zb = mb[2 * S + j];
+    const double eb = mb[3 * S + j], pb = mb[4 * S + j], xb = mb[5 * S + j];
+    fb[j] = c.rho0 * rb - 2.0 * c.me * eb;
+    fb[S + j] = c.rho0 * rb + c.mJ * Jb + c.me * eb;
+    fb[2 * S + j] = c.rho0 * rb - c.mJ * Jb + c.me * eb;
+    fb[3 * S + j] = c.mz * zb - 2.0 * c.meps * xb;
+    fb[4 * S + j] = c.mz * zb + c.mpsi * pb + c.meps * xb;
+    fb[5 * S + j] = c.mz * zb - c.mpsi * pb + c.meps * xb;
+  }
+}
+
+// L_i = 1/2 sum_j (rho_j - target_j)^2 per lattice (target NULL: rho0) and
+// its gradient with respect to the state; fixed tree order.
+__global__ __launch_bounds__(256) void k_loss(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const double* __restrict__ f, const double* __restrict__ target,
+    double* __restrict__ loss, double* __restrict__ fb, int64_t S) {
+  __shared__ double red[256];
+  const int inst = blockIdx.x;
+  const Consts c = cs[inst];
+  double acc = 0.0;
+  for (int64_t j = offs[inst] + threadIdx.x; j < offs[inst + 1]; j += 256) {
+    const double rho = lbm::density(c, f[j], f[S + j], f[2 * S + j]);
+    const double d = rho - (target ? target[j] : c.rho0);
+    acc += 0.5 * d * d;
+    const double g = c.rho0 * d;
+    fb[j] = g;
+    fb[S + j] = g;
+    fb[2 * S + j] = g;
+    fb[3 * S + j] = 0.0;
+    fb[4 * S + j] = 0.0;
+    fb[5 * S + j] = 0.0;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[inst] = red[0];
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// rbar[3*inst + q] = sum over the lattice's adjoint tiles, in tile order.
+__global__ void k_rbar_reduce(const int64_t* __restrict__ first,
+                              int64_t n_inst, const double* __restrict__ slots,
+                              double* __restrict__ rbar) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t t = first[i]; t < first[i + 1]; ++t) {
+    a += slots[3 * t];
+    b += slots[3 * t + 1];
+    c += slots[3 * t + 2];
+  }
+  rbar[3 * i] = a;
+  rbar[3 * i + 1] = b;
+  rbar[3 * i + 2] = c;
+}
+
+// ------------------------------------------------------------ host side --
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct AdjLayout {
+  int64_t n_fwd, n_rec, n_adj, n_ck, n_seg;
+  size_t consts, offs, fwd_tiles, rec_tiles, adj_tiles, adj_first, rslots,
+      scratch, pp, ckpt, seg, total;
+};
+
+lbm_tuning rec_tuning(const lbm_tuning& t) {
+  lbm_tuning r = t;
+  r.steps_per_launch = 1;
+  return r;
+}
+
+int64_t adj_tile_count(const lbm_batch* b) {
+  int64_t s = 0;
+  for (int64_t i = 0; i < b->n_inst; ++i)
+    s += (b->offsets[i + 1] - b->offsets[i] + kAdjOut - 1) / kAdjOut;
+  return s;
+}
+
+AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C) {
+  AdjLayout L{};
+  L.n_fwd = b->count_tiles(b->tune);
+  L.n_rec = b->count_tiles(rec_tuning(b->tune));
+  L.n_adj = adj_tile_count(b);
+  L.n_ck = nsteps > 0 ? (nsteps + C - 1) / C : 1;
+  L.n_seg = std::max<int64_t>(0, std::min(C, nsteps) - 1);
+  const size_t state = sizeof(double) * 6 * (size_t)b->n_total;
+  size_t o = 0;
+  L.consts = o;
+  o = align256(o + sizeof(Consts) * b->n_inst);
+  L.offs = o;
+  o = align256(o + sizeof(int64_t) * (b->n_inst + 1));
+  L.fwd_tiles = o;
+  o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_fwd));
+  L.rec_tiles = o;
+  o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_rec));
+  L.adj_tiles = o;
+  o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_adj));
+  L.adj_first = o;
+  o = align256(o + sizeof(int64_t) * (b->n_inst + 1));
+  L.rslots = o;
+  o = align256(o + sizeof(double) * 3 * std::max<int64_t>(1, L.n_adj));
+  L.scratch = o;  // per-lattice loss / rbar staging
+  o = align256(o + sizeof(double) * 3 * b->n_inst);
+  L.pp = o;
+  o = align256(o + state);
+  L.ckpt = o;
+  o = align256(o + state * (size_t)L.n_ck);
+  L.seg = o;
+  o = align256(o + state * (size_t)L.n_seg);
+  L.total = o;
+  return L;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+std::vector<TileRef> tile_table(const lbm_batch* b, int64_t out) {
+  std::vector<TileRef> v;
+  for (int64_t i = 0; i < b->n_inst; ++i) {
+    const int64_t n = b->offsets[i + 1] - b->offsets[i];
+    for (int64_t t = 0; t * out < n; ++t) v.push_back(TileRef{(int32_t)i, (int32_t)t});
+  }
+  return v;
+}
+
+// Launches `steps` forward steps on f with ping-pong through pp (an even
+// number of launches when steps >= 2; otherwise one launch and a copy).
+int fwd_steps(lbm_batch* b, const Consts* cs, const int64_t* offs,
+              const TileRef* tiles, int64_t ntiles, double* f, double* pp,
+              int64_t steps, hipStream_t s) {
+  double* a = f;
+  double* w = pp;
+  int64_t launches = 0;
+  const int H = 2 * b->tune.steps_per_launch;
+  for (int k : split_steps(steps, b->tune.steps_per_launch)) {
+    int rc = launch_batch_tile(cs, offs, tiles, ntiles, a, w, b->n_total,
+                               b->tune.nodes_per_lane, H, k,
+                               b->tune.waves_per_group, s);
+    if (rc) return rc;
+    std::swap(a, w);
+    ++launches;
+  }
+  if (launches & 1)
+    return hip_check(hipMemcpyAsync(f, pp, sizeof(double) * 6 * b->n_total,
+                                    hipMemcpyDeviceToDevice, s),
+                     "hipMemcpyAsync");
+  return LBM_OK;
+}
+
+int check_adj(const lbm_batch* b, const void* ws, size_t ws_bytes,
+              int64_t nsteps, int64_t C) {
+  if (!b || !ws) return set_err(LBM_EINVAL, "NULL argument");
+  if (b->adj_ws != ws || b->adj_nsteps != nsteps || b->adj_ckpt != C ||
+      !same_tuning(b->adj_tune, b->tune))
+    return set_err(LBM_EINVAL,
+                   "no checkpoints for this workspace, nsteps and ckpt_every: "
+                   "call lbm_batch_forward_ckpt first");
+  if (ws_bytes < adj_layout(b, nsteps, C).total)
+    return set_err(LBM_EWORKSPACE, "adjoint workspace too small");
+  return LBM_OK;
+}
+
+// The reverse sweep: recompute each checkpoint segment, then adjoint steps.
+int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
+                    double* fbar, double* rbar, hipStream_t s) {
+  const AdjLayout L = adj_layout(b, nsteps, C);
+  const Consts* cs = at<Consts>(ws, L.consts);
+  const int64_t* offs = at<int64_t>(ws, L.offs);
+  const size_t SD = 6 * (size_t)b->n_total;
+  double* slots = at<double>(ws, L.rslots);
+  const int64_t nsl = 3 * std::max<int64_t>(1, L.n_adj);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((nsl + 255) / 256)), dim3(256), 0,
+                     s, slots, nsl, 0.0);
+  int rc = hip_check(hipGetLastError(), "k_fill");
+  if (rc) return rc;
+  double* cur = fbar;
+  double* oth = at<double>(ws, L.pp);
+  const int Prec = b->tune.nodes_per_lane, Wrec = b->tune.waves_per_group;
+  for (int64_t k = L.n_ck - 1; k >= 0; --k) {
+    const int64_t t0 = k * C;
+    const int64_t len = std::min(C, nsteps - t0);
+    double* ck = at<double>(ws, L.ckpt) + SD * k;
+    auto state = [&](int64_t i) {
+      return i == 0 ? ck : at<double>(ws, L.seg) + SD * (i - 1);
+    };
+    for (int64_t i = 1; i < len; ++i) {
+      rc = launch_batch_tile(cs, offs, at<TileRef>(ws, L.rec_tiles), L.n_rec,
+                             state(i - 1), state(i), b->n_total, Prec, 2, 1,
+                             Wrec, s);
+      if (rc) return rc;
+    }
+    for (int64_t i = len - 1; i >= 0; --i) {
+      hipLaunchKernelGGL(k_adjoint_step, dim3((unsigned)L.n_adj),
+                         dim3(kAdjBlock), 0, s, cs, offs,
+                         at<TileRef>(ws, L.adj_tiles), L.n_adj,
+                         (const double*)state(i), (const double*)cur, oth,
+                         b->n_total, slots);
+      if ((rc = hip_check(hipGetLastError(), "k_adjoint_step"))) return rc;
+      std::swap(cur, oth);
+    }
+  }
+  if (cur != fbar &&
+      (rc = hip_check(hipMemcpyAsync(fbar, cur, sizeof(double) * SD,
+                                     hipMemcpyDeviceToDevice, s),
+                      "hipMemcpyAsync")))
+    return rc;
+  hipLaunchKernelGGL(k_rbar_reduce, dim3((unsigned)((b->n_inst + 255) / 256)),
+                     dim3(256), 0, s, at<int64_t>(ws, L.adj_first), b->n_inst,
+                     (const double*)slots, rbar);
+  return hip_check(hipGetLastError(), "k_rbar_reduce");
+}
+
+lbm_batch* single_batch(lbm_handle* h) {
+  if (h->one) return h->one;
+  const int64_t offs[2] = {0, h->n};
+  if (lbm_batch_init(&h->one, 1, offs, &h->p, h->stream) != LBM_OK) return nullptr;
+  if (h->tune.kernel == LBM_KERNEL_BLOCKED) lbm_batch_set_tuning(h->one, &h->tune);
+  return h->one;
+}
+
+}  // namespace
+
+namespace lbm {
+void drop_adjoint_graph(lbm_batch* b) {
+  if (b->adj_exec) (void)hipGraphExecDestroy(b->adj_exec);
+  b->adj_exec = nullptr;
+  b->ag_fbar = nullptr;
+  b->ag_rbar = nullptr;
+}
+}  // namespace lbm
+
+extern "C" {
+
+size_t lbm_batch_adjoint_workspace_bytes(const lbm_batch* b, int64_t nsteps,
+                                         int64_t ckpt_every) {
+  if (!b || nsteps < 0 || ckpt_every < 1) return 0;
+  return adj_layout(b, nsteps, ckpt_every).total;
+}
+
+int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
+                           int64_t nsteps, int64_t ckpt_every) {
+  if (!b || !f || !ws) return set_err(LBM_EINVAL, "NULL argument");
+  if (nsteps < 0 || ckpt_every < 1)
+    return set_err(LBM_EINVAL, "need nsteps >= 0 and ckpt_every >= 1");
+  const AdjLayout L = adj_layout(b, nsteps, ckpt_every);
+  if (ws_bytes < L.total)
+    return set_err(LBM_EWORKSPACE, "adjoint workspace of %zu bytes, need %zu",
+                   ws_bytes, L.total);
+  if (overlaps(f, sizeof(double) * 6 * b->n_total, ws, ws_bytes))
+    return set_err(LBM_EINVAL, "f and ws overlap");
+  if (((uintptr_t)f | (uintptr_t)ws) & 7)
+    return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
+  const hipStream_t s = b->stream;
+  int rc = LBM_OK;
+  const bool same = b->adj_ws == ws && b->adj_nsteps == nsteps &&
+                    b->adj_ckpt == ckpt_every && same_tuning(b->adj_tune, b->tune);
+  if (!same) {
+    // tables of this workspace layout: forward tiles, recompute tiles
+    // (one step, halo 2), adjoint tiles and each lattice's first adjoint tile
+    const auto fwd = tile_table(b, tile_width(b->tune) - 4 * b->tune.steps_per_launch);
+    const auto rec = tile_table(b, tile_width(b->tune) - 4);
+    const auto adj = tile_table(b, kAdjOut);
+    std::vector<int64_t> first(b->n_inst + 1, 0);
+    for (const TileRef& t : adj) first[t.inst + 1]++;
+    for (int64_t i = 0; i < b->n_inst; ++i) first[i + 1] += first[i];
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+      if (!rc && bytes)
+        rc = hip_check(hipMemcpyAsync(at<char>(ws, off), src, bytes,
+                                      hipMemcpyHostToDevice, s),
+                       "hipMemcpyAsync");
+    };
+    up(L.consts, b->consts.data(), sizeof(Consts) * b->n_inst);
+    up(L.offs, b->offsets.data(), sizeof(int64_t) * (b->n_inst + 1));
+    up(L.fwd_tiles, fwd.data(), sizeof(TileRef) * fwd.size());
+    up(L.rec_tiles, rec.data(), sizeof(TileRef) * rec.size());
+    up(L.adj_tiles, adj.data(), sizeof(TileRef) * adj.size());
+    up(L.adj_first, first.data(), sizeof(int64_t) * first.size());
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (rc) return rc;
+    drop_adjoint_graph(b);
+    b->adj_ws = ws;
+    b->adj_nsteps = nsteps;
+    b->adj_ckpt = ckpt_every;
+    b->adj_tune = b->tune;
+  }
+  const size_t SB = sizeof(double) * 6 * b->n_total;
+  const Consts* cs = at<Consts>(ws, L.consts);
+  const int64_t* offs = at<int64_t>(ws, L.offs);
+  for (int64_t k = 0; k < L.n_ck && !rc; ++k) {
+    rc = hip_check(hipMemcpyAsync(at<char>(ws, L.ckpt) + SB * k, f, SB,
+                                  hipMemcpyDeviceToDevice, s),
+                   "hipMemcpyAsync");
+    const int64_t len = std::min(ckpt_every, nsteps - k * ckpt_every);
+    if (!rc && len > 0)
+      rc = fwd_steps(b, cs, offs, at<TileRef>(ws, L.fwd_tiles), L.n_fwd, f,
+                     at<double>(ws, L.pp), len, s);
+  }
+  return rc;
+}
+
+int lbm_batch_adjoint(lbm_batch* b, void* ws, size_t ws_bytes, int64_t nsteps,
+                      int64_t ckpt_every, double* fbar, double* rbar,
+                      int use_graph) {
+  int rc = check_adj(b, ws, ws_bytes, nsteps, ckpt_every);
+  if (rc) return rc;
+  if (!fbar || !rbar) return set_err(LBM_EINVAL, "NULL argument");
+  if (overlaps(fbar, sizeof(double) * 6 * b->n_total, ws, ws_bytes))
+    return set_err(LBM_EINVAL, "fbar overlaps the workspace");
+  if (!use_graph) return enqueue_adjoint(b, ws, nsteps, ckpt_every, fbar, rbar, b->stream);
+  if (!(b->adj_exec && b->ag_fbar == fbar && b->ag_rbar == rbar)) {
+    drop_adjoint_graph(b);
+    if (!b->cap &&
+        (rc = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking),
+                        "hipStreamCreate")))
+      return rc;
+    if ((rc = hip_check(hipStreamBeginCapture(b->cap,
+                                              hipStreamCaptureModeThreadLocal),
+                        "hipStreamBeginCapture")))
+      return rc;
+    const int rc_enq = enqueue_adjoint(b, ws, nsteps, ckpt_every, fbar, rbar, b->cap);
+    hipGraph_t graph = nullptr;
+    rc = hip_check(hipStreamEndCapture(b->cap, &graph), "hipStreamEndCapture");
+    if (rc_enq) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc_enq;
+    }
+    if (rc) return rc;
+    rc = hip_check(hipGraphInstantiate(&b->adj_exec, graph, nullptr, nullptr, 0),
+                   "hipGraphInstantiate");
+    (void)hipGraphDestroy(graph);
+    if (rc) {
+      b->adj_exec = nullptr;
+      return rc;
+    }
+    b->ag_fbar = fbar;
+    b->ag_rbar = rbar;
+  }
+  return hip_check(hipGraphLaunch(b->adj_exec, b->stream), "hipGraphLaunch");
+}
+
+int lbm_batch_loss(lbm_batch* b, const double* f, const double* target,
+                   void* ws, size_t ws_bytes, double* loss, double* fbar) {
+  if (!b || !f || !ws || !loss || !fbar) return set_err(LBM_EINVAL, "NULL argument");
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt).total)
+    return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  hipLaunchKernelGGL(k_loss, dim3((unsigned)b->n_inst), dim3(256), 0, b->stream,
+                     at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs), f, target,
+                     loss, fbar, b->n_total);
+  return hip_check(hipGetLastError(), "k_loss");
+}
+
+int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
+                                  const double* J, const double* zeta,
+                                  const double* fbar, double* rho_bar,
+                                  double* J_bar, double* zeta_bar, void* ws,
+                                  size_t ws_bytes) {
+  if (!b || !rho || !J || !zeta || !fbar || !rho_bar || !J_bar || !zeta_bar || !ws)
+    return set_err(LBM_EINVAL, "NULL argument");
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt).total)
+    return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  hipLaunchKernelGGL(k_equilibrium_adjoint, dim3((unsigned)b->n_inst), dim3(256),
+                     0, b->stream, at<Consts>(ws, L.consts),
+                     at<int64_t>(ws, L.offs), rho, J, zeta, fbar, rho_bar,
+                     J_bar, zeta_bar, b->n_total);
+  return hip_check(hipGetLastError(), "k_equilibrium_adjoint");
+}
+
+int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
+                              void* ws, size_t ws_bytes) {
+  if (!b || !mbar || !fbar || !ws) return set_err(LBM_EINVAL, "NULL argument");
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt).total)
+    return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  hipLaunchKernelGGL(k_moments_adjoint, dim3((unsigned)b->n_inst), dim3(256), 0,
+                     b->stream, at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs),
+                     mbar, fbar, b->n_total);
+  return hip_check(hipGetLastError(), "k_moments_adjoint");
+}
+
+// ----------------------------------------------------- single lattice --
+
+size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
+                                   int64_t ckpt_every) {
+  if (!h) return 0;
+  lbm_batch* b = single_batch(h);
+  // rbar staging for the host copy lives in the scratch region
+  return b ? lbm_batch_adjoint_workspace_bytes(b, nsteps, ckpt_every) : 0;
+}
+
+int lbm_forward_ckpt(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
+                     int64_t nsteps, int64_t ckpt_every) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  lbm_batch* b = single_batch(h);
+  if (!b) return LBM_EINVAL;
+  if (h->tune.kernel == LBM_KERNEL_BLOCKED && !same_tuning(b->tune, h->tune))
+    lbm_batch_set_tuning(b, &h->tune);
+  return lbm_batch_forward_ckpt(b, f, ws, ws_bytes, nsteps, ckpt_every);
+}
+
+int lbm_adjoint(lbm_handle* h, void* ws, size_t ws_bytes, int64_t nsteps,
+                int64_t ckpt_every, double* fbar, double rbar[3], int use_graph) {
+  if (!h || !rbar) return set_err(LBM_EINVAL, "NULL argument");
+  lbm_batch* b = single_batch(h);
+  if (!b) return LBM_EINVAL;
+  const AdjLayout L = adj_layout(b, nsteps, ckpt_every);
+  double* dev = at<double>(ws, L.scratch);
+  int rc = lbm_batch_adjoint(b, ws, ws_bytes, nsteps, ckpt_every, fbar, dev,
+                             use_graph);
+  if (!rc)
+    rc = hip_check(hipMemcpyAsync(rbar, dev, 3 * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream),
+                   "hipMemcpyAsync");
+  if (!rc) rc = hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return rc;
+}
+
+int lbm_loss(lbm_handle* h, const double* f, const double* target, void* ws,
+             size_t ws_bytes, double* loss, double* fbar) {
+  if (!h || !loss) return set_err(LBM_EINVAL, "NULL argument");
+  lbm_batch* b = single_batch(h);
+  if (!b) return LBM_EINVAL;
+  if (b->adj_ws != ws) return set_err(LBM_EINVAL, "call lbm_forward_ckpt first");
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  double* dev = at<double>(ws, L.scratch);
+  int rc = lbm_batch_loss(b, f, target, ws, ws_bytes, dev, fbar);
+  if (!rc)
+    rc = hip_check(hipMemcpyAsync(loss, dev, sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream),
+                   "hipMemcpyAsync");
+  if (!rc) rc = hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return rc;
+}
+
+int lbm_equilibrium_adjoint(lbm_handle* h, const double* rho, const double* J,
+                            const double* zeta, const double* fbar,
+                            double* rho_bar, double* J_bar, double* zeta_bar,
+                            void* ws, size_t ws_bytes) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  lbm_batch* b = single_batch(h);
+  if (!b) return LBM_EINVAL;
+  return lbm_batch_equilibrium_adjoint(b, rho, J, zeta, fbar, rho_bar, J_bar,
+                                       zeta_bar, ws, ws_bytes);
+}
+
+int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
+                        void* ws, size_t ws_bytes) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  lbm_batch* b = single_batch(h);
+  if (!b) return LBM_EINVAL;
+  return lbm_batch_moments_adjoint(b, mbar, fbar, ws, ws_bytes);
+}
+
+}  // extern "C"

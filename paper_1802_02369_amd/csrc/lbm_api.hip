@@ -99,11 +99,16 @@ int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream) {
   return LBM_OK;
 }
 
-void lbm_destroy(lbm_handle* h) { delete h; }
+void lbm_destroy(lbm_handle* h) {
+  if (!h) return;
+  lbm_batch_destroy(h->one);
+  delete h;
+}
 
 int lbm_set_stream(lbm_handle* h, void* stream) {
   if (!h) return set_err(LBM_EINVAL, "handle is NULL");
   h->stream = (hipStream_t)stream;
+  if (h->one) lbm_batch_set_stream(h->one, stream);
   return LBM_OK;
 }
 
@@ -114,6 +119,8 @@ int lbm_set_params(lbm_handle* h, const lbm_params* p) {
   if (rc) return rc;
   h->p = *p;
   h->c = c;
+  lbm_batch_destroy(h->one);  // rebuilt with the new constants when needed
+  h->one = nullptr;
   return LBM_OK;
 }
 

@@ -21,46 +21,7 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-bool same_tuning(const lbm_tuning& a, const lbm_tuning& b) {
-  return a.kernel == b.kernel && a.nodes_per_lane == b.nodes_per_lane &&
-         a.steps_per_launch == b.steps_per_launch &&
-         a.waves_per_group == b.waves_per_group;
-}
-
-int64_t tile_width(const lbm_tuning& t) {
-  return 64 * (int64_t)t.nodes_per_lane * t.waves_per_group;
-}
-
 }  // namespace
-
-struct lbm_batch {
-  int64_t n_inst = 0, n_total = 0;
-  std::vector<int64_t> offsets;
-  std::vector<lbm_params> params;
-  std::vector<Consts> consts;
-  hipStream_t stream = nullptr;
-  hipStream_t cap = nullptr;  // private stream used only for graph capture
-  lbm_tuning tune{};
-  // what lbm_batch_prepare uploaded
-  const void* prep_ws = nullptr;
-  lbm_tuning prep_tune{};
-  int64_t prep_tiles = 0;
-  // captured graph of the last lbm_batch_run(use_graph = 1)
-  hipGraphExec_t exec = nullptr;
-  const double* g_f = nullptr;
-  const void* g_ws = nullptr;
-  int64_t g_nsteps = -1;
-  lbm_tuning g_tune{};
-
-  // tiles of the current table for a tuning: sum of ceil(L_i / OUT)
-  int64_t count_tiles(const lbm_tuning& t) const {
-    const int64_t out = tile_width(t) - 4 * (int64_t)t.steps_per_launch;
-    int64_t s = 0;
-    for (int64_t i = 0; i < n_inst; ++i)
-      s += (offsets[i + 1] - offsets[i] + out - 1) / out;
-    return s;
-  }
-};
 
 namespace {
 
@@ -130,6 +91,14 @@ int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
                      "hipMemcpyAsync");
   return LBM_OK;
 }
+
+}  // namespace
+
+namespace lbm {
+void drop_adjoint_graph(lbm_batch* b);
+}
+
+namespace {
 
 void drop_graph(lbm_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -347,6 +316,7 @@ int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
 void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
   drop_graph(b);
+  lbm::drop_adjoint_graph(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
 }
@@ -481,6 +451,18 @@ int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     b->g_tune = b->tune;
   }
   return hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+}
+
+int lbm_batch_moments(lbm_batch* b, const double* f, double* m, void* ws,
+                      size_t ws_bytes) {
+  int rc = check_batch_ws(b, ws, ws_bytes);
+  if (rc) return rc;
+  if (!f || !m) return set_err(LBM_EINVAL, "NULL argument");
+  if (overlaps(f, sizeof(double) * 6 * b->n_total, m, sizeof(double) * 6 * b->n_total))
+    return set_err(LBM_EINVAL, "f and m overlap");
+  const Layout L = layout(b, b->prep_tiles, false);
+  return launch_batch_moments(at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs),
+                              b->n_inst, f, m, b->n_total, b->stream);
 }
 
 int lbm_batch_diagnostics(lbm_batch* b, const double* f, void* ws,

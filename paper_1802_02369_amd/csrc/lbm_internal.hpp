@@ -5,6 +5,7 @@
 
 #include <string>
 #include <vector>
+#include <map>
 
 #include "../../include/lbm.h"
 #include "lbm_device.hpp"
@@ -38,6 +39,8 @@ int launch_batch_equilibrium(const Consts* cs, const int64_t* offs,
                              int64_t n_inst, const double* rho, const double* J,
                              const double* zeta, double* f, int64_t S,
                              hipStream_t s);
+int launch_batch_moments(const Consts* cs, const int64_t* offs, int64_t n_inst,
+                         const double* f, double* m, int64_t S, hipStream_t s);
 int launch_batch_diag(const Consts* cs, const int64_t* offs, int64_t n_inst,
                       const double* f, int64_t S, double* out, hipStream_t s);
 
@@ -61,10 +64,63 @@ int check_tuning(const lbm_tuning* t);
 
 }  // namespace lbm
 
+namespace lbm {
+inline bool same_tuning(const lbm_tuning& a, const lbm_tuning& b) {
+  return a.kernel == b.kernel && a.nodes_per_lane == b.nodes_per_lane &&
+         a.steps_per_launch == b.steps_per_launch &&
+         a.waves_per_group == b.waves_per_group;
+}
+
+inline int64_t tile_width(const lbm_tuning& t) {
+  return 64 * (int64_t)t.nodes_per_lane * t.waves_per_group;
+}
+}  // namespace lbm
+
 struct lbm_handle {
   int64_t n;
   lbm_params p;
   lbm::Consts c;
   hipStream_t stream;
   lbm_tuning tune;
+  lbm_batch* one = nullptr;  // batch of this one lattice, for the adjoint
 };
+
+struct lbm_batch {
+  int64_t n_inst = 0, n_total = 0;
+  std::vector<int64_t> offsets;
+  std::vector<lbm_params> params;
+  std::vector<lbm::Consts> consts;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream used only for graph capture
+  lbm_tuning tune{};
+  // what lbm_batch_prepare uploaded
+  const void* prep_ws = nullptr;
+  lbm_tuning prep_tune{};
+  int64_t prep_tiles = 0;
+  // captured graph of the last lbm_batch_run(use_graph = 1)
+  hipGraphExec_t exec = nullptr;
+  const double* g_f = nullptr;
+  const void* g_ws = nullptr;
+  int64_t g_nsteps = -1;
+  lbm_tuning g_tune{};
+  // adjoint workspace uploaded by lbm_batch_forward_ckpt
+  const void* adj_ws = nullptr;
+  int64_t adj_nsteps = -1, adj_ckpt = -1;
+  lbm_tuning adj_tune{};
+  // captured graph of the last lbm_batch_adjoint(use_graph = 1)
+  hipGraphExec_t adj_exec = nullptr;
+  const double* ag_fbar = nullptr;
+  const double* ag_rbar = nullptr;
+
+  // tiles of the current table for a tuning: sum of ceil(L_i / OUT)
+  int64_t count_tiles(const lbm_tuning& t) const {
+    const int64_t out = lbm::tile_width(t) - 4 * (int64_t)t.steps_per_launch;
+    int64_t s = 0;
+    for (int64_t i = 0; i < n_inst; ++i)
+      s += (offsets[i + 1] - offsets[i] + out - 1) / out;
+    return s;
+  }
+};
+
+
+

@@ -90,8 +90,27 @@ def lib():
             "lbm_batch_run": ([_vp, _vp, _vp, _sz, _i64, ctypes.c_int],
                               ctypes.c_int),
             "lbm_batch_diagnostics": ([_vp, _vp, _vp, _sz, _dp], ctypes.c_int),
+            "lbm_batch_moments": ([_vp, _vp, _vp, _vp, _sz], ctypes.c_int),
             "lbm_batch_autotune": ([_vp, _vp, _vp, _sz, _i64, ctypes.c_char_p,
                                     ctypes.POINTER(CTuning)], ctypes.c_int),
+            "lbm_adjoint_workspace_bytes": ([_vp, _i64, _i64], _sz),
+            "lbm_forward_ckpt": ([_vp, _vp, _vp, _sz, _i64, _i64], ctypes.c_int),
+            "lbm_adjoint": ([_vp, _vp, _sz, _i64, _i64, _vp, _dp, ctypes.c_int],
+                            ctypes.c_int),
+            "lbm_loss": ([_vp, _vp, _vp, _vp, _sz, _dp, _vp], ctypes.c_int),
+            "lbm_equilibrium_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _vp, _sz], ctypes.c_int),
+            "lbm_moments_adjoint": ([_vp, _vp, _vp, _vp, _sz], ctypes.c_int),
+            "lbm_batch_adjoint_workspace_bytes": ([_vp, _i64, _i64], _sz),
+            "lbm_batch_forward_ckpt": ([_vp, _vp, _vp, _sz, _i64, _i64],
+                                       ctypes.c_int),
+            "lbm_batch_adjoint": ([_vp, _vp, _sz, _i64, _i64, _vp, _vp,
+                                   ctypes.c_int], ctypes.c_int),
+            "lbm_batch_loss": ([_vp, _vp, _vp, _vp, _sz, _vp, _vp], ctypes.c_int),
+            "lbm_batch_equilibrium_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                               _vp, _vp, _sz], ctypes.c_int),
+            "lbm_batch_moments_adjoint": ([_vp, _vp, _vp, _vp, _sz],
+                                          ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -243,6 +262,56 @@ class Lattice:
                                  ctypes.byref(t)))
         return self.get_tuning()
 
+    # ------------------------------------------------------ gradients --
+    def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):
+        nb = int(lib().lbm_adjoint_workspace_bytes(self._h, int(nsteps),
+                                                   int(ckpt_every)))
+        if nb == 0:
+            check(LBM_EINVAL)
+        return torch.empty((nb + 7) // 8, dtype=torch.float64, device=device)
+
+    def forward_ckpt(self, f, nsteps: int, ckpt_every: int, aws):
+        """Advances f by nsteps steps, keeping checkpoints in aws."""
+        check(lib().lbm_forward_ckpt(self._h, _dev_ptr(f, 6 * self.n, "f"),
+                                     _dev_ptr(aws), aws.numel() * 8,
+                                     int(nsteps), int(ckpt_every)))
+        return f
+
+    def adjoint(self, aws, nsteps: int, ckpt_every: int, fbar,
+                use_graph: bool = True):
+        """fbar: dL/df(T) in, dL/df(0) out.  Returns dL/d(s_e, s_psi, s_eps)."""
+        r = (ctypes.c_double * 3)()
+        check(lib().lbm_adjoint(self._h, _dev_ptr(aws), aws.numel() * 8,
+                                int(nsteps), int(ckpt_every),
+                                _dev_ptr(fbar, 6 * self.n, "fbar"), r,
+                                1 if use_graph else 0))
+        return list(r)
+
+    def loss(self, f, target, aws):
+        """L = 1/2 sum (rho - target)^2 (target None: rho0) and dL/df."""
+        fbar = torch.empty_like(f)
+        L = ctypes.c_double()
+        check(lib().lbm_loss(self._h, _dev_ptr(f, 6 * self.n, "f"),
+                             None if target is None else _dev_ptr(target, self.n, "target"),
+                             _dev_ptr(aws), aws.numel() * 8, ctypes.byref(L),
+                             _dev_ptr(fbar)))
+        return L.value, fbar
+
+    def equilibrium_adjoint(self, rho, J, zeta, fbar, aws):
+        out = [torch.empty_like(rho) for _ in range(3)]
+        check(lib().lbm_equilibrium_adjoint(
+            self._h, _dev_ptr(rho, self.n), _dev_ptr(J, self.n),
+            _dev_ptr(zeta, self.n), _dev_ptr(fbar, 6 * self.n),
+            *[_dev_ptr(x) for x in out], _dev_ptr(aws), aws.numel() * 8))
+        return tuple(out)
+
+    def moments_adjoint(self, mbar, aws):
+        fbar = torch.empty_like(mbar)
+        check(lib().lbm_moments_adjoint(self._h, _dev_ptr(mbar, 6 * self.n),
+                                        _dev_ptr(fbar), _dev_ptr(aws),
+                                        aws.numel() * 8))
+        return fbar
+
     def diagnostics(self, f: torch.Tensor, ws: torch.Tensor | None = None,
                     raise_nonfinite: bool = False):
         ws = ws if ws is not None else self.workspace(f.device)
@@ -335,6 +404,13 @@ class Batch:
                                   1 if use_graph else 0))
         return f
 
+    def moments(self, f: torch.Tensor) -> torch.Tensor:
+        ws = self.ws if self.ws is not None else self.prepare(f.device)
+        m = torch.empty_like(f)
+        check(lib().lbm_batch_moments(self._h, _dev_ptr(f, 6 * self.n_total, "f"),
+                                      _dev_ptr(m), _dev_ptr(ws), ws.numel() * 8))
+        return m
+
     def diagnostics(self, f: torch.Tensor, raise_nonfinite: bool = False):
         import numpy as np
         ws = self.ws if self.ws is not None else self.prepare(f.device)
@@ -355,3 +431,56 @@ class Batch:
             ws.numel() * 8, int(probe_steps),
             cache_path.encode() if cache_path else None, ctypes.byref(t)))
         return self.get_tuning()
+
+    # ------------------------------------------------------ gradients --
+    def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):
+        nb = int(lib().lbm_batch_adjoint_workspace_bytes(
+            self._h, int(nsteps), int(ckpt_every)))
+        if nb == 0:
+            check(LBM_EINVAL)
+        return torch.empty((nb + 7) // 8, dtype=torch.float64, device=device)
+
+    def forward_ckpt(self, f, nsteps: int, ckpt_every: int, aws):
+        check(lib().lbm_batch_forward_ckpt(
+            self._h, _dev_ptr(f, 6 * self.n_total, "f"), _dev_ptr(aws),
+            aws.numel() * 8, int(nsteps), int(ckpt_every)))
+        return f
+
+    def adjoint(self, aws, nsteps: int, ckpt_every: int, fbar,
+                use_graph: bool = True):
+        """fbar: dL/df(T) in, dL/df(0) out.  Returns (n_inst, 3) rate
+        gradients dL_i/d(s_e, s_psi, s_eps) on the device."""
+        rbar = torch.empty((self.n_inst, 3), dtype=torch.float64,
+                           device=fbar.device)
+        check(lib().lbm_batch_adjoint(
+            self._h, _dev_ptr(aws), aws.numel() * 8, int(nsteps),
+            int(ckpt_every), _dev_ptr(fbar, 6 * self.n_total, "fbar"),
+            _dev_ptr(rbar), 1 if use_graph else 0))
+        return rbar
+
+    def loss(self, f, target, aws):
+        """Per-lattice L_i = 1/2 sum (rho - target)^2 (target None: rho0) on
+        the device, and dL/df."""
+        fbar = torch.empty_like(f)
+        loss = torch.empty(self.n_inst, dtype=torch.float64, device=f.device)
+        check(lib().lbm_batch_loss(
+            self._h, _dev_ptr(f, 6 * self.n_total, "f"),
+            None if target is None else _dev_ptr(target, self.n_total, "target"),
+            _dev_ptr(aws), aws.numel() * 8, _dev_ptr(loss), _dev_ptr(fbar)))
+        return loss, fbar
+
+    def equilibrium_adjoint(self, rho, J, zeta, fbar, aws):
+        out = [torch.empty_like(rho) for _ in range(3)]
+        n = self.n_total
+        check(lib().lbm_batch_equilibrium_adjoint(
+            self._h, _dev_ptr(rho, n), _dev_ptr(J, n), _dev_ptr(zeta, n),
+            _dev_ptr(fbar, 6 * n), *[_dev_ptr(x) for x in out], _dev_ptr(aws),
+            aws.numel() * 8))
+        return tuple(out)
+
+    def moments_adjoint(self, mbar, aws):
+        fbar = torch.empty_like(mbar)
+        check(lib().lbm_batch_moments_adjoint(
+            self._h, _dev_ptr(mbar, 6 * self.n_total), _dev_ptr(fbar),
+            _dev_ptr(aws), aws.numel() * 8))
+        return fbar

@@ -1,0 +1,225 @@
+"""GPU parity of the reverse mode (adjoint step, checkpointed gradients, loss
+seed, equilibrium adjoint, batch form, autograd wrapper) against the oracle's
+adjoint, its tangent-linear model and central differences."""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import TOL, gpu_params, max_err, oracle_params, random_state
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def lbm():
+    from paper_1802_02369_amd import lbm as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev())
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear"])
+@pytest.mark.parametrize("n", [3, 5, 64, 251, 252, 253, 256, 1000, 3001])
+def test_one_adjoint_step(pname, n):
+    """fbar(t) and the rate partials of one step against the oracle's
+    adjoint (exact per-node Jacobian blocks, transposed)."""
+    rng = np.random.default_rng(n)
+    po = oracle_params(pname)
+    f0 = random_state(rng, n, po)
+    fbn = rng.standard_normal((6, n))
+    want_fb, want_r = oracle.step_adjoint(f0, fbn, po)
+    lat = lbm().Lattice(n, gpu_params(po))
+    aws = lat.adjoint_workspace(1, 1, dev())
+    f = T(f0)
+    lat.forward_ckpt(f, 1, 1, aws)
+    assert max_err(f.cpu().numpy(), oracle.step(f0, po)) < TOL
+    fb = T(fbn)
+    r = lat.adjoint(aws, 1, 1, fb, use_graph=False)
+    assert max_err(fb.cpu().numpy(), want_fb) < TOL
+    scale = np.abs(want_r).max()
+    np.testing.assert_allclose(r, want_r, rtol=1e-11, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("pname,n,steps,ckpt", [
+    ("paper", 64, 40, 7), ("odd", 300, 33, 33), ("nosource", 97, 25, 1),
+    ("linear", 260, 18, 5), ("odd", 1200, 50, 8)])
+def test_checkpointed_gradient(pname, n, steps, ckpt):
+    rng = np.random.default_rng(steps)
+    po = oracle_params(pname)
+    j = np.arange(n)
+    rho = po.rho0 * (1 + 0.05 * np.sin(2 * np.pi * j / n) + 0.01 * rng.standard_normal(n))
+    J = po.rho0 * po.lam * 0.02 * np.cos(2 * np.pi * j / n)
+    zeta = rho * (po.s0 + 0.02 * po.cp * rng.standard_normal(n))
+    tgt = po.rho0 * (1 + 0.03 * np.sin(2 * np.pi * j / n + 1))
+    L, rb, Jb, zb, sb = oracle.gradient(rho, J, zeta, steps, tgt, po)
+    lat = lbm().Lattice(n, gpu_params(po))
+    aws = lat.adjoint_workspace(steps, ckpt, dev())
+    r_, J_, z_ = T(rho), T(J), T(zeta)
+    f = lat.equilibrium(r_, J_, z_)
+    lat.forward_ckpt(f, steps, ckpt, aws)
+    Lg, fbar = lat.loss(f, T(tgt), aws)
+    assert rel(Lg, L) < 1e-11
+    r = lat.adjoint(aws, steps, ckpt, fbar)
+    g = lat.equilibrium_adjoint(r_, J_, z_, fbar, aws)
+    for got, want in zip(g, (rb, Jb, zb)):
+        w = np.abs(want).max()
+        assert np.abs(got.cpu().numpy() - want).max() <= 1e-10 * w + 1e-300
+    np.testing.assert_allclose(r, sb, rtol=1e-10, atol=1e-12 * np.abs(sb).max())
+
+
+def test_graph_adjoint_matches_direct():
+    rng = np.random.default_rng(5)
+    po = oracle_params("odd")
+    n, steps, ckpt = 700, 40, 9
+    f0 = random_state(rng, n, po)
+    lat = lbm().Lattice(n, gpu_params(po))
+    aws = lat.adjoint_workspace(steps, ckpt, dev())
+    f = T(f0)
+    lat.forward_ckpt(f, steps, ckpt, aws)
+    seed = T(rng.standard_normal((6, n)))
+    ref = seed.clone()
+    rr = lat.adjoint(aws, steps, ckpt, ref, use_graph=False)
+    for rep in range(3):
+        fb = seed.clone()
+        _ = (fb * 3).sum().item()
+        r = lat.adjoint(aws, steps, ckpt, fb, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(fb, ref) and r == rr, rep
+
+
+def test_adjoint_config_gradient():
+    """N = 8192, eight-mode initial field, 10000 steps, checkpoints every
+    100: the gradient of L = 1/2 |rho(T) - target|^2 (target: the oracle's
+    run of the seed-4 field) against the oracle's tangent-linear directional
+    derivatives (random directions in rho(0), J(0) and each rate) and
+    against central differences of the GPU forward run in the rates."""
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_adjoint()
+    n, steps, ckpt = cfg["n"], cfg["steps"], cfg["ckpt"]
+    fl, tf = cfg["fields"], cfg["target_fields"]
+    po = oracle_params("paper", s_e=cfg["s_e"])
+    say(f"adjoint config n={n} steps={steps} ckpt={ckpt}")
+    tgt = oracle.moments(oracle.run(oracle.init(tf.rho, tf.J, tf.zeta, po), steps, po), po)[0]
+    lat = lbm().Lattice(n, gpu_params(po))
+    aws = lat.adjoint_workspace(steps, ckpt, dev())
+    r_, J_, z_ = T(fl.rho), T(fl.J), T(fl.zeta)
+    f = lat.equilibrium(r_, J_, z_)
+    lat.forward_ckpt(f, steps, ckpt, aws)
+    Lg, fbar = lat.loss(f, T(tgt), aws)
+    rbar = lat.adjoint(aws, steps, ckpt, fbar)
+    g_rho, g_J, g_z = (x.cpu().numpy() for x in lat.equilibrium_adjoint(r_, J_, z_, fbar, aws))
+    rng = np.random.default_rng(9)
+    dirs = []
+    for k in range(4):
+        dirs.append((rng.standard_normal(n), rng.standard_normal(n), np.zeros(n), np.zeros(3)))
+    for q in range(3):
+        e = np.zeros(3)
+        e[q] = 1.0
+        dirs.append((np.zeros(n), np.zeros(n), np.zeros(n), e))
+    say("  oracle tangent-linear runs: 7 directions")
+    with ThreadPoolExecutor(7) as ex:
+        res = list(ex.map(lambda d: oracle.directional(fl.rho, fl.J, fl.zeta, *d, steps, tgt, po), dirs))
+    for (Lo, dL), d in zip(res, dirs):
+        adj = g_rho @ d[0] + g_J @ d[1] + np.dot(rbar, d[3])
+        say(f"  <grad, v> = {adj:.12e}   tangent-linear {dL:.12e}")
+        assert rel(Lg, Lo) < 1e-9
+        assert rel(adj, dL) < 1e-6
+    # central differences of the GPU forward run in each rate; the error is
+    # measured against the size of the rate gradient (dL/ds_eps is ~1e-8 here,
+    # below the rounding floor of a difference quotient of L ~ 1)
+    h = 1e-5
+    scale = np.abs(rbar).max()
+    for q in range(3):
+        vals = []
+        for sgn in (1, -1):
+            rates = [po.s_e, po.s_psi, po.s_eps]
+            rates[q] += sgn * h
+            p2 = oracle_params("paper", s_e=rates[0], s_psi=rates[1], s_eps=rates[2])
+            l2 = lbm().Lattice(n, gpu_params(p2))
+            g = l2.equilibrium(r_, J_, z_)
+            l2.step(g, steps)
+            vals.append(0.5 * float(((g[:3].sum(0) * po.rho0 - T(tgt)) ** 2).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        say(f"  dL/drate[{q}]: adjoint {rbar[q]:.10e}  central difference {fd:.10e}")
+        assert abs(rbar[q] - fd) < 1e-6 * scale
+
+
+def test_batched_adjoint():
+    """Per-lattice gradients of a ragged batch against the oracle, lattice by
+    lattice (loss 1/2 sum (rho(T) - rho0)^2 per lattice)."""
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_batched_adjoint(n_inst=24, steps=150, ckpt=13,
+                                           lmin=100, lmax=1500)
+    bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
+    ps = [oracle_params("paper", s_e=float(s)) for s in bt.s_e]
+    b = lbm().Batch(bt.offsets, [gpu_params(p) for p in ps])
+    fl = bt.fields
+    r_, J_, z_ = T(fl.rho), T(fl.J), T(fl.zeta)
+    f = b.equilibrium(r_, J_, z_)
+    aws = b.adjoint_workspace(steps, ckpt, dev())
+    b.forward_ckpt(f, steps, ckpt, aws)
+    loss, fbar = b.loss(f, None, aws)
+    rbar = b.adjoint(aws, steps, ckpt, fbar).cpu().numpy()
+    g_rho = b.equilibrium_adjoint(r_, J_, z_, fbar, aws)[0].cpu().numpy()
+    loss = loss.cpu().numpy()
+
+    def one(i):
+        a, c = bt.offsets[i], bt.offsets[i + 1]
+        x = bt.instance(i)
+        return oracle.gradient(x.rho, x.J, x.zeta, steps, np.full(c - a, ps[i].rho0), ps[i])
+
+    with ThreadPoolExecutor(16) as ex:
+        res = list(ex.map(one, range(bt.n_inst)))
+    for i, (L, rb, Jb, zb, sb) in enumerate(res):
+        a, c = bt.offsets[i], bt.offsets[i + 1]
+        assert rel(loss[i], L) < 1e-10, i
+        assert np.abs(g_rho[a:c] - rb).max() <= 1e-10 * np.abs(rb).max(), i
+        np.testing.assert_allclose(rbar[i], sb, rtol=1e-9, atol=1e-12 * np.abs(sb).max())
+
+
+def test_autograd_function():
+    from paper_1802_02369_amd.autograd import LBMFunction
+    po = oracle_params("paper", s_e=1.7)
+    n, steps, ckpt = 128, 60, 8
+    rng = np.random.default_rng(4)
+    j = np.arange(n)
+    rho = 1 + 0.05 * np.sin(2 * np.pi * j / n) + 0.01 * rng.standard_normal(n)
+    J = 0.02 * np.cos(2 * np.pi * j / n)
+    zeta = 0.01 * rng.standard_normal(n)
+    tgt = 1 + 0.02 * np.sin(2 * np.pi * j / n + 2)
+    r_ = T(rho).requires_grad_()
+    J_ = T(J).requires_grad_()
+    z_ = T(zeta).requires_grad_()
+    se = torch.tensor(1.7, dtype=torch.float64, device=dev(), requires_grad=True)
+    seps = torch.tensor(1.5, dtype=torch.float64, device=dev(), requires_grad=True)
+    rho_T = LBMFunction.apply(r_, J_, z_, se, seps, steps, ckpt, None)
+    loss = 0.5 * ((rho_T - T(tgt)) ** 2).sum()
+    loss.backward()
+    L, rb, Jb, zb, sb = oracle.gradient(rho, J, zeta, steps, tgt, po)
+    assert rel(loss.item(), L) < 1e-11
+    for got, want in ((r_.grad, rb), (J_.grad, Jb), (z_.grad, zb)):
+        assert np.abs(got.cpu().numpy() - want).max() <= 1e-10 * np.abs(want).max()
+    _, _, dpsi = lbm().coupled_rates(1.7)
+    assert rel(se.grad.item(), sb[0] + sb[1] * dpsi) < 1e-9
+    assert rel(seps.grad.item(), sb[2]) < 1e-9
