@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", type=str, default=None,
+                    help="comma list of extra legs to run: plain,batched,"
+                         "adjoint,batched_adjoint")
     ap.add_argument("--flops-per-node", type=float, default=None,
                     help="override the FP64 flops per node-update")
     ap.add_argument("--tuning", type=str, default=None,
@@ -131,6 +134,111 @@ def cpu_baseline(n: int, steps: int = 3):
                       f"({n * steps:.3g} node-updates, {dt:.1f} s, 1 thread)"}
 
 
+def _dev_fields(torch, fl, dev):
+    return [torch.from_numpy(x).to(dev) for x in (fl.rho, fl.J, fl.zeta)]
+
+
+def bench_batched(torch, lbm, workloads, stream, single_glups):
+    """4096 lattices, lengths log-uniform in [512, 16384], 5000 steps in one
+    hipGraph launch, tile shape from the autotuner."""
+    import tempfile
+    dev = torch.device("cuda:0")
+    cfg = workloads.config_batched()
+    bt, steps = cfg["batch"], cfg["steps"]
+    log(f"bench: batched, {bt.n_inst} lattices, {bt.offsets[-1]} nodes, "
+        f"{steps} steps")
+    params = []
+    for s_e in bt.s_e:
+        s_psi, s_eps, _ = lbm.coupled_rates(float(s_e))
+        params.append(lbm.Params(s_e=float(s_e), s_psi=s_psi, s_eps=s_eps))
+    b = lbm.Batch(bt.offsets, params)
+    f0 = b.equilibrium(*_dev_fields(torch, bt.fields, dev))
+    f = f0.clone()
+    cache = os.path.join(tempfile.gettempdir(), "lbm_tune_cache.json")
+    tune = b.autotune(f, probe_steps=32, cache_path=cache)
+    b.run(f, steps)  # warm-up, captures the graph
+    torch.cuda.synchronize()
+    ms = time_runs(lambda: b.run(f, steps), lambda: f.copy_(f0), 1, torch,
+                   stream)
+    d = b.diagnostics(f)
+    ok = bool((d[:, 6] == 0).all() and (d[:, 7] == 0).all())
+    g = b.n_total * steps / (ms * 1e-3) / 1e9
+    log(f"bench: batched {g:.2f} GLUPS, tuning {tune}, finite: {ok}")
+    return {"value": g, "unit": "GLUPS", "n_inst": bt.n_inst,
+            "n_nodes": b.n_total, "time_steps": steps, "ms": ms,
+            "tuning": tune, "graph": True, "valid": ok,
+            "vs_single_lattice": g / single_glups}
+
+
+def bench_adjoint(torch, lbm, workloads, stream):
+    """Gradient of L = 1/2 |rho(T) - target|^2 on one lattice of 8192 nodes
+    through 10000 steps (checkpoints every 100): forward with checkpoints,
+    loss seed, recompute + reverse sweep (one hipGraph), equilibrium adjoint.
+    Throughput in forward node-steps per second of the whole gradient."""
+    dev = torch.device("cuda:0")
+    cfg = workloads.config_adjoint()
+    n, steps, ck = cfg["n"], cfg["steps"], cfg["ckpt"]
+    s_psi, s_eps, _ = lbm.coupled_rates(cfg["s_e"])
+    lat = lbm.Lattice(n, lbm.Params(s_e=cfg["s_e"], s_psi=s_psi, s_eps=s_eps))
+    tgt_f = lat.equilibrium(*_dev_fields(torch, cfg["target_fields"], dev))
+    lat.step(tgt_f, steps)
+    target = lat.moments(tgt_f)[0].clone()
+    fields = _dev_fields(torch, cfg["fields"], dev)
+    aws = lat.adjoint_workspace(steps, ck, dev)
+    log(f"bench: adjoint, n={n}, {steps} steps, checkpoints every {ck}")
+
+    def grad():
+        f = lat.equilibrium(*fields)
+        lat.forward_ckpt(f, steps, ck, aws)
+        _, fbar = lat.loss(f, target, aws)
+        r = lat.adjoint(aws, steps, ck, fbar)
+        lat.equilibrium_adjoint(*fields, fbar, aws)
+        return r
+
+    grad()  # warm-up, captures the reverse graph
+    torch.cuda.synchronize()
+    ms = time_runs(grad, lambda: None, 2, torch, stream) / 2
+    g = n * steps / (ms * 1e-3) / 1e9
+    log(f"bench: adjoint {g:.3f} G node-steps/s ({ms:.1f} ms per gradient)")
+    return {"value": g, "unit": "G forward node-steps/s (whole gradient)",
+            "n_nodes": n, "time_steps": steps, "ckpt_every": ck,
+            "ms_per_gradient": ms}
+
+
+def bench_batched_adjoint(torch, lbm, workloads, stream):
+    """Per-lattice rate gradients of 1024 lattices (lengths uniform in
+    [1024, 8192]) through 4000 steps, checkpoints every 63, one reverse
+    hipGraph."""
+    dev = torch.device("cuda:0")
+    cfg = workloads.config_batched_adjoint()
+    bt, steps, ck = cfg["batch"], cfg["steps"], cfg["ckpt"]
+    params = []
+    for s_e in bt.s_e:
+        s_psi, s_eps, _ = lbm.coupled_rates(float(s_e))
+        params.append(lbm.Params(s_e=float(s_e), s_psi=s_psi, s_eps=s_eps))
+    b = lbm.Batch(bt.offsets, params)
+    fields = _dev_fields(torch, bt.fields, dev)
+    aws = b.adjoint_workspace(steps, ck, dev)
+    log(f"bench: batched adjoint, {bt.n_inst} lattices, {b.n_total} nodes, "
+        f"{steps} steps, checkpoints every {ck} ({aws.numel() * 8 / 1e9:.1f} GB)")
+
+    def grad():
+        f = b.equilibrium(*fields)
+        b.forward_ckpt(f, steps, ck, aws)
+        _, fbar = b.loss(f, None, aws)
+        return b.adjoint(aws, steps, ck, fbar)
+
+    grad()
+    torch.cuda.synchronize()
+    ms = time_runs(grad, lambda: None, 1, torch, stream)
+    g = b.n_total * steps / (ms * 1e-3) / 1e9
+    log(f"bench: batched adjoint {g:.3f} G node-steps/s ({ms:.1f} ms)")
+    del aws
+    return {"value": g, "unit": "G forward node-steps/s (whole gradient)",
+            "n_inst": bt.n_inst, "n_nodes": b.n_total, "time_steps": steps,
+            "ckpt_every": ck, "ms_per_gradient": ms}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -212,7 +320,7 @@ def main():
         "valid": bool(ok),
     }
 
-    if not args.no_extras:
+    if not args.no_extras and "plain" in (args.only or "plain").split(","):
         # one launch per time step on the same lattice: HBM-bound reference
         plat = lbm.Lattice(n, params)
         plat.set_tuning(lbm.KERNEL_PLAIN)
@@ -231,6 +339,15 @@ def main():
                          "frac": BYTES_PER_NODE_LAUNCH * n / (plaunch * 1e-3) / 1e9
                          / HBM_PEAK_GBS}}
         log(f"bench: plain {out['plain']['value']:.2f} GLUPS")
+
+    legs = set((args.only or "plain,batched,adjoint,batched_adjoint").split(","))
+    if not args.no_extras and "batched" in legs:
+        out["batched"] = bench_batched(torch, lbm, workloads, stream, out["value"])
+    if not args.no_extras and "adjoint" in legs:
+        out["adjoint"] = bench_adjoint(torch, lbm, workloads, stream)
+    if not args.no_extras and "batched_adjoint" in legs:
+        out["batched_adjoint"] = bench_batched_adjoint(torch, lbm, workloads,
+                                                       stream)
 
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline (about 15 s)")
