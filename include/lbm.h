@@ -56,17 +56,28 @@ enum {
  *           of section 7.  s_e also sets the viscosity of the source term,
  *           nu = (1/s_e - 1/2) lambda dx (eqs. henon-d1q3q3, nu-d1q3q3).
  *   u0_lin, s0_lin  reference state of the linearised equilibria
- *           (eq_kind = 1)
+ *           (eq_kind = 1); u0_lin is also the advection velocity u0 of the
+ *           thermal scheme (eq_kind = 3)
+ *   alpha   eps_eq = alpha lambda^2 zeta of the thermal scheme (eq_kind = 3),
+ *           -2 < alpha < 1 (section 4)
  *   source_on  1: add the entropy production of step (vii) of section 8
  *   eq_kind    0: nonlinear equilibria of section 8 (eqs. energie-equilibre,
  *              psi-equilibre, eq-energie-entropie-d1q3q3);
  *              1: linear equilibria of section 7 (eq. equilibres-NS-linearise,
- *              printed for lambda = cp = rho0 = 1; other values are rejected)
+ *              printed for lambda = cp = rho0 = 1; other values are rejected);
+ *              2: fluid D1Q3 scheme of sections 2-3 (eq. energie-equilibre
+ *              with the isentropic pressure p0 (rho/rho0)^gamma), the g
+ *              distribution passive (psi_eq = eps_eq = 0);
+ *              3: thermal D1Q3 advection-diffusion scheme of section 4
+ *              (psi_eq = u0 zeta, eps_eq = alpha lambda^2 zeta), the f
+ *              distribution passive (e_eq = (3 c0^2 - 2 lambda^2) rho).
+ *              Kinds 2 and 3 need source_on = 0.
  */
 typedef struct lbm_params {
   double lambda, rho0, cp, gamma, prandtl, c0, s0;
   double s_e, s_psi, s_eps;
   double u0_lin, s0_lin;
+  double alpha;
   int32_t source_on;
   int32_t eq_kind;
 } lbm_params;

@@ -44,6 +44,7 @@ class OrcParams(ctypes.Structure):
         ("s_e", ctypes.c_double), ("s_psi", ctypes.c_double),
         ("s_eps", ctypes.c_double),
         ("u0_lin", ctypes.c_double), ("s0_lin", ctypes.c_double),
+        ("alpha", ctypes.c_double),
         ("source_on", ctypes.c_int32), ("eq_kind", ctypes.c_int32),
     ]
 
@@ -64,6 +65,7 @@ class Params:
     s_eps: float = 1.5
     u0_lin: float = 0.0
     s0_lin: float = 0.0
+    alpha: float = 0.0
     source_on: int = 1
     eq_kind: int = 0
 
@@ -74,7 +76,7 @@ class Params:
         return OrcParams(self.lam, self.rho0, self.cp, self.gamma,
                          self.prandtl, self.c0, self.s0, self.dx, self.s_e,
                          s_psi, self.s_eps, self.u0_lin, self.s0_lin,
-                         int(self.source_on), int(self.eq_kind))
+                         self.alpha, int(self.source_on), int(self.eq_kind))
 
     def rates(self) -> tuple[float, float, float]:
         p = self.c()

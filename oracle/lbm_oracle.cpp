@@ -193,10 +193,14 @@ bool make_ctx(const orc_params* p, Ctx* c) {
   if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return false;
   if (!valid_rate(p->s_e) || !valid_rate(p->s_psi) || !valid_rate(p->s_eps))
     return false;
-  if (p->eq_kind != 0 && p->eq_kind != 1) return false;
+  if (p->eq_kind < 0 || p->eq_kind > 3) return false;
   // The linear equilibria of section 7 are printed in units lambda = cp = 1.
   if (p->eq_kind == 1 && (p->lambda != 1.0 || p->cp != 1.0 || p->rho0 != 1.0))
     return false;
+  // The single-distribution schemes carry no temperature source; the
+  // thermal one is stable for -2 < alpha < 1 (section 4).
+  if (p->eq_kind >= 2 && p->source_on) return false;
+  if (p->eq_kind == 3 && !(p->alpha > -2.0 && p->alpha < 1.0)) return false;
   c->p = *p;
   const double l = p->lambda, cp = p->cp, r0 = p->rho0;
   // Eq. M-d1q3q3: rows (rho, J, zeta, e, psi, eps), columns (f0, f+, f-,
@@ -250,6 +254,21 @@ void equilibria(const Ctx& c, const S& rho, const S& J, const S& zeta,
                  (rho * (s - p.s0) +
                   (1.0 - 1.0 / p.gamma) * p.cp * rho * log(rho / p.rho0)) +
              (3.0 * (rho * u * u + pr) - 2.0 * l2 * rho) * s;
+  } else if (p.eq_kind == 2) {
+    // Section 2-3: fluid D1Q3 for the isentropic equations, eq.
+    // energie-equilibre with the isentropic pressure p0 (rho/rho0)^gamma.
+    // The entropy distribution is left passive (psi_eq = eps_eq = 0).
+    const S p_iso = c.p0 * pow(rho / p.rho0, p.gamma);
+    e_eq = 3.0 * (rho * u * u + p_iso) - 2.0 * l2 * rho;
+    psi_eq = 0.0 * rho;
+    eps_eq = 0.0 * rho;
+  } else if (p.eq_kind == 3) {
+    // Section 4: thermal D1Q3, psi_eq = u0 zeta, eps_eq = alpha lambda^2 zeta.
+    // The fluid distribution is left passive with the linear acoustic
+    // equilibrium e_eq = (3 c0^2 - 2 lambda^2) rho.
+    e_eq = (3.0 * p.c0 * p.c0 - 2.0 * l2) * rho;
+    psi_eq = p.u0_lin * zeta;
+    eps_eq = p.alpha * l2 * zeta;
   } else {
     // Eq. equilibres-NS-linearise, as printed (units lambda = cp = 1).
     const double u0 = p.u0_lin, s0 = p.s0_lin, c0 = p.c0, g = p.gamma;

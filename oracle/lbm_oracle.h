@@ -35,10 +35,17 @@ typedef struct orc_params {
   double s0;       /* reference specific entropy of the EOS */
   double dx;       /* space step; the scheme depends on it only through nu */
   double s_e, s_psi, s_eps; /* relaxation rates of e, psi, eps */
-  double u0_lin, s0_lin;    /* reference state of the linearised equilibria */
+  double u0_lin, s0_lin;    /* reference state of the linearised equilibria;
+                               u0_lin is also the advection velocity u0 of
+                               the thermal scheme (eq_kind 3) */
+  double alpha;             /* eps_eq = alpha lambda^2 zeta (eq_kind 3) */
   int32_t source_on;        /* 1: add the entropy-production source, step (vii) */
   int32_t eq_kind;          /* 0: nonlinear equilibria of section 8;
-                               1: linear equilibria of section 7 */
+                               1: linear equilibria of section 7;
+                               2: the fluid D1Q3 scheme of sections 2-3
+                                  (isentropic pressure), g passive;
+                               3: the thermal D1Q3 advection-diffusion
+                                  scheme of section 4, f passive */
 } orc_params;
 
 /* Relaxation-rate coupling of section 7 (eq. lien-sigma-sigma) and the

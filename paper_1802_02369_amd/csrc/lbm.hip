@@ -57,14 +57,18 @@ int make_consts(const lbm_params* p, Consts* c) {
   if (!(std::isfinite(p->gamma) && p->gamma > 1.0))
     return set_err(LBM_EINVAL, "gamma must be finite and > 1");
   if (!std::isfinite(p->s0) || !std::isfinite(p->u0_lin) ||
-      !std::isfinite(p->s0_lin))
-    return set_err(LBM_EINVAL, "s0, u0_lin, s0_lin must be finite");
+      !std::isfinite(p->s0_lin) || !std::isfinite(p->alpha))
+    return set_err(LBM_EINVAL, "s0, u0_lin, s0_lin, alpha must be finite");
   if (!valid_rate(p->s_e) || !valid_rate(p->s_psi) || !valid_rate(p->s_eps))
     return set_err(LBM_EINVAL, "relaxation rates must lie in (0, 2)");
   if (p->source_on != 0 && p->source_on != 1)
     return set_err(LBM_EINVAL, "source_on must be 0 or 1");
-  if (p->eq_kind != 0 && p->eq_kind != 1)
-    return set_err(LBM_EINVAL, "eq_kind must be 0 or 1");
+  if (p->eq_kind < 0 || p->eq_kind > 3)
+    return set_err(LBM_EINVAL, "eq_kind must be 0, 1, 2 or 3");
+  if (p->eq_kind >= 2 && p->source_on)
+    return set_err(LBM_EINVAL, "the single-distribution schemes need source_on = 0");
+  if (p->eq_kind == 3 && !(p->alpha > -2.0 && p->alpha < 1.0))
+    return set_err(LBM_EINVAL, "alpha must lie in (-2, 1)");
   if (p->eq_kind == 1 && (p->lambda != 1.0 || p->cp != 1.0 || p->rho0 != 1.0))
     return set_err(LBM_EINVAL,
                    "linear equilibria are defined for lambda = cp = rho0 = 1");
@@ -112,6 +116,13 @@ int make_consts(const lbm_params* p, Consts* c) {
                 3.0 * s0 * c0 * c0 + 2.0 - 2.0 * s0 - 2.0 / g;
     c->lin[7] = 6.0 * u0 * s0;
     c->lin[8] = 3.0 * (u0 * u0 + s0 * c0 * c0);
+  } else if (p->eq_kind == 3) {
+    // Thermal scheme of section 4: its equilibria are linear in (rho, J,
+    // zeta), so it runs on the linear path.
+    c->eq_kind = 1;
+    c->lin[0] = 3.0 * p->c0 * p->c0 - 2.0 * l * l;
+    c->lin[5] = p->u0_lin;
+    c->lin[8] = p->alpha * l * l;
   }
   return LBM_OK;
 }

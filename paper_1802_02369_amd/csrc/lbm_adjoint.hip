@@ -70,6 +70,10 @@ __device__ __forceinline__ void node_forward(const Consts& c, double f0,
     q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
     q.psi_eq = q.zeta * q.u;
     q.eps_eq = c.eps_c * q.rho * q.X + q.e_eq * q.s;
+  } else if (c.eq_kind == 2) {
+    q.e_eq = 3.0 * (q.J * q.u + lbm::iso_pressure(c, q.rho)) - c.two_l2 * q.rho;
+    q.psi_eq = 0.0;
+    q.eps_eq = 0.0;
   } else {
     q.e_eq = c.lin[0] * q.rho + c.lin[1] * q.J + c.lin[2] * q.zeta;
     q.psi_eq = c.lin[3] * q.rho + c.lin[4] * q.J + c.lin[5] * q.zeta;
@@ -104,6 +108,11 @@ __device__ __forceinline__ void equilibria_adjoint(const Consts& c,
     rb -= c.two_l2 * eb;
     rb += c.r * q.T * pbar;
     Tb += q.rho * c.r * pbar;
+  } else if (c.eq_kind == 2) {
+    // e_eq = 3 (J u + p_iso) - 2 lambda^2 rho, d p_iso / d rho = gamma p_iso / rho
+    Jb += 3.0 * q.u * eb;
+    ub += 3.0 * q.J * eb;
+    rb += (3.0 * c.gamma * lbm::iso_pressure(c, q.rho) * ir - c.two_l2) * eb;
   } else {
     rb += c.lin[0] * eb + c.lin[3] * pb + c.lin[6] * xb;
     Jb += c.lin[1] * eb + c.lin[4] * pb + c.lin[7] * xb;

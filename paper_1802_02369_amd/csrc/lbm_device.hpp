@@ -34,9 +34,10 @@ struct Consts {
   double fa, fb, fc;  // M^-1 for f: 1/(3 rho0), 1/(3 rho0 lambda^2), 1/(2 rho0 lambda)
   double ga, gb, gc;  // M^-1 for g: same with rho0 cp
   double gamma, cp;
-  // linear equilibria (section 7): e = l[0] rho + l[1] J + l[2] zeta, etc.
+  // linear equilibria (section 7, and the thermal scheme of section 4):
+  // e = l[0] rho + l[1] J + l[2] zeta, psi = l[3..5] . W, eps = l[6..8] . W
   double lin[9];
-  int32_t eq_kind;
+  int32_t eq_kind;  // 0 section 8, 1 linear, 2 isentropic fluid D1Q3
   int32_t pad;
 };
 
@@ -70,6 +71,12 @@ __device__ __forceinline__ void thermo(const Consts& c, double rho, double J,
   T = c.T0 * exp(X);
 }
 
+// Isentropic pressure p0 (rho/rho0)^gamma = rho r T0 (rho/rho0)^(gamma-1)
+// of the fluid D1Q3 scheme (sections 2-3).
+__device__ __forceinline__ double iso_pressure(const Consts& c, double rho) {
+  return rho * c.r * c.T0 * exp(c.gm1 * log(rho * c.irho0));
+}
+
 // Steps (ii)-(vi) at one node, in place on the six populations: moments,
 // equilibria, relaxation, back to populations.  Returns u, T and the two
 // factors the source needs: rw = rho / T and w = 1 / T.
@@ -96,6 +103,10 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
     e_eq = 3.0 * (J * u + p) - c.two_l2 * rho;
     psi_eq = zeta * u;
     eps_eq = c.eps_c * rho * X + e_eq * s;
+  } else if (c.eq_kind == 2) {
+    e_eq = 3.0 * (J * u + iso_pressure(c, rho)) - c.two_l2 * rho;
+    psi_eq = 0.0;
+    eps_eq = 0.0;
   } else {
     e_eq = c.lin[0] * rho + c.lin[1] * J + c.lin[2] * zeta;
     psi_eq = c.lin[3] * rho + c.lin[4] * J + c.lin[5] * zeta;
@@ -151,6 +162,10 @@ __device__ __forceinline__ void equilibrium(const Consts& c, double rho,
     e_eq = 3.0 * (J * u + p) - c.two_l2 * rho;
     psi_eq = zeta * u;
     eps_eq = c.eps_c * rho * X + e_eq * s;
+  } else if (c.eq_kind == 2) {
+    e_eq = 3.0 * (J * u + iso_pressure(c, rho)) - c.two_l2 * rho;
+    psi_eq = 0.0;
+    eps_eq = 0.0;
   } else {
     e_eq = c.lin[0] * rho + c.lin[1] * J + c.lin[2] * zeta;
     psi_eq = c.lin[3] * rho + c.lin[4] * J + c.lin[5] * zeta;

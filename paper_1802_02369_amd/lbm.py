@@ -31,7 +31,7 @@ class LBMError(RuntimeError):
 class CParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in (
         "lam", "rho0", "cp", "gamma", "prandtl", "c0", "s0",
-        "s_e", "s_psi", "s_eps", "u0_lin", "s0_lin")] + [
+        "s_e", "s_psi", "s_eps", "u0_lin", "s0_lin", "alpha")] + [
         ("source_on", ctypes.c_int32), ("eq_kind", ctypes.c_int32)]
 
 
@@ -148,6 +148,7 @@ class Params:
     s_eps: float = 1.5
     u0_lin: float = 0.0
     s0_lin: float = 0.0
+    alpha: float = 0.0
     source_on: int = 1
     eq_kind: int = 0
 
@@ -157,8 +158,8 @@ class Params:
             s_psi = coupled_rates(self.s_e, self.gamma, self.prandtl)[0]
         return CParams(self.lam, self.rho0, self.cp, self.gamma, self.prandtl,
                        self.c0, self.s0, self.s_e, s_psi, self.s_eps,
-                       self.u0_lin, self.s0_lin, int(self.source_on),
-                       int(self.eq_kind))
+                       self.u0_lin, self.s0_lin, self.alpha,
+                       int(self.source_on), int(self.eq_kind))
 
 
 def _stream_ptr(stream=None) -> int:

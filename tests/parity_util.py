@@ -16,6 +16,9 @@ PARAM_SETS = {
                 s0=0.37, s_e=1.37, s_eps=1.1),
     "nosource": dict(s_e=1.6, source_on=0),
     "linear": dict(eq_kind=1, u0_lin=0.15, s0_lin=0.2, s_e=1.9),
+    "fluid": dict(eq_kind=2, source_on=0, s_e=1.7, c0=0.55),
+    "thermal": dict(eq_kind=3, source_on=0, u0_lin=0.2, alpha=-0.5, s_e=1.6,
+                    s_psi=1.3),
 }
 
 
@@ -33,7 +36,7 @@ def gpu_params(po: oracle.Params):
     return lbm.Params(lam=po.lam, rho0=po.rho0, cp=po.cp, gamma=po.gamma,
                       prandtl=po.prandtl, c0=po.c0, s0=po.s0, s_e=po.s_e,
                       s_psi=po.s_psi, s_eps=po.s_eps, u0_lin=po.u0_lin,
-                      s0_lin=po.s0_lin, source_on=po.source_on,
+                      s0_lin=po.s0_lin, alpha=po.alpha, source_on=po.source_on,
                       eq_kind=po.eq_kind)
 
 

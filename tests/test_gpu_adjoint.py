@@ -39,7 +39,8 @@ def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
-@pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear"])
+@pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear", "fluid",
+                                   "thermal"])
 @pytest.mark.parametrize("n", [3, 5, 64, 251, 252, 253, 256, 1000, 3001])
 def test_one_adjoint_step(pname, n):
     """fbar(t) and the rate partials of one step against the oracle's

@@ -52,7 +52,8 @@ def make_lattice(n, po, tuning="p2k8w4"):
     return lat
 
 
-@pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear"])
+@pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear", "fluid",
+                                   "thermal"])
 def test_equilibrium_and_moments(pname):
     rng = np.random.default_rng(100)
     po = oracle_params(pname)
@@ -71,7 +72,7 @@ def test_equilibrium_and_moments(pname):
 @pytest.mark.parametrize("n", [3, 4, 5, 63, 64, 65, 255, 257, 1000, 4099, 20011])
 def test_one_step(tuning, n):
     rng = np.random.default_rng(n)
-    for pname in ("paper", "odd", "nosource", "linear"):
+    for pname in ("paper", "odd", "nosource", "linear", "fluid", "thermal"):
         po = oracle_params(pname)
         f0 = random_state(rng, n, po)
         say(f"one step {tuning} n={n} {pname}")
@@ -193,3 +194,31 @@ def test_diagnostics_and_nonfinite_detection():
     f[0, 5] = -1.0  # rho <= 0 at node 5
     d = lat.diagnostics(f)
     assert d[7] >= 1
+
+
+@pytest.mark.parametrize("n", [40, 160])
+def test_source_switch_energy_and_entropy(n):
+    """Strong wave delta rho = 0.1 rho0, T_max = 3, nu = 6.579e-4 (section 9)
+    on the GPU with and without the source term: sum rho E and sum zeta from
+    lbm_diagnostics track the oracle's, entropy is constant without the
+    source and produced with it, and the energy defect is much smaller with
+    the source."""
+    dx = 1.0 / n
+    s_e = oracle.rate_from_viscosity(6.579e-4, 1.0, dx)
+    j = np.arange(n)
+    rho = 1 + 0.1 * np.sin(2 * np.pi * j / n)
+    J = rho * 0.5 * (rho - 1)
+    res = {}
+    for src in (0, 1):
+        po = oracle_params("paper", s_e=s_e, source_on=src)
+        lat = lbm().Lattice(n, gpu_params(po))
+        f = lat.equilibrium(*to_dev(rho, J, np.zeros(n)))
+        d0 = lat.diagnostics(f)
+        lat.step(f, 3 * n)
+        d1 = lat.diagnostics(f)
+        g = oracle.run(oracle.init(rho, J, np.zeros(n), po), 3 * n, po)
+        dw = oracle.diagnostics(g, po)
+        np.testing.assert_allclose(d1[:4], dw[:4], rtol=1e-11, atol=1e-13)
+        res[src] = ((d1[3] - d0[3]) / d0[3], d1[2] - d0[2])
+    assert abs(res[0][1]) < 1e-12 and res[1][1] > 1e-3
+    assert abs(res[1][0]) < 0.25 * abs(res[0][0])

@@ -463,3 +463,135 @@ def test_gradient_matches_directional_and_finite_differences(ckpt):
 
     fd = (loss_at(1) - loss_at(-1)) / (2 * h)
     assert fd == pytest.approx(dL, rel=1e-6)
+
+
+# ------------------------------------------- claims of sections 7 and 9 ---
+
+@pytest.mark.parametrize("u0,s0", [(0.0, 0.0), (0.15, 0.2)])
+def test_linear_equilibria_stable_as_section7_reports(u0, s0):
+    """Section 7 reports numerical stability of the scheme with the linear
+    equilibria of eq. equilibres-NS-linearise for gamma = 1.4, Pr = 1,
+    c0 = lambda/2, s_e = 1.9 (nu = 6.579e-4, dx = 1/40) and also for
+    u0 = 0.15 lambda, s0 = 0.2 cp.  Every Fourier mode of the 40-node lattice
+    must have all eigenvalues of its amplification matrix inside the unit
+    circle, and the reference state must be a fixed point."""
+    g = printed()["linear_wave_run"]
+    s_e = oracle.rate_from_viscosity(g["nu"], 1.0, g["dx"])
+    p = oracle.Params(eq_kind=1, u0_lin=u0, s0_lin=s0, s0=s0, s_e=s_e,
+                      source_on=0, gamma=g["gamma"], prandtl=g["prandtl"])
+    n = int(round(1 / g["dx"]))
+    base = oracle.init(np.ones(n), np.full(n, u0), np.full(n, s0), p)
+    np.testing.assert_allclose(oracle.step(base, p), base, atol=1e-15)
+    j = np.arange(n)
+    zmax = 0.0
+    for m in range(n):
+        ph = np.exp(2j * np.pi * m * j / n)
+        G = np.zeros((6, 6), complex)
+        for c in range(6):
+            dr, di = np.zeros((6, n)), np.zeros((6, n))
+            dr[c], di[c] = ph.real, ph.imag
+            _, a = oracle.step_tlm(base, dr, np.zeros(3), p)
+            _, b = oracle.step_tlm(base, di, np.zeros(3), p)
+            G[:, c] = ((a + 1j * b) * ph.conj()).sum(axis=1) / n
+        zmax = max(zmax, np.abs(np.linalg.eigvals(G)).max())
+    assert zmax <= 1 + 1e-12
+    # a perturbed run over T_f = 120 steps stays bounded
+    rng = np.random.default_rng(12)
+    f = base * (1 + 1e-3 * rng.uniform(-1, 1, base.shape))
+    d0 = np.abs(f - base).max()
+    f = oracle.run(f, g["T_f_steps"], p)
+    assert np.abs(f - base).max() <= 2 * d0
+
+
+@pytest.mark.parametrize("dx", [1 / 40, 1 / 80, 1 / 160])
+def test_source_term_energy_and_entropy_as_section9_reports(dx):
+    """Section 9 (Fig. 4 text), strong wave delta rho = 0.1 rho0 on the three
+    meshes, T_max = 3, nu = 6.579e-4: without the source term the specific
+    entropy is quasi constant and total energy is not conserved; with it the
+    energy defect is very small and entropy is produced."""
+    g = printed()["experiments"]
+    n = int(round(1 / dx))
+    steps = int(round(g["T_max"] / dx))
+    s_e = oracle.rate_from_viscosity(g["nu"], 1.0, dx)
+    j = np.arange(n)
+    rho = 1 + 0.1 * np.sin(2 * np.pi * j / n)
+    u = g["c0_over_lambda"] * (rho - 1)
+    out = {}
+    for src in (0, 1):
+        p = oracle.Params(s_e=s_e, source_on=src, dx=dx)
+        f = oracle.init(rho, rho * u, np.zeros(n), p)
+        d0 = oracle.diagnostics(f, p)
+        d1 = oracle.diagnostics(oracle.run(f, steps, p), p)
+        out[src] = ((d1[3] - d0[3]) / d0[3], d1[2] - d0[2])
+    (dE0, dz0), (dE1, dz1) = out[0], out[1]
+    assert abs(dz0) < 1e-12                  # entropy constant without source
+    assert dz1 > 1e-3                        # produced with it
+    assert abs(dE1) < 0.25 * abs(dE0)        # energy defect much smaller
+    assert dE0 < 0                           # kinetic energy lost to nowhere
+
+
+# --------------------------------- single-distribution schemes (2-4) ---
+
+def _mode_eigs(p, n=256, m=1, base=None):
+    if base is None:
+        base = oracle.init(np.full(n, p.rho0), np.zeros(n), np.zeros(n), p)
+    j = np.arange(n)
+    ph = np.exp(2j * np.pi * m * j / n)
+    G = np.zeros((6, 6), complex)
+    for c in range(6):
+        dr, di = np.zeros((6, n)), np.zeros((6, n))
+        dr[c], di[c] = ph.real, ph.imag
+        _, a = oracle.step_tlm(base, dr, np.zeros(3), p)
+        _, b = oracle.step_tlm(base, di, np.zeros(3), p)
+        G[:, c] = ((a + 1j * b) * ph.conj()).sum(axis=1) / n
+    return G
+
+
+@pytest.mark.parametrize("c0,s_e", [(0.5, 1.9), (0.4, 1.5)])
+def test_fluid_d1q3_scheme(c0, s_e):
+    """Sections 2-3: the fluid D1Q3 with e_eq of eq. energie-equilibre and the
+    isentropic pressure: first-order flux = isentropic Euler flux; sound
+    speed c0 and damping (k^2/2) nu (1 - c0^2/lambda^2) from eq. edp-d1q3
+    with the exact theta_e = 3 (lambda^2 - c0^2) d_x J at rest."""
+    p = oracle.Params(eq_kind=2, source_on=0, c0=c0, s_e=s_e, s_psi=1.2)
+    rng = np.random.default_rng(21)
+    rho = rng.uniform(0.6, 1.6, 40)
+    u = rng.uniform(-0.3, 0.3, 40)
+    e_eq = oracle.equilibria(rho, rho * u, 0 * rho, p)[0]
+    p_iso = p.rho0 * c0**2 / p.gamma * rho**p.gamma
+    np.testing.assert_allclose(2 / 3 * rho + e_eq / 3, rho * u**2 + p_iso, rtol=1e-13)
+    n = 256
+    z = np.linalg.eigvals(_mode_eigs(p, n))
+    kap = 2 * np.pi / n
+    ac = [w for w in z if abs(np.angle(w)) > 0.5 * c0 * kap and abs(w) > 0.99]
+    assert len(ac) == 2
+    sig = 1 / s_e - 0.5
+    for w in ac:
+        np.testing.assert_allclose(abs(np.angle(w)) / kap, c0, rtol=1e-4)
+        np.testing.assert_allclose(-np.log(abs(w)), kap**2 / 2 * sig * (1 - c0**2),
+                                   rtol=1e-3)
+
+
+@pytest.mark.parametrize("u0,alpha,s_psi", [(0.0, 0.0, 1.5), (0.1, -1.0, 1.2),
+                                            (0.3, 0.5, 1.8)])
+def test_thermal_d1q3_scheme(u0, alpha, s_psi):
+    """Section 4: advection-diffusion with psi_eq = u0 zeta and eps_eq =
+    alpha lambda^2 zeta; a Fourier mode of zeta moves at u0 and decays at
+    kappa k^2 with the printed identification
+    kappa = ((2 + alpha)/3 lambda^2 - u0^2) (1/s_psi - 1/2) dt."""
+    p = oracle.Params(eq_kind=3, source_on=0, u0_lin=u0, alpha=alpha,
+                      s_psi=s_psi, s_e=1.5)
+    n = 256
+    G = _mode_eigs(p, n)
+    z = np.linalg.eigvals(G[3:, 3:])  # the g block (f is passive)
+    kap = 2 * np.pi / n
+    w = z[np.argmax(np.abs(z))]
+    kappa = ((2 + alpha) / 3 - u0**2) * (1 / s_psi - 0.5)
+    np.testing.assert_allclose(-np.angle(w) / kap, u0, rtol=2e-4, atol=1e-9)
+    np.testing.assert_allclose(-np.log(abs(w)), kappa * kap**2, rtol=2e-3)
+    # the f distribution does not feed the g distribution
+    np.testing.assert_allclose(G[3:, :3], 0, atol=1e-15)
+    # stability constraint of section 4
+    with pytest.raises(ValueError):
+        oracle.step(oracle.init(np.ones(5), np.zeros(5), np.zeros(5), p),
+                    oracle.Params(eq_kind=3, source_on=0, alpha=1.2))
