@@ -59,13 +59,12 @@ COUNTERS = os.path.join(ROOT, "profiles", "counters_n16M.json")
 
 
 def source_hash() -> str:
-    """Hash of the HIP sources; counter figures taken from other sources are
-    not reported as this kernel's traffic."""
-    import glob
+    """Hash of the sources of the blocked forward kernel; counter figures
+    taken from other sources are not reported as this kernel's traffic."""
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1802_02369_amd", "csrc", "*"))):
-        with open(p, "rb") as fh:
+    for f in counter_record().get("source_files", []):
+        with open(os.path.join(ROOT, "paper_1802_02369_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

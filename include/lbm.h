@@ -221,6 +221,13 @@ int lbm_equilibrium_adjoint(lbm_handle* h, const double* rho, const double* J,
 /* Reverse of lbm_moments: fbar = M^T mbar (device, 6*n each). */
 int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
                         void* ws, size_t ws_bytes);
+/* Kernel of the reverse sweep: LBM_KERNEL_PLAIN (default, AUTO) runs one
+ * reverse step per launch, one node per thread (HBM-bound, 144 B per
+ * node-step); LBM_KERNEL_BLOCKED keeps dL/df in registers for K reverse steps
+ * of a forward-shaped tile (reads only the recomputed states, but needs about
+ * 2.5x the arithmetic of a forward step per node).  Takes effect at the next
+ * lbm_forward_ckpt. */
+int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
 
 /* ------------------------------------------------- batches of lattices */
 
@@ -290,6 +297,7 @@ int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
                                   size_t ws_bytes);
 int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
                               void* ws, size_t ws_bytes);
+int lbm_batch_set_adjoint_kernel(lbm_batch* b, int kernel);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@
 #include "../../include/lbm.h"
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
+#include "lbm_tile.hpp"
 
 using lbm::Consts;
 
@@ -223,75 +224,6 @@ __global__ __launch_bounds__(kPlainBlock) void k_step_plain(
 // OUT = 64*P*WG - 4K and loads nodes [t*OUT - 2K, t*OUT + OUT + 2K)
 // (periodic).
 //
-// Global memory is touched only at the start and the end of the launch, and
-// always coalesced: node i of a wavefront's segment travels through that
-// wavefront's LDS buffer between the coalesced order (lane l handles
-// i = k*64 + l) and the register order (lane l owns i = l*P + k).  The LDS
-// index i + i/P pads one double per lane row so that both orders are free of
-// bank conflicts.  Staging is private to a wavefront (wave_barrier only).
-template <int P>
-__device__ __forceinline__ int lds_idx(int i) {
-  return i + i / P;
-}
-
-__device__ __forceinline__ int64_t wrap_near(int64_t x, int64_t n, bool small) {
-  if (small) return lbm::wrap_mod(x, n);
-  return x < 0 ? x + n : (x >= n ? x - n : x);
-}
-
-// Arrays of a lattice of length L are at fin + q*S (S >= L, the array
-// stride of the state the lattice lives in).
-template <int P>
-__device__ __forceinline__ void tile_load(const double* __restrict__ fin,
-                                          int64_t S, int64_t n, int64_t start,
-                                          bool inside, bool small, int lane,
-                                          double* lds, double (&f)[6][P]) {
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    const double* src = fin + (int64_t)q * S;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      const int i = k * 64 + lane;
-      const int64_t g = inside ? start + i : wrap_near(start + i, n, small);
-      lds[lds_idx<P>(i)] = src[g];
-    }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int k = 0; k < P; ++k) f[q][k] = lds[lds_idx<P>(lane * P + k)];
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-// Stores the nodes of this wavefront's segment whose tile index lies in
-// [lo, hi) and whose global index is below n.
-template <int P>
-__device__ __forceinline__ void tile_store(double* __restrict__ fout,
-                                           int64_t S, int64_t n, int64_t start,
-                                           int lo, int hi, int lane, double* lds,
-                                           const double (&f)[6][P]) {
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-#pragma unroll
-    for (int k = 0; k < P; ++k) lds[lds_idx<P>(lane * P + k)] = f[q][k];
-    __builtin_amdgcn_wave_barrier();
-    double* dst = fout + (int64_t)q * S;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      const int i = k * 64 + lane;
-      const int64_t g = start + i;
-      if (i >= lo && i < hi && g < n) dst[g] = lds[lds_idx<P>(i)];
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-// Values exchanged between neighbouring wavefronts of a workgroup each step:
-// [0..1] u, T of the last node of the wavefront, [2..3] u, T of its first
-// node, [4..5] f+*, g+* of its last node, [6..7] f-*, g-* of its first node.
-struct Boundary {
-  double v[8];
-};
-
 // One time step of a register tile.  The source of node k needs u, T of k-1
 // and k+1, so the collisions run in the order P-1, 0, 1, ..., P-2 and each
 // source is applied as soon as its right neighbour exists; only a window of
@@ -404,12 +336,15 @@ __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
 // Tile t of a lattice of n nodes (array stride S) starting at lattice index
 // `start` = t*OUT - H, OUT = W - 2H: load, K <= H/2 steps, store of the
 // interior [H, W - H) (one step has radius 2, so K steps need H >= 2K).
+// With every_step, the interior is stored after each step s = 1..K into the
+// state fout + (s-1)*state_stride (the states a reverse sweep needs).
 template <int P, int WG>
 __device__ __forceinline__ void tile_run(const Consts& c,
                                          const double* __restrict__ fin,
                                          double* __restrict__ fout, int64_t S,
                                          int64_t n, int64_t start, int H,
-                                         int K) {
+                                         int K, bool every_step = false,
+                                         int64_t state_stride = 0) {
   constexpr int WW = 64 * P;
   constexpr int W = WG * WW;
   __shared__ double stage[WG * (WW + 64)];
@@ -422,10 +357,15 @@ __device__ __forceinline__ void tile_run(const Consts& c,
   const bool small = n < W;
   double f[6][P];
   tile_load<P>(fin, S, n, wstart, inside, small, lane, lds, f);
-  for (int step = 0; step < K; ++step) tile_step<P, WG>(c, f, bnd, lane, wave);
   // tile indices [H, W - H) are valid; in this wavefront's numbering:
-  tile_store<P>(fout, S, n, wstart, H - wave * WW, W - H - wave * WW, lane,
-                lds, f);
+  const int lo = H - wave * WW, hi = W - H - wave * WW;
+  for (int step = 0; step < K; ++step) {
+    tile_step<P, WG>(c, f, bnd, lane, wave);
+    if (every_step)
+      tile_store<P>(fout + step * state_stride, S, n, wstart, lo, hi, lane,
+                    lds, f);
+  }
+  if (!every_step) tile_store<P>(fout, S, n, wstart, lo, hi, lane, lds, f);
 }
 
 template <int P, int WG>
@@ -442,11 +382,14 @@ __global__ __launch_bounds__(64 * WG) void k_step_tile(
 // which occupies [offs[inst], offs[inst+1]) of every array of a state of
 // array stride S, with that lattice's own constants.  The tiling (halo H,
 // OUT = W - 2H) is fixed by the tile table; a launch runs K <= H/2 steps.
+// state_stride > 0: store the state after every step, step s into
+// fout + (s-1)*state_stride.
 template <int P, int WG>
 __global__ __launch_bounds__(64 * WG) void k_batch_tile(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const lbm::TileRef* __restrict__ tiles, const double* __restrict__ fin,
-    double* __restrict__ fout, int64_t S, int H, int K, int64_t ntiles) {
+    double* __restrict__ fout, int64_t S, int H, int K, int64_t ntiles,
+    int64_t state_stride) {
   const int64_t b = blockIdx.x;
   if (b >= ntiles) return;  // uniform over the workgroup
   const lbm::TileRef tr = tiles[b];
@@ -455,7 +398,7 @@ __global__ __launch_bounds__(64 * WG) void k_batch_tile(
   const Consts c = cs[tr.inst];
   const int OUT = 64 * P * WG - 2 * H;
   tile_run<P, WG>(c, fin + off, fout + off, S, n, (int64_t)tr.t * OUT - H, H,
-                  K);
+                  K, state_stride > 0, state_stride);
 }
 
 // One workgroup per lattice of a batch: moments m = M f (eq. M-d1q3q3).
@@ -672,22 +615,23 @@ template <int P, int WG>
 static void launch_batch_t(const Consts* cs, const int64_t* offs,
                            const TileRef* tiles, int64_t ntiles,
                            const double* fin, double* fout, int64_t S, int H,
-                           int K, hipStream_t s) {
+                           int K, int64_t state_stride, hipStream_t s) {
   hipLaunchKernelGGL((k_batch_tile<P, WG>), dim3((unsigned)ntiles),
                      dim3(64 * WG), 0, s, cs, offs, tiles, fin, fout, S, H, K,
-                     ntiles);
+                     ntiles, state_stride);
 }
 
 int launch_batch_tile(const Consts* cs, const int64_t* offs,
                       const TileRef* tiles, int64_t ntiles, const double* fin,
                       double* fout, int64_t S, int P, int H, int K, int wg,
-                      hipStream_t s) {
+                      hipStream_t s, int64_t state_stride) {
   if (ntiles <= 0) return LBM_OK;
   if (K < 1 || 2 * K > H || 2 * H >= 64 * P * wg)
     return set_err(LBM_EINVAL, "bad batched tile geometry H=%d K=%d", H, K);
 #define LBM_BATCH_CASE(PP, WW)                                              \
   if (P == PP && wg == WW) {                                                \
-    launch_batch_t<PP, WW>(cs, offs, tiles, ntiles, fin, fout, S, H, K, s); \
+    launch_batch_t<PP, WW>(cs, offs, tiles, ntiles, fin, fout, S, H, K,    \
+                           state_stride, s);                                \
     return hip_check(hipGetLastError(), "k_batch_tile");                    \
   }
   LBM_BATCH_CASE(2, 1)

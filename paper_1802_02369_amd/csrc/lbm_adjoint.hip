@@ -31,6 +31,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_internal.hpp"
+#include "lbm_tile.hpp"
 
 using lbm::Consts;
 using lbm::TileRef;
@@ -220,6 +221,286 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
   if (t < 3) rslots[3 * b + t] += red[t][0];
 }
 
+// ------------------------------------------------ register-tile adjoint --
+//
+// K reverse steps of a tile of 64*P*WG nodes per launch (the forward tile
+// shape, halo H = 2K on each side).  fbar stays in registers; each step reads
+// the forward state f(t) of the tile (coalesced, through LDS) and does:
+//   A  u, T (and rho, s, X) of every node from f(t);
+//   -  streamed adjoint: fbar*_+(k) = fbar_+(k+1), fbar*_-(k) = fbar_-(k-1),
+//      with u, T of the outside neighbours (DPP, LDS between wavefronts);
+//   B  each node's source adjoint zbar and the terms it sends its neighbours,
+//      A_k = 2 c rho w du zbar and B_k = 2 c (cp/Pr) rho w^2 dT zbar;
+//   C  the gather of A, B from both neighbours and the node-local chain.
+// Rate partials are summed over the tile's output nodes [H, W - H) only (the
+// output regions of the tiles partition each lattice).
+template <int P>
+__device__ __forceinline__ void shift_left(double (&a)[P], double in_right) {
+#pragma unroll
+  for (int k = 0; k < P - 1; ++k) a[k] = a[k + 1];
+  a[P - 1] = in_right;
+}
+template <int P>
+__device__ __forceinline__ void shift_right(double (&a)[P], double in_left) {
+#pragma unroll
+  for (int k = P - 1; k > 0; --k) a[k] = a[k - 1];
+  a[0] = in_left;
+}
+
+template <int P, int WG>
+__device__ __forceinline__ void adjoint_tile_step(
+    const Consts& c, const double (&ft)[6][P], double (&fb)[6][P],
+    Boundary* bnd, double (*bab)[4], int lane, int wave, const bool (&own)[P],
+    double& r0, double& r1, double& r2) {
+  // A: forward quantities of each node
+  double rho[P], u[P], s[P], X[P], T[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    rho[k] = lbm::density(c, ft[0][k], ft[1][k], ft[2][k]);
+    const double J = c.mJ * (ft[1][k] - ft[2][k]);
+    const double zeta = c.mz * (ft[3][k] + (ft[4][k] + ft[5][k]));
+    lbm::thermo(c, rho[k], J, zeta, u[k], s[k], X[k], T[k]);
+  }
+  if (WG > 1) {
+    if (lane == 0) {
+      bnd[wave].v[0] = fb[1][0];
+      bnd[wave].v[1] = fb[4][0];
+      bnd[wave].v[2] = u[0];
+      bnd[wave].v[3] = T[0];
+    }
+    if (lane == 63) {
+      bnd[wave].v[4] = fb[2][P - 1];
+      bnd[wave].v[5] = fb[5][P - 1];
+      bnd[wave].v[6] = u[P - 1];
+      bnd[wave].v[7] = T[P - 1];
+    }
+    __syncthreads();
+  }
+  double fpR = lbm::from_right(fb[1][0]), gpR = lbm::from_right(fb[4][0]);
+  double fmL = lbm::from_left(fb[2][P - 1]), gmL = lbm::from_left(fb[5][P - 1]);
+  double uL = lbm::from_left(u[P - 1]), TL = lbm::from_left(T[P - 1]);
+  double uR = lbm::from_right(u[0]), TR = lbm::from_right(T[0]);
+  if (WG > 1) {
+    if (lane == 63 && wave < WG - 1) {
+      fpR = bnd[wave + 1].v[0];
+      gpR = bnd[wave + 1].v[1];
+      uR = bnd[wave + 1].v[2];
+      TR = bnd[wave + 1].v[3];
+    }
+    if (lane == 0 && wave > 0) {
+      fmL = bnd[wave - 1].v[4];
+      gmL = bnd[wave - 1].v[5];
+      uL = bnd[wave - 1].v[6];
+      TL = bnd[wave - 1].v[7];
+    }
+  }
+  // streamed adjoint (transpose of (viii)): fb now holds fbar*
+  shift_left<P>(fb[1], fpR);
+  shift_left<P>(fb[4], gpR);
+  shift_right<P>(fb[2], fmL);
+  shift_right<P>(fb[5], gmL);
+  // B: source adjoint and what each node sends to its neighbours
+  double A[P], B[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const double ul = k == 0 ? uL : u[k - 1], ur = k == P - 1 ? uR : u[k + 1];
+    const double tl = k == 0 ? TL : T[k - 1], tr = k == P - 1 ? TR : T[k + 1];
+    const double w = 1.0 / T[k];
+    const double Zb = c.ga * (fb[3][k] + fb[4][k] + fb[5][k]);
+    A[k] = 2.0 * c.src_c * rho[k] * w * (ur - ul) * Zb;
+    B[k] = 2.0 * c.src_c * c.cPr * rho[k] * w * w * (tr - tl) * Zb;
+  }
+  if (WG > 1) {
+    if (lane == 0) {
+      bab[wave][0] = A[0];
+      bab[wave][1] = B[0];
+    }
+    if (lane == 63) {
+      bab[wave][2] = A[P - 1];
+      bab[wave][3] = B[P - 1];
+    }
+    __syncthreads();
+  }
+  double AL = lbm::from_left(A[P - 1]), BL = lbm::from_left(B[P - 1]);
+  double AR = lbm::from_right(A[0]), BR = lbm::from_right(B[0]);
+  if (WG > 1) {
+    if (lane == 0 && wave > 0) {
+      AL = bab[wave - 1][2];
+      BL = bab[wave - 1][3];
+    }
+    if (lane == 63 && wave < WG - 1) {
+      AR = bab[wave + 1][0];
+      BR = bab[wave + 1][1];
+    }
+  }
+  // C: gather and node-local reverse chain
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    __builtin_amdgcn_sched_barrier(0);
+    const double ul = k == 0 ? uL : u[k - 1], ur = k == P - 1 ? uR : u[k + 1];
+    const double tl = k == 0 ? TL : T[k - 1], tr = k == P - 1 ? TR : T[k + 1];
+    const double al = k == 0 ? AL : A[k - 1], ar = k == P - 1 ? AR : A[k + 1];
+    const double bl = k == 0 ? BL : B[k - 1], br = k == P - 1 ? BR : B[k + 1];
+    NodeFwd q;
+    q.rho = rho[k];
+    q.J = c.mJ * (ft[1][k] - ft[2][k]);
+    q.e = c.me * ((ft[1][k] + ft[2][k]) - 2.0 * ft[0][k]);
+    q.zeta = c.mz * (ft[3][k] + (ft[4][k] + ft[5][k]));
+    q.psi = c.mpsi * (ft[4][k] - ft[5][k]);
+    q.eps = c.meps * ((ft[4][k] + ft[5][k]) - 2.0 * ft[3][k]);
+    q.u = u[k];
+    q.s = s[k];
+    q.X = X[k];
+    q.T = T[k];
+    q.w = 1.0 / T[k];
+    if (c.eq_kind == 0) {
+      const double p = q.rho * c.r * q.T;
+      q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
+      q.psi_eq = q.zeta * q.u;
+      q.eps_eq = c.eps_c * q.rho * q.X + q.e_eq * q.s;
+    } else if (c.eq_kind == 2) {
+      q.e_eq = 3.0 * (q.J * q.u + lbm::iso_pressure(c, q.rho)) - c.two_l2 * q.rho;
+      q.psi_eq = 0.0;
+      q.eps_eq = 0.0;
+    } else {
+      q.e_eq = c.lin[0] * q.rho + c.lin[1] * q.J + c.lin[2] * q.zeta;
+      q.psi_eq = c.lin[3] * q.rho + c.lin[4] * q.J + c.lin[5] * q.zeta;
+      q.eps_eq = c.lin[6] * q.rho + c.lin[7] * q.J + c.lin[8] * q.zeta;
+    }
+    const double a0 = fb[0][k], ap = fb[1][k], am = fb[2][k];
+    const double b0 = fb[3][k], bp = fb[4][k], bm = fb[5][k];
+    const double du = ur - ul, dT = tr - tl;
+    const double Q = du * du + c.cPr * dT * dT * q.w;
+    const double Zb = c.ga * (b0 + bp + bm);
+    double ub = al - ar;
+    double Tb = bl - br - Zb * c.src_c * q.rho * q.w * q.w *
+                              (du * du + 2.0 * c.cPr * dT * dT * q.w);
+    double rb = Zb * c.src_c * q.w * Q;
+    double dr0 = 0.0;
+    if (c.src_c != 0.0) dr0 -= Zb * 0.25 * q.rho * q.w * Q / (c.s_e * c.s_e);
+    rb += c.fa * (a0 + ap + am);
+    double Jb = c.fc * (ap - am);
+    const double esb = c.fb * (0.5 * (ap + am) - a0);
+    double zb = Zb;
+    const double psisb = c.gc * (bp - bm);
+    const double epssb = c.gb * (0.5 * (bp + bm) - b0);
+    const double eb = (1.0 - c.s_e) * esb;
+    const double psib = (1.0 - c.s_psi) * psisb;
+    const double epsb = (1.0 - c.s_eps) * epssb;
+    if (own[k]) {
+      r0 += dr0 + (q.e_eq - q.e) * esb;
+      r1 += (q.psi_eq - q.psi) * psisb;
+      r2 += (q.eps_eq - q.eps) * epssb;
+    }
+    equilibria_adjoint(c, q, c.s_e * esb, c.s_psi * psisb, c.s_eps * epssb,
+                       ub, Tb, rb, Jb, zb);
+    fb[0][k] = c.rho0 * rb - 2.0 * c.me * eb;
+    fb[1][k] = c.rho0 * rb + c.mJ * Jb + c.me * eb;
+    fb[2][k] = c.rho0 * rb - c.mJ * Jb + c.me * eb;
+    fb[3][k] = c.mz * zb - 2.0 * c.meps * epsb;
+    fb[4][k] = c.mz * zb + c.mpsi * psib + c.meps * epsb;
+    fb[5][k] = c.mz * zb - c.mpsi * psib + c.meps * epsb;
+  }
+}
+
+// Reverse steps i_hi-1 down to i_lo of a checkpoint segment; the forward
+// state of step i is ck (i = 0) or seg + (i-1)*SD.
+template <int P, int WG>
+__global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const TileRef* __restrict__ tiles, int64_t ntiles,
+    const double* __restrict__ ck, const double* __restrict__ seg, int64_t SD,
+    int i_lo, int i_hi, const double* __restrict__ fbn,
+    double* __restrict__ fbo, int64_t S, int H, double* __restrict__ rslots) {
+  constexpr int WW = 64 * P;
+  constexpr int W = WG * WW;
+  __shared__ double stage[WG * (WW + 64)];
+  __shared__ Boundary bnd[WG];
+  __shared__ double bab[WG][4];
+  __shared__ double red[3][64 * WG];
+  const int64_t b = blockIdx.x;
+  if (b >= ntiles) return;  // uniform over the workgroup
+  const TileRef tr = tiles[b];
+  const int64_t off = offs[tr.inst];
+  const int64_t n = offs[tr.inst + 1] - off;
+  const Consts c = cs[tr.inst];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double* lds = stage + wave * (WW + 64);
+  const int OUT = W - 2 * H;
+  const int64_t start = (int64_t)tr.t * OUT - H;
+  const int64_t wstart = start + wave * WW;
+  const bool inside = start >= 0 && start + W <= n;
+  const bool small = n < W;
+  bool own[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int it = wave * WW + lane * P + k;
+    own[k] = it >= H && it < W - H && start + it < n;
+  }
+  double fb[6][P];
+  tile_load<P>(fbn + off, S, n, wstart, inside, small, lane, lds, fb);
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  for (int i = i_hi - 1; i >= i_lo; --i) {
+    const double* st = (i == 0 ? ck : seg + (int64_t)(i - 1) * SD) + off;
+    double ft[6][P];
+    tile_load<P>(st, S, n, wstart, inside, small, lane, lds, ft);
+    adjoint_tile_step<P, WG>(c, ft, fb, bnd, bab, lane, wave, own, r0, r1, r2);
+  }
+  tile_store<P>(fbo + off, S, n, wstart, H - wave * WW, W - H - wave * WW,
+                lane, lds, fb);
+  const int t = threadIdx.x;
+  red[0][t] = r0;
+  red[1][t] = r1;
+  red[2][t] = r2;
+  __syncthreads();
+  for (int w = 32 * WG; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] += red[0][t + w];
+      red[1][t] += red[1][t + w];
+      red[2][t] += red[2][t + w];
+    }
+    __syncthreads();
+  }
+  if (t < 3) rslots[3 * b + t] += red[t][0];
+}
+
+template <int P, int WG>
+void launch_adjoint_tile_t(const Consts* cs, const int64_t* offs,
+                           const TileRef* tiles, int64_t ntiles,
+                           const double* ck, const double* seg, int64_t SD,
+                           int i_lo, int i_hi, const double* fbn, double* fbo,
+                           int64_t S, int H, double* rslots, hipStream_t s) {
+  hipLaunchKernelGGL((k_adjoint_tile<P, WG>), dim3((unsigned)ntiles),
+                     dim3(64 * WG), 0, s, cs, offs, tiles, ntiles, ck, seg, SD,
+                     i_lo, i_hi, fbn, fbo, S, H, rslots);
+}
+
+int launch_adjoint_tile(int P, int WG, const Consts* cs, const int64_t* offs,
+                        const TileRef* tiles, int64_t ntiles, const double* ck,
+                        const double* seg, int64_t SD, int i_lo, int i_hi,
+                        const double* fbn, double* fbo, int64_t S, int H,
+                        double* rslots, hipStream_t s) {
+  if (i_hi - i_lo < 1 || 2 * (i_hi - i_lo) > H || 2 * H >= 64 * P * WG)
+    return set_err(LBM_EINVAL, "bad adjoint tile geometry");
+#define LBM_ADJ_CASE(PP, WW)                                                  \
+  if (P == PP && WG == WW) {                                                  \
+    launch_adjoint_tile_t<PP, WW>(cs, offs, tiles, ntiles, ck, seg, SD, i_lo, \
+                                  i_hi, fbn, fbo, S, H, rslots, s);           \
+    return hip_check(hipGetLastError(), "k_adjoint_tile");                    \
+  }
+  LBM_ADJ_CASE(2, 1)
+  LBM_ADJ_CASE(2, 2)
+  LBM_ADJ_CASE(2, 4)
+  LBM_ADJ_CASE(2, 8)
+  LBM_ADJ_CASE(4, 1)
+  LBM_ADJ_CASE(4, 2)
+  LBM_ADJ_CASE(4, 4)
+  LBM_ADJ_CASE(4, 8)
+#undef LBM_ADJ_CASE
+  return set_err(LBM_EINVAL, "unsupported adjoint tile shape P=%d waves=%d", P, WG);
+}
+
 // fbar of the equilibrium initialisation -> adjoints of rho, J, zeta.
 __global__ __launch_bounds__(256) void k_equilibrium_adjoint(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
@@ -331,15 +612,12 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct AdjLayout {
   int64_t n_fwd, n_rec, n_adj, n_ck, n_seg;
-  size_t consts, offs, fwd_tiles, rec_tiles, adj_tiles, adj_first, rslots,
-      scratch, pp, ckpt, seg, total;
+  size_t consts, offs, fwd_tiles, rec_tiles, adj_tiles, adj_first, rec_first,
+      rslots, scratch, pp, ckpt, seg, total;
 };
 
-lbm_tuning rec_tuning(const lbm_tuning& t) {
-  lbm_tuning r = t;
-  r.steps_per_launch = 1;
-  return r;
-}
+// The recompute runs with the forward tile shape and stores every step.
+lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
 
 int64_t adj_tile_count(const lbm_batch* b) {
   int64_t s = 0;
@@ -369,8 +647,11 @@ AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C) {
   o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_adj));
   L.adj_first = o;
   o = align256(o + sizeof(int64_t) * (b->n_inst + 1));
+  L.rec_first = o;
+  o = align256(o + sizeof(int64_t) * (b->n_inst + 1));
   L.rslots = o;
-  o = align256(o + sizeof(double) * 3 * std::max<int64_t>(1, L.n_adj));
+  o = align256(o + sizeof(double) * 3 *
+                       std::max<int64_t>(1, std::max(L.n_adj, L.n_rec)));
   L.scratch = o;  // per-lattice loss / rbar staging
   o = align256(o + sizeof(double) * 3 * b->n_inst);
   L.pp = o;
@@ -425,7 +706,7 @@ int check_adj(const lbm_batch* b, const void* ws, size_t ws_bytes,
               int64_t nsteps, int64_t C) {
   if (!b || !ws) return set_err(LBM_EINVAL, "NULL argument");
   if (b->adj_ws != ws || b->adj_nsteps != nsteps || b->adj_ckpt != C ||
-      !same_tuning(b->adj_tune, b->tune))
+      !same_tuning(b->adj_tune, b->tune) || b->adj_plain_up != b->adj_plain)
     return set_err(LBM_EINVAL,
                    "no checkpoints for this workspace, nsteps and ckpt_every: "
                    "call lbm_batch_forward_ckpt first");
@@ -442,7 +723,7 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
   const int64_t* offs = at<int64_t>(ws, L.offs);
   const size_t SD = 6 * (size_t)b->n_total;
   double* slots = at<double>(ws, L.rslots);
-  const int64_t nsl = 3 * std::max<int64_t>(1, L.n_adj);
+  const int64_t nsl = 3 * std::max<int64_t>(1, std::max(L.n_adj, L.n_rec));
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((nsl + 255) / 256)), dim3(256), 0,
                      s, slots, nsl, 0.0);
   int rc = hip_check(hipGetLastError(), "k_fill");
@@ -450,6 +731,7 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
   double* cur = fbar;
   double* oth = at<double>(ws, L.pp);
   const int Prec = b->tune.nodes_per_lane, Wrec = b->tune.waves_per_group;
+  const int Krec = b->tune.steps_per_launch;
   for (int64_t k = L.n_ck - 1; k >= 0; --k) {
     const int64_t t0 = k * C;
     const int64_t len = std::min(C, nsteps - t0);
@@ -457,20 +739,37 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
     auto state = [&](int64_t i) {
       return i == 0 ? ck : at<double>(ws, L.seg) + SD * (i - 1);
     };
-    for (int64_t i = 1; i < len; ++i) {
+    // states t0+1 .. t0+len-1, up to Krec of them per launch
+    for (int64_t i0 = 0; i0 + 1 < len; i0 += Krec) {
+      const int k = (int)std::min<int64_t>(Krec, len - 1 - i0);
       rc = launch_batch_tile(cs, offs, at<TileRef>(ws, L.rec_tiles), L.n_rec,
-                             state(i - 1), state(i), b->n_total, Prec, 2, 1,
-                             Wrec, s);
+                             state(i0), state(i0 + 1), b->n_total, Prec,
+                             2 * Krec, k, Wrec, s, (int64_t)SD);
       if (rc) return rc;
     }
-    for (int64_t i = len - 1; i >= 0; --i) {
-      hipLaunchKernelGGL(k_adjoint_step, dim3((unsigned)L.n_adj),
-                         dim3(kAdjBlock), 0, s, cs, offs,
-                         at<TileRef>(ws, L.adj_tiles), L.n_adj,
-                         (const double*)state(i), (const double*)cur, oth,
-                         b->n_total, slots);
-      if ((rc = hip_check(hipGetLastError(), "k_adjoint_step"))) return rc;
-      std::swap(cur, oth);
+    if (b->adj_plain) {
+      for (int64_t i = len - 1; i >= 0; --i) {
+        hipLaunchKernelGGL(k_adjoint_step, dim3((unsigned)L.n_adj),
+                           dim3(kAdjBlock), 0, s, cs, offs,
+                           at<TileRef>(ws, L.adj_tiles), L.n_adj,
+                           (const double*)state(i), (const double*)cur, oth,
+                           b->n_total, slots);
+        if ((rc = hip_check(hipGetLastError(), "k_adjoint_step"))) return rc;
+        std::swap(cur, oth);
+      }
+    } else {
+      // up to Krec reverse steps per launch, with the forward tile shape
+      for (int64_t hi = len; hi > 0;) {
+        const int64_t lo = std::max<int64_t>(0, hi - Krec);
+        rc = launch_adjoint_tile(Prec, Wrec, cs, offs,
+                                 at<TileRef>(ws, L.rec_tiles), L.n_rec, ck,
+                                 at<double>(ws, L.seg), (int64_t)SD, (int)lo,
+                                 (int)hi, cur, oth, b->n_total, 2 * Krec,
+                                 slots, s);
+        if (rc) return rc;
+        std::swap(cur, oth);
+        hi = lo;
+      }
     }
   }
   if (cur != fbar &&
@@ -479,8 +778,9 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
                       "hipMemcpyAsync")))
     return rc;
   hipLaunchKernelGGL(k_rbar_reduce, dim3((unsigned)((b->n_inst + 255) / 256)),
-                     dim3(256), 0, s, at<int64_t>(ws, L.adj_first), b->n_inst,
-                     (const double*)slots, rbar);
+                     dim3(256), 0, s,
+                     at<int64_t>(ws, b->adj_plain ? L.adj_first : L.rec_first),
+                     b->n_inst, (const double*)slots, rbar);
   return hip_check(hipGetLastError(), "k_rbar_reduce");
 }
 
@@ -527,16 +827,24 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   const hipStream_t s = b->stream;
   int rc = LBM_OK;
   const bool same = b->adj_ws == ws && b->adj_nsteps == nsteps &&
-                    b->adj_ckpt == ckpt_every && same_tuning(b->adj_tune, b->tune);
+                    b->adj_ckpt == ckpt_every &&
+                    same_tuning(b->adj_tune, b->tune) &&
+                    b->adj_plain_up == b->adj_plain;
   if (!same) {
     // tables of this workspace layout: forward tiles, recompute tiles
     // (one step, halo 2), adjoint tiles and each lattice's first adjoint tile
     const auto fwd = tile_table(b, tile_width(b->tune) - 4 * b->tune.steps_per_launch);
-    const auto rec = tile_table(b, tile_width(b->tune) - 4);
+    const auto rec =
+        tile_table(b, tile_width(b->tune) - 4 * b->tune.steps_per_launch);
     const auto adj = tile_table(b, kAdjOut);
-    std::vector<int64_t> first(b->n_inst + 1, 0);
-    for (const TileRef& t : adj) first[t.inst + 1]++;
-    for (int64_t i = 0; i < b->n_inst; ++i) first[i + 1] += first[i];
+    auto firsts = [&](const std::vector<TileRef>& tab) {
+      std::vector<int64_t> first(b->n_inst + 1, 0);
+      for (const TileRef& t : tab) first[t.inst + 1]++;
+      for (int64_t i = 0; i < b->n_inst; ++i) first[i + 1] += first[i];
+      return first;
+    };
+    const auto first = firsts(adj);
+    const auto rfirst = firsts(rec);
     auto up = [&](size_t off, const void* src, size_t bytes) {
       if (!rc && bytes)
         rc = hip_check(hipMemcpyAsync(at<char>(ws, off), src, bytes,
@@ -549,6 +857,7 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     up(L.rec_tiles, rec.data(), sizeof(TileRef) * rec.size());
     up(L.adj_tiles, adj.data(), sizeof(TileRef) * adj.size());
     up(L.adj_first, first.data(), sizeof(int64_t) * first.size());
+    up(L.rec_first, rfirst.data(), sizeof(int64_t) * rfirst.size());
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (rc) return rc;
     drop_adjoint_graph(b);
@@ -556,6 +865,7 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     b->adj_nsteps = nsteps;
     b->adj_ckpt = ckpt_every;
     b->adj_tune = b->tune;
+    b->adj_plain_up = b->adj_plain;
   }
   const size_t SB = sizeof(double) * 6 * b->n_total;
   const Consts* cs = at<Consts>(ws, L.consts);
@@ -653,7 +963,25 @@ int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
   return hip_check(hipGetLastError(), "k_moments_adjoint");
 }
 
+int lbm_batch_set_adjoint_kernel(lbm_batch* b, int kernel) {
+  if (!b) return set_err(LBM_EINVAL, "batch is NULL");
+  if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_PLAIN &&
+      kernel != LBM_KERNEL_BLOCKED)
+    return set_err(LBM_EINVAL, "unknown adjoint kernel %d", kernel);
+  b->adj_plain = kernel != LBM_KERNEL_BLOCKED;
+  return LBM_OK;
+}
+
 // ----------------------------------------------------- single lattice --
+
+int lbm_set_adjoint_kernel(lbm_handle* h, int kernel) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_PLAIN &&
+      kernel != LBM_KERNEL_BLOCKED)
+    return set_err(LBM_EINVAL, "unknown adjoint kernel %d", kernel);
+  h->adj_kernel = kernel == LBM_KERNEL_BLOCKED ? LBM_KERNEL_BLOCKED : LBM_KERNEL_PLAIN;
+  return LBM_OK;
+}
 
 size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
                                    int64_t ckpt_every) {
@@ -670,6 +998,7 @@ int lbm_forward_ckpt(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
   if (!b) return LBM_EINVAL;
   if (h->tune.kernel == LBM_KERNEL_BLOCKED && !same_tuning(b->tune, h->tune))
     lbm_batch_set_tuning(b, &h->tune);
+  b->adj_plain = h->adj_kernel != LBM_KERNEL_BLOCKED;
   return lbm_batch_forward_ckpt(b, f, ws, ws_bytes, nsteps, ckpt_every);
 }
 

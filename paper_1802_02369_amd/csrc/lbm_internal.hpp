@@ -31,10 +31,12 @@ int launch_diagnostics(const Consts& c, const double* f, int64_t n,
 int launch_moments(const Consts& c, const double* f, double* m, int64_t n,
                    hipStream_t s);
 
+// state_stride > 0: store the state after every one of the K steps, step s
+// (1-based) into fout + (s-1)*state_stride.
 int launch_batch_tile(const Consts* cs, const int64_t* offs,
                       const TileRef* tiles, int64_t ntiles, const double* fin,
                       double* fout, int64_t S, int P, int H, int K, int wg,
-                      hipStream_t s);
+                      hipStream_t s, int64_t state_stride = 0);
 int launch_batch_equilibrium(const Consts* cs, const int64_t* offs,
                              int64_t n_inst, const double* rho, const double* J,
                              const double* zeta, double* f, int64_t S,
@@ -82,6 +84,7 @@ struct lbm_handle {
   lbm::Consts c;
   hipStream_t stream;
   lbm_tuning tune;
+  int32_t adj_kernel = LBM_KERNEL_PLAIN;  // reverse-sweep kernel
   lbm_batch* one = nullptr;  // batch of this one lattice, for the adjoint
 };
 
@@ -107,6 +110,8 @@ struct lbm_batch {
   const void* adj_ws = nullptr;
   int64_t adj_nsteps = -1, adj_ckpt = -1;
   lbm_tuning adj_tune{};
+  bool adj_plain = true;      // one reverse step per launch (else K per launch)
+  bool adj_plain_up = false;  // the value the uploaded tables were built for
   // captured graph of the last lbm_batch_adjoint(use_graph = 1)
   hipGraphExec_t adj_exec = nullptr;
   const double* ag_fbar = nullptr;

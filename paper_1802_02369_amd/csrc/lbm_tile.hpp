@@ -1,0 +1,80 @@
+// Register-tile helpers shared by the forward and reverse tile kernels:
+// coalesced loads and stores of a wavefront's segment through LDS, and the
+// per-step boundary record exchanged between the wavefronts of a tile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.hpp"
+
+namespace {
+
+// Global memory is touched only at the start and the end of the launch, and
+// always coalesced: node i of a wavefront's segment travels through that
+// wavefront's LDS buffer between the coalesced order (lane l handles
+// i = k*64 + l) and the register order (lane l owns i = l*P + k).  The LDS
+// index i + i/P pads one double per lane row so that both orders are free of
+// bank conflicts.  Staging is private to a wavefront (wave_barrier only).
+template <int P>
+__device__ __forceinline__ int lds_idx(int i) {
+  return i + i / P;
+}
+
+__device__ __forceinline__ int64_t wrap_near(int64_t x, int64_t n, bool small) {
+  if (small) return lbm::wrap_mod(x, n);
+  return x < 0 ? x + n : (x >= n ? x - n : x);
+}
+
+// Arrays of a lattice of length L are at fin + q*S (S >= L, the array
+// stride of the state the lattice lives in).
+template <int P>
+__device__ __forceinline__ void tile_load(const double* __restrict__ fin,
+                                          int64_t S, int64_t n, int64_t start,
+                                          bool inside, bool small, int lane,
+                                          double* lds, double (&f)[6][P]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double* src = fin + (int64_t)q * S;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int i = k * 64 + lane;
+      const int64_t g = inside ? start + i : wrap_near(start + i, n, small);
+      lds[lds_idx<P>(i)] = src[g];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < P; ++k) f[q][k] = lds[lds_idx<P>(lane * P + k)];
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Stores the nodes of this wavefront's segment whose tile index lies in
+// [lo, hi) and whose global index is below n.
+template <int P>
+__device__ __forceinline__ void tile_store(double* __restrict__ fout,
+                                           int64_t S, int64_t n, int64_t start,
+                                           int lo, int hi, int lane, double* lds,
+                                           const double (&f)[6][P]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) lds[lds_idx<P>(lane * P + k)] = f[q][k];
+    __builtin_amdgcn_wave_barrier();
+    double* dst = fout + (int64_t)q * S;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int i = k * 64 + lane;
+      const int64_t g = start + i;
+      if (i >= lo && i < hi && g < n) dst[g] = lds[lds_idx<P>(i)];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Values exchanged between neighbouring wavefronts of a workgroup each step.
+struct Boundary {
+  double v[8];
+};
+
+}  // namespace

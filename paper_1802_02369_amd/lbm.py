@@ -111,6 +111,8 @@ def lib():
                                                _vp, _vp, _sz], ctypes.c_int),
             "lbm_batch_moments_adjoint": ([_vp, _vp, _vp, _vp, _sz],
                                           ctypes.c_int),
+            "lbm_set_adjoint_kernel": ([_vp, ctypes.c_int], ctypes.c_int),
+            "lbm_batch_set_adjoint_kernel": ([_vp, ctypes.c_int], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -264,6 +266,9 @@ class Lattice:
         return self.get_tuning()
 
     # ------------------------------------------------------ gradients --
+    def set_adjoint_kernel(self, kernel: int = KERNEL_PLAIN):
+        check(lib().lbm_set_adjoint_kernel(self._h, int(kernel)))
+
     def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):
         nb = int(lib().lbm_adjoint_workspace_bytes(self._h, int(nsteps),
                                                    int(ckpt_every)))
@@ -434,6 +439,9 @@ class Batch:
         return self.get_tuning()
 
     # ------------------------------------------------------ gradients --
+    def set_adjoint_kernel(self, kernel: int = KERNEL_PLAIN):
+        check(lib().lbm_batch_set_adjoint_kernel(self._h, int(kernel)))
+
     def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):
         nb = int(lib().lbm_batch_adjoint_workspace_bytes(
             self._h, int(nsteps), int(ckpt_every)))

@@ -39,10 +39,11 @@ def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
+@pytest.mark.parametrize("adj", ["plain", "blocked"])
 @pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear", "fluid",
                                    "thermal"])
 @pytest.mark.parametrize("n", [3, 5, 64, 251, 252, 253, 256, 1000, 3001])
-def test_one_adjoint_step(pname, n):
+def test_one_adjoint_step(pname, n, adj):
     """fbar(t) and the rate partials of one step against the oracle's
     adjoint (exact per-node Jacobian blocks, transposed)."""
     rng = np.random.default_rng(n)
@@ -51,6 +52,8 @@ def test_one_adjoint_step(pname, n):
     fbn = rng.standard_normal((6, n))
     want_fb, want_r = oracle.step_adjoint(f0, fbn, po)
     lat = lbm().Lattice(n, gpu_params(po))
+    if adj == "blocked":
+        lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
     aws = lat.adjoint_workspace(1, 1, dev())
     f = T(f0)
     lat.forward_ckpt(f, 1, 1, aws)
@@ -62,10 +65,13 @@ def test_one_adjoint_step(pname, n):
     np.testing.assert_allclose(r, want_r, rtol=1e-11, atol=1e-12 * scale)
 
 
+@pytest.mark.parametrize("kernel", ["plain", "blocked", "blocked_p4w2k5",
+                                    "plainfwd"])
 @pytest.mark.parametrize("pname,n,steps,ckpt", [
     ("paper", 64, 40, 7), ("odd", 300, 33, 33), ("nosource", 97, 25, 1),
-    ("linear", 260, 18, 5), ("odd", 1200, 50, 8)])
-def test_checkpointed_gradient(pname, n, steps, ckpt):
+    ("linear", 260, 18, 5), ("odd", 1200, 50, 8), ("fluid", 700, 37, 20),
+    ("thermal", 500, 30, 30), ("odd", 5000, 70, 35)])
+def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
     rng = np.random.default_rng(steps)
     po = oracle_params(pname)
     j = np.arange(n)
@@ -75,6 +81,13 @@ def test_checkpointed_gradient(pname, n, steps, ckpt):
     tgt = po.rho0 * (1 + 0.03 * np.sin(2 * np.pi * j / n + 1))
     L, rb, Jb, zb, sb = oracle.gradient(rho, J, zeta, steps, tgt, po)
     lat = lbm().Lattice(n, gpu_params(po))
+    if kernel == "plainfwd":
+        lat.set_tuning(kernel=lbm().KERNEL_PLAIN)
+    elif kernel == "blocked":
+        lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+    elif kernel == "blocked_p4w2k5":
+        lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+        lat.set_tuning(nodes_per_lane=4, steps_per_launch=5, waves_per_group=2)
     aws = lat.adjoint_workspace(steps, ckpt, dev())
     r_, J_, z_ = T(rho), T(J), T(zeta)
     f = lat.equilibrium(r_, J_, z_)
@@ -166,7 +179,8 @@ def test_adjoint_config_gradient():
         assert abs(rbar[q] - fd) < 1e-6 * scale
 
 
-def test_batched_adjoint():
+@pytest.mark.parametrize("adj", ["plain", "blocked"])
+def test_batched_adjoint(adj):
     """Per-lattice gradients of a ragged batch against the oracle, lattice by
     lattice (loss 1/2 sum (rho(T) - rho0)^2 per lattice)."""
     from paper_1802_02369_amd import workloads
@@ -175,6 +189,8 @@ def test_batched_adjoint():
     bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
     ps = [oracle_params("paper", s_e=float(s)) for s in bt.s_e]
     b = lbm().Batch(bt.offsets, [gpu_params(p) for p in ps])
+    if adj == "blocked":
+        b.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
     fl = bt.fields
     r_, J_, z_ = T(fl.rho), T(fl.J), T(fl.zeta)
     f = b.equilibrium(r_, J_, z_)
