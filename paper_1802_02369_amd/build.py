@@ -15,6 +15,10 @@ HIPFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP64 fused multiply-adds as three-address v_fma_f64: the two-address
+    # v_fmac_f64 ties the addend to the destination, which costs a register
+    # copy per polynomial coefficient held in a vector register
+    "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
     "-Wno-unused-command-line-argument",
 ]
 

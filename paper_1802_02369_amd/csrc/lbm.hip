@@ -103,6 +103,14 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->gc = 1.0 / (2.0 * r0 * cp * l);
   c->gamma = g;
   c->cp = cp;
+  c->se_fb = p->s_e * c->fb;
+  c->se_3 = p->s_e / 3.0;
+  c->sp_gc = p->s_psi * c->gc;
+  c->sp_2 = p->s_psi / 2.0;
+  c->sx_gb = p->s_eps * c->gb;
+  c->sx_3 = p->s_eps / 3.0;
+  c->src_g = c->ga * c->src_c;
+  c->xs0l = c->xs0 - c->gm1 * std::log(r0);
   c->eq_kind = p->eq_kind;
   if (p->eq_kind == 1) {
     // Eq. equilibres-NS-linearise as printed (lambda = cp = rho0 = 1).
@@ -168,6 +176,7 @@ __global__ __launch_bounds__(256) void k_moments(Consts c,
 
 // One time step, one node per thread, push streaming.  Block b owns nodes
 // [b*B, b*B + B); threads 0 and 1 also compute u, T of the two halo nodes.
+template <int EQ>
 __global__ __launch_bounds__(kPlainBlock) void k_step_plain(
     Consts c, const double* __restrict__ fin, double* __restrict__ fout,
     int64_t n) {
@@ -186,7 +195,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_step_plain(
     g0 = fin[3 * n + j];
     gp = fin[4 * n + j];
     gm = fin[5 * n + j];
-    lbm::collide_local(c, f0, fp, fm, g0, gp, gm, u, T, rw, w);
+    lbm::collide_local<EQ>(c, f0, fp, fm, g0, gp, gm, u, T, rw, w);
     su[tid + 1] = u;
     sT[tid + 1] = T;
   }
@@ -231,15 +240,15 @@ __global__ __launch_bounds__(kPlainBlock) void k_step_plain(
 // first and last lanes of a wavefront take their outside neighbours from the
 // adjacent wavefronts through LDS (two workgroup barriers per step; each
 // slot of `bnd` is written and read between the same pair of barriers).
-template <int P, int WG>
+template <int P, int WG, int EQ>
 __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
                                           Boundary* bnd, int lane, int wave) {
   double uA, TA, rwA, wA;  // node P-1, collided first
-  lbm::collide_local(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
+  lbm::collide_local<EQ>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
                      f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
   double um, Tm, rwm, wm;  // node k (the one whose source is next)
   __builtin_amdgcn_sched_barrier(0);
-  lbm::collide_local(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0], f[5][0],
+  lbm::collide_local<EQ>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0], f[5][0],
                      um, Tm, rwm, wm);
   if (WG > 1) {
     if (lane == 63) {
@@ -271,7 +280,7 @@ __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
     // nodes: that would hold several nodes' temporaries live at once.
     __builtin_amdgcn_sched_barrier(0);
     if (k + 1 < P - 1) {
-      lbm::collide_local(c, f[0][k + 1], f[1][k + 1], f[2][k + 1], f[3][k + 1],
+      lbm::collide_local<EQ>(c, f[0][k + 1], f[1][k + 1], f[2][k + 1], f[3][k + 1],
                          f[4][k + 1], f[5][k + 1], ur, Tr, rwr, wr);
     } else if (k + 1 == P - 1) {
       ur = uA;
@@ -338,7 +347,7 @@ __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
 // interior [H, W - H) (one step has radius 2, so K steps need H >= 2K).
 // With every_step, the interior is stored after each step s = 1..K into the
 // state fout + (s-1)*state_stride (the states a reverse sweep needs).
-template <int P, int WG>
+template <int P, int WG, int EQ>
 __device__ __forceinline__ void tile_run(const Consts& c,
                                          const double* __restrict__ fin,
                                          double* __restrict__ fout, int64_t S,
@@ -350,7 +359,7 @@ __device__ __forceinline__ void tile_run(const Consts& c,
   __shared__ double stage[WG * (WW + 64)];
   __shared__ Boundary bnd[WG];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* lds = stage + wave * (WW + 64);
   const int64_t wstart = start + wave * WW;
   const bool inside = start >= 0 && start + W <= n;
@@ -360,7 +369,7 @@ __device__ __forceinline__ void tile_run(const Consts& c,
   // tile indices [H, W - H) are valid; in this wavefront's numbering:
   const int lo = H - wave * WW, hi = W - H - wave * WW;
   for (int step = 0; step < K; ++step) {
-    tile_step<P, WG>(c, f, bnd, lane, wave);
+    tile_step<P, WG, EQ>(c, f, bnd, lane, wave);
     if (every_step)
       tile_store<P>(fout + step * state_stride, S, n, wstart, lo, hi, lane,
                     lds, f);
@@ -368,24 +377,24 @@ __device__ __forceinline__ void tile_run(const Consts& c,
   if (!every_step) tile_store<P>(fout, S, n, wstart, lo, hi, lane, lds, f);
 }
 
-template <int P, int WG>
-__global__ __launch_bounds__(64 * WG) void k_step_tile(
+template <int P, int WG, int EQ>
+__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : 1) void k_step_tile(
     Consts c, const double* __restrict__ fin, double* __restrict__ fout,
     int64_t n, int K, int64_t ntiles) {
   const int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;  // uniform over the workgroup
   const int OUT = 64 * P * WG - 4 * K;
-  tile_run<P, WG>(c, fin, fout, n, n, tile * OUT - 2 * K, 2 * K, K);
+  tile_run<P, WG, EQ>(c, fin, fout, n, n, tile * OUT - 2 * K, 2 * K, K);
 }
 
 // Batched form: workgroup b advances tile tiles[b].t of lattice tiles[b].inst,
 // which occupies [offs[inst], offs[inst+1]) of every array of a state of
 // array stride S, with that lattice's own constants.  The tiling (halo H,
 // OUT = W - 2H) is fixed by the tile table; a launch runs K <= H/2 steps.
-// state_stride > 0: store the state after every step, step s into
+// EVERY: store the state after every step, step s into
 // fout + (s-1)*state_stride.
-template <int P, int WG>
-__global__ __launch_bounds__(64 * WG) void k_batch_tile(
+template <int P, int WG, int EQ, bool EVERY>
+__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : 1) void k_batch_tile(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const lbm::TileRef* __restrict__ tiles, const double* __restrict__ fin,
     double* __restrict__ fout, int64_t S, int H, int K, int64_t ntiles,
@@ -397,8 +406,8 @@ __global__ __launch_bounds__(64 * WG) void k_batch_tile(
   const int64_t n = offs[tr.inst + 1] - off;
   const Consts c = cs[tr.inst];
   const int OUT = 64 * P * WG - 2 * H;
-  tile_run<P, WG>(c, fin + off, fout + off, S, n, (int64_t)tr.t * OUT - H, H,
-                  K, state_stride > 0, state_stride);
+  tile_run<P, WG, EQ>(c, fin + off, fout + off, S, n, (int64_t)tr.t * OUT - H, H,
+                  K, EVERY, state_stride);
 }
 
 // One workgroup per lattice of a batch: moments m = M f (eq. M-d1q3q3).
@@ -550,8 +559,11 @@ int launch_equilibrium(const Consts& c, const double* rho, const double* J,
 
 int launch_step_plain(const Consts& c, const double* fin, double* fout,
                       int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_plain, dim3((unsigned)cdiv(n, kPlainBlock)),
-                     dim3(kPlainBlock), 0, s, c, fin, fout, n);
+  const dim3 grid((unsigned)cdiv(n, kPlainBlock)), block(kPlainBlock);
+  if (c.eq_kind == 0)
+    hipLaunchKernelGGL(k_step_plain<0>, grid, block, 0, s, c, fin, fout, n);
+  else
+    hipLaunchKernelGGL(k_step_plain<-1>, grid, block, 0, s, c, fin, fout, n);
   return hip_check(hipGetLastError(), "k_step_plain");
 }
 
@@ -561,8 +573,12 @@ template <int P, int WG>
 static void launch_tile_t(const Consts& c, const double* fin, double* fout,
                           int64_t n, int K, hipStream_t s) {
   const int64_t ntiles = cdiv(n, tile_out(P, K, WG));
-  hipLaunchKernelGGL((k_step_tile<P, WG>), dim3((unsigned)ntiles),
-                     dim3(64 * WG), 0, s, c, fin, fout, n, K, ntiles);
+  if (c.eq_kind == 0)
+    hipLaunchKernelGGL((k_step_tile<P, WG, 0>), dim3((unsigned)ntiles),
+                       dim3(64 * WG), 0, s, c, fin, fout, n, K, ntiles);
+  else
+    hipLaunchKernelGGL((k_step_tile<P, WG, -1>), dim3((unsigned)ntiles),
+                       dim3(64 * WG), 0, s, c, fin, fout, n, K, ntiles);
 }
 
 template <int P>
@@ -615,23 +631,33 @@ template <int P, int WG>
 static void launch_batch_t(const Consts* cs, const int64_t* offs,
                            const TileRef* tiles, int64_t ntiles,
                            const double* fin, double* fout, int64_t S, int H,
-                           int K, int64_t state_stride, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_tile<P, WG>), dim3((unsigned)ntiles),
-                     dim3(64 * WG), 0, s, cs, offs, tiles, fin, fout, S, H, K,
-                     ntiles, state_stride);
+                           int K, int64_t state_stride, int eq, hipStream_t s) {
+  const dim3 grid((unsigned)ntiles), block(64 * WG);
+  if (eq == 0 && state_stride == 0)
+    hipLaunchKernelGGL((k_batch_tile<P, WG, 0, false>), grid, block, 0, s, cs,
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
+  else if (eq == 0)
+    hipLaunchKernelGGL((k_batch_tile<P, WG, 0, true>), grid, block, 0, s, cs,
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
+  else if (state_stride == 0)
+    hipLaunchKernelGGL((k_batch_tile<P, WG, -1, false>), grid, block, 0, s, cs,
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
+  else
+    hipLaunchKernelGGL((k_batch_tile<P, WG, -1, true>), grid, block, 0, s, cs,
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
 }
 
 int launch_batch_tile(const Consts* cs, const int64_t* offs,
                       const TileRef* tiles, int64_t ntiles, const double* fin,
                       double* fout, int64_t S, int P, int H, int K, int wg,
-                      hipStream_t s, int64_t state_stride) {
+                      int eq, hipStream_t s, int64_t state_stride) {
   if (ntiles <= 0) return LBM_OK;
   if (K < 1 || 2 * K > H || 2 * H >= 64 * P * wg)
     return set_err(LBM_EINVAL, "bad batched tile geometry H=%d K=%d", H, K);
 #define LBM_BATCH_CASE(PP, WW)                                              \
   if (P == PP && wg == WW) {                                                \
     launch_batch_t<PP, WW>(cs, offs, tiles, ntiles, fin, fout, S, H, K,    \
-                           state_stride, s);                                \
+                           state_stride, eq, s);                            \
     return hip_check(hipGetLastError(), "k_batch_tile");                    \
   }
   LBM_BATCH_CASE(2, 1)

@@ -65,7 +65,7 @@ __device__ __forceinline__ void node_forward(const Consts& c, double f0,
   q.psi = c.mpsi * (gp - gm);
   q.eps = c.meps * (sg - 2.0 * g0);
   lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T);
-  q.w = 1.0 / q.T;
+  q.w = lbm::recip(q.T);
   if (c.eq_kind == 0) {
     const double p = q.rho * c.r * q.T;
     q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
@@ -92,7 +92,7 @@ __device__ __forceinline__ void equilibria_adjoint(const Consts& c,
                                                    double& rb, double& Jb,
                                                    double& zb) {
   double sb = 0.0, Xb = 0.0;
-  const double ir = 1.0 / q.rho;
+  const double ir = lbm::recip(q.rho);
   if (c.eq_kind == 0) {
     // eps_eq = eps_c rho X + e_eq s
     rb += c.eps_c * q.X * xb;
@@ -305,7 +305,7 @@ __device__ __forceinline__ void adjoint_tile_step(
   for (int k = 0; k < P; ++k) {
     const double ul = k == 0 ? uL : u[k - 1], ur = k == P - 1 ? uR : u[k + 1];
     const double tl = k == 0 ? TL : T[k - 1], tr = k == P - 1 ? TR : T[k + 1];
-    const double w = 1.0 / T[k];
+    const double w = lbm::recip(T[k]);
     const double Zb = c.ga * (fb[3][k] + fb[4][k] + fb[5][k]);
     A[k] = 2.0 * c.src_c * rho[k] * w * (ur - ul) * Zb;
     B[k] = 2.0 * c.src_c * c.cPr * rho[k] * w * w * (tr - tl) * Zb;
@@ -352,7 +352,7 @@ __device__ __forceinline__ void adjoint_tile_step(
     q.s = s[k];
     q.X = X[k];
     q.T = T[k];
-    q.w = 1.0 / T[k];
+    q.w = lbm::recip(T[k]);
     if (c.eq_kind == 0) {
       const double p = q.rho * c.r * q.T;
       q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
@@ -690,7 +690,7 @@ int fwd_steps(lbm_batch* b, const Consts* cs, const int64_t* offs,
   for (int k : split_steps(steps, b->tune.steps_per_launch)) {
     int rc = launch_batch_tile(cs, offs, tiles, ntiles, a, w, b->n_total,
                                b->tune.nodes_per_lane, H, k,
-                               b->tune.waves_per_group, s);
+                               b->tune.waves_per_group, b->eq_class(), s);
     if (rc) return rc;
     std::swap(a, w);
     ++launches;
@@ -744,7 +744,8 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
       const int k = (int)std::min<int64_t>(Krec, len - 1 - i0);
       rc = launch_batch_tile(cs, offs, at<TileRef>(ws, L.rec_tiles), L.n_rec,
                              state(i0), state(i0 + 1), b->n_total, Prec,
-                             2 * Krec, k, Wrec, s, (int64_t)SD);
+                             2 * Krec, k, Wrec, b->eq_class(), s,
+                             (int64_t)SD);
       if (rc) return rc;
     }
     if (b->adj_plain) {

@@ -79,7 +79,7 @@ int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
   for (int k : split_steps(nsteps, b->tune.steps_per_launch)) {
     int rc = launch_batch_tile(cs, offs, tiles, b->prep_tiles, a, w,
                                b->n_total, b->tune.nodes_per_lane, H, k,
-                               b->tune.waves_per_group, s);
+                               b->tune.waves_per_group, b->eq_class(), s);
     if (rc) return rc;
     std::swap(a, w);
     ++launches;

@@ -37,6 +37,13 @@ struct Consts {
   // linear equilibria (section 7, and the thermal scheme of section 4):
   // e = l[0] rho + l[1] J + l[2] zeta, psi = l[3..5] . W, eps = l[6..8] . W
   double lin[9];
+  // Steps (v)-(vi) in population space (see collide_local): rate times the
+  // M^-1 entry of each non-conserved moment, and rate / 3, rate / 2.
+  double se_fb, se_3;  // s_e fb, s_e / 3
+  double sp_gc, sp_2;  // s_psi gc, s_psi / 2
+  double sx_gb, sx_3;  // s_eps gb, s_eps / 3
+  double src_g;        // ga src_c: the source increment of each g population
+  double xs0l;         // xs0 - (gamma - 1) ln rho0
   int32_t eq_kind;  // 0 section 8, 1 linear, 2 isentropic fluid D1Q3
   int32_t pad;
 };
@@ -60,45 +67,115 @@ __device__ __forceinline__ double density(const Consts& c, double f0, double fp,
   return (a + b) + d;
 }
 
+// 1/x for the positive normal numbers of the step (rho, T): the hardware
+// reciprocal estimate refined by two Newton-Raphson iterations
+// r <- r + r (1 - x r), within one ulp of 1/x (not always correctly rounded).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// ln 2 = kLn2Hi + kLn2Lo: kLn2Hi is ln 2 rounded to 42 significant bits, so
+// that n kLn2Hi is exact for |n| < 2^11; kLn2Lo is the rest rounded to double.
+constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;
+constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
+constexpr double kLog2e = 0x1.71547652b82fep+0;     // 1 / ln 2
+constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
+
+// Natural logarithm of a positive finite x.  Method: x = m 2^k with m in
+// [sqrt(1/2), sqrt(2)); ln m = 2 atanh(z) with z = (m-1)/(m+1), |z| < 0.172,
+// written 2z + z w Q(w), w = z^2, where Q is a degree-6 Chebyshev fit of
+// (2 atanh(z) - 2z)/z^3 on [0, 0.02944] (relative error of the fit below
+// 5e-18; coefficients from csrc/gen_poly.py); ln x = k ln 2 + ln m with ln 2
+// in two parts (the additive reduction of Cody & Waite).  Error a few ulp.
+// x <= 0 gives NaN; so do NaN and +inf.
+__device__ __forceinline__ double ln_pos(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);
+  int k = __builtin_amdgcn_frexp_exp(x);
+  if (m < kSqrtHalf) {
+    m = m + m;
+    k -= 1;
+  }
+  const double z = (m - 1.0) * recip(m + 1.0);
+  const double w = z * z;
+  double q = 0x1.2b584c80de001p-3;
+  q = fma(q, w, 0x1.39fe603f8739ep-3);
+  q = fma(q, w, 0x1.7462b4ac51915p-3);
+  q = fma(q, w, 0x1.c71c62e57c0cfp-3);
+  q = fma(q, w, 0x1.2492492df14bfp-2);
+  q = fma(q, w, 0x1.99999999952e2p-2);
+  q = fma(q, w, 0x1.5555555555558p-1);
+  const double lm = fma(z * w, q, z + z);
+  const double kd = (double)k;
+  const double r = fma(kd, kLn2Hi, fma(kd, kLn2Lo, lm));
+  return x > 0.0 ? r : __builtin_nan("");
+}
+
+// e^x for the moderate arguments of the equation of state.  Method (Cody &
+// Waite): n = nearest integer to x / ln 2, r = x - n ln 2 with ln 2 in two
+// parts, |r| <= 0.3466; e^r = 1 + r (1 + r R(r)) where R is a degree-9
+// Chebyshev fit of (e^r - 1 - r)/r^2 (relative error of e^r below 2e-17;
+// coefficients from csrc/gen_poly.py); e^x = 2^n e^r.  Error a few ulp.
+// Overflow gives +inf and underflow 0 (the hardware saturates n); NaN stays
+// NaN.
+__device__ __forceinline__ double exp_fin(double x) {
+  const double n = __builtin_rint(x * kLog2e);
+  const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
+  double q = 0x1.af38a71a18cb9p-26;
+  q = fma(q, r, 0x1.2891834686c7ep-22);
+  q = fma(q, r, 0x1.71de0daf7a6ccp-19);
+  q = fma(q, r, 0x1.a019b90eefe8ep-16);
+  q = fma(q, r, 0x1.a01a01a7c3d59p-13);
+  q = fma(q, r, 0x1.6c16c1788b646p-10);
+  q = fma(q, r, 0x1.11111111109b4p-7);
+  q = fma(q, r, 0x1.5555555553d64p-5);
+  q = fma(q, r, 0x1.5555555555556p-3);
+  q = fma(q, r, 0x1.0000000000001p-1);
+  q = fma(q, r, 1.0);
+  q = fma(q, r, 1.0);
+  return __builtin_amdgcn_ldexp(q, (int)n);
+}
+
 // Thermodynamics from conserved moments: u, T and w = 1/T, plus X = ln(T/T0).
 __device__ __forceinline__ void thermo(const Consts& c, double rho, double J,
                                        double zeta, double& u, double& s,
                                        double& X, double& T) {
-  const double ir = 1.0 / rho;
+  const double ir = recip(rho);
   u = J * ir;
   s = zeta * ir;
-  X = c.gm1 * log(rho * c.irho0) + (c.gcp * s + c.xs0);
-  T = c.T0 * exp(X);
+  X = c.gm1 * ln_pos(rho) + (c.gcp * s + c.xs0l);
+  T = c.T0 * exp_fin(X);
 }
 
 // Isentropic pressure p0 (rho/rho0)^gamma = rho r T0 (rho/rho0)^(gamma-1)
 // of the fluid D1Q3 scheme (sections 2-3).
 __device__ __forceinline__ double iso_pressure(const Consts& c, double rho) {
-  return rho * c.r * c.T0 * exp(c.gm1 * log(rho * c.irho0));
+  return rho * c.r * c.T0 * exp_fin(c.gm1 * ln_pos(rho * c.irho0));
 }
 
 // Steps (ii)-(vi) at one node, in place on the six populations: moments,
 // equilibria, relaxation, back to populations.  Returns u, T and the two
-// factors the source needs: rw = rho / T and w = 1 / T.
+// factors the source needs: rw = rho / T and w = 1 / T.  EQ = 0 compiles the
+// equilibria of section 8 only (every lattice of the launch has eq_kind 0);
+// EQ = -1 selects them per lattice from c.eq_kind.
+template <int EQ>
 __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
                                               double& fp, double& fm,
                                               double& g0, double& gp,
                                               double& gm, double& u, double& T,
                                               double& rw, double& w) {
-  // (ii) moments, eq. M-d1q3q3
-  const double sf = fp + fm;
+  // (ii) the conserved moments, eq. M-d1q3q3
   const double rho = density(c, f0, fp, fm);
   const double J = c.mJ * (fp - fm);
-  const double e = c.me * (sf - 2.0 * f0);
-  const double sg = gp + gm;
-  const double zeta = c.mz * (g0 + sg);
-  const double psi = c.mpsi * (gp - gm);
-  const double eps = c.meps * (sg - 2.0 * g0);
+  const double zeta = c.mz * (g0 + (gp + gm));
   // (iv) equilibria
   double s, X;
   thermo(c, rho, J, zeta, u, s, X, T);
   double e_eq, psi_eq, eps_eq;
-  if (c.eq_kind == 0) {
+  if (EQ == 0 || c.eq_kind == 0) {
     const double p = rho * c.r * T;
     e_eq = 3.0 * (J * u + p) - c.two_l2 * rho;
     psi_eq = zeta * u;
@@ -112,20 +189,21 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
     psi_eq = c.lin[3] * rho + c.lin[4] * J + c.lin[5] * zeta;
     eps_eq = c.lin[6] * rho + c.lin[7] * J + c.lin[8] * zeta;
   }
-  // (v) relaxation, eq. relaxation-d1q3q3
-  const double es = e + c.s_e * (e_eq - e);
-  const double psis = psi + c.s_psi * (psi_eq - psi);
-  const double epss = eps + c.s_eps * (eps_eq - eps);
-  // (vi) f* = M^-1 m*
-  const double fr = c.fa * rho, fe = c.fb * es, fj = c.fc * J;
-  f0 = fr - fe;
-  fp = fr + 0.5 * fe + fj;
-  fm = fr + 0.5 * fe - fj;
-  const double gz = c.ga * zeta, ge = c.gb * epss, gj = c.gc * psis;
-  g0 = gz - ge;
-  gp = gz + 0.5 * ge + gj;
-  gm = gz + 0.5 * ge - gj;
-  w = 1.0 / T;
+  // (v) relaxation (eq. relaxation-d1q3q3) and (vi) f* = M^-1 m*, combined:
+  // only e, psi, eps change, so f* = f + M^-1 (m* - m).  With fb e =
+  // (f+ + f- - 2 f0)/3, gc psi = (g+ - g-)/2 and gb eps = (g+ + g- - 2 g0)/3
+  // (products of entries of M and M^-1), the changes are
+  //   de = fb (e* - e) = s_e fb e_eq - s_e (f+ + f- - 2 f0)/3, etc.
+  const double de = fma(c.se_fb, e_eq, -c.se_3 * ((fp + fm) - 2.0 * f0));
+  const double dp = fma(c.sp_gc, psi_eq, -c.sp_2 * (gp - gm));
+  const double dx = fma(c.sx_gb, eps_eq, -c.sx_3 * ((gp + gm) - 2.0 * g0));
+  f0 = f0 - de;
+  fp = fma(0.5, de, fp);
+  fm = fma(0.5, de, fm);
+  g0 = g0 - dx;
+  gp = fma(0.5, dx, gp) + dp;
+  gm = fma(0.5, dx, gm) - dp;
+  w = recip(T);
   rw = rho * w;
 }
 
@@ -147,8 +225,7 @@ __device__ __forceinline__ double source_g(const Consts& c, double rw, double w,
                                            double TR) {
   const double du = uR - uL;
   const double dT = TR - TL;
-  const double dz = c.src_c * rw * (du * du + c.cPr * (dT * dT) * w);
-  return c.ga * dz;
+  return c.src_g * rw * (du * du + c.cPr * (dT * dT) * w);
 }
 
 // Equilibrium populations from (rho, J, zeta).
@@ -184,18 +261,17 @@ __device__ __forceinline__ void equilibrium(const Consts& c, double rho,
 // Cross-lane moves of a double over the whole 64-lane wavefront (DPP
 // wave_shr:1 / wave_shl:1 on both 32-bit halves).  from_left: lane l receives
 // lane l-1's value; from_right: lane l receives lane l+1's value.  The edge
-// lane (0, resp. 63) keeps its own value.
+// lane (0, resp. 63) has no source and receives 0 (bound_ctrl); callers use
+// it only for nodes whose values are discarded or replaced.
 __device__ __forceinline__ double from_left(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
-  return __hiloint2double(hi2, lo2);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_right(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
-  return __hiloint2double(hi2, lo2);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ int64_t wrap_mod(int64_t x, int64_t n) {

@@ -32,11 +32,12 @@ int launch_moments(const Consts& c, const double* f, double* m, int64_t n,
                    hipStream_t s);
 
 // state_stride > 0: store the state after every one of the K steps, step s
-// (1-based) into fout + (s-1)*state_stride.
+// (1-based) into fout + (s-1)*state_stride.  eq = 0 when every lattice of
+// the table has the equilibria of section 8 (eq_kind 0), else -1.
 int launch_batch_tile(const Consts* cs, const int64_t* offs,
                       const TileRef* tiles, int64_t ntiles, const double* fin,
                       double* fout, int64_t S, int P, int H, int K, int wg,
-                      hipStream_t s, int64_t state_stride = 0);
+                      int eq, hipStream_t s, int64_t state_stride = 0);
 int launch_batch_equilibrium(const Consts* cs, const int64_t* offs,
                              int64_t n_inst, const double* rho, const double* J,
                              const double* zeta, double* f, int64_t S,
@@ -116,6 +117,13 @@ struct lbm_batch {
   hipGraphExec_t adj_exec = nullptr;
   const double* ag_fbar = nullptr;
   const double* ag_rbar = nullptr;
+
+  // equilibrium class of the tile kernels: 0 if every lattice has eq_kind 0
+  int eq_class() const {
+    for (const lbm_params& q : params)
+      if (q.eq_kind != 0) return -1;
+    return 0;
+  }
 
   // tiles of the current table for a tuning: sum of ceil(L_i / OUT)
   int64_t count_tiles(const lbm_tuning& t) const {

@@ -68,6 +68,58 @@ def test_equilibrium_and_moments(pname):
     assert max_err(m.cpu().numpy(), oracle.moments(want, po)) < TOL
 
 
+def _wide_fields(rng, n, po, decades, ds):
+    rho = po.rho0 * 10.0 ** rng.uniform(-decades, decades, n)
+    J = rho * 0.1 * po.lam * rng.uniform(-1, 1, n)
+    zeta = rho * (po.s0 + ds * po.cp * rng.uniform(-1, 1, n))
+    return rho, J, zeta
+
+
+def _node_err(got, ref):
+    """Per node, relative to that node's largest population."""
+    return (np.abs(got - ref).max(axis=0) / np.abs(ref).max(axis=0)).max()
+
+
+@pytest.mark.parametrize("pname", ["paper", "odd", "fluid"])
+def test_equilibrium_wide_thermodynamic_range(pname):
+    """The equation of state (a logarithm and an exponential per node) far
+    from the reference state: rho/rho0 log-uniform in [1e-3, 1e3] and
+    s - s0 uniform in [-6 cp, 6 cp], so T/T0 spans ~e^-11 .. e^11.
+    Equilibrium populations against the oracle (C library log and exp); the
+    limit allows a few ulp of the ~11-ulp conditioning of T in X."""
+    rng = np.random.default_rng(7)
+    po = oracle_params(pname)
+    n = 4099
+    fields = _wide_fields(rng, n, po, 3, 6)
+    say(f"wide-range equilibrium {pname} n={n}")
+    lat = make_lattice(n, po)
+    f = lat.equilibrium(*to_dev(*fields))
+    err = _node_err(f.cpu().numpy(), oracle.init(*fields, po))
+    say(f"  {err:.2e}")
+    assert err < 5e-14
+
+
+@pytest.mark.parametrize("pname", ["paper", "odd", "fluid"])
+@pytest.mark.parametrize("tuning", ["plain", "p2k8w4"])
+def test_step_broad_thermodynamic_range(pname, tuning):
+    """One time step from the oracle's equilibrium state with rho/rho0 in
+    [0.1, 10] and s - s0 in [-1.5 cp, 1.5 cp] (T/T0 up to ~20).  Wider ranges
+    are ill-conditioned in the scheme itself: at T/T0 ~ e^11, zeta is a sum of
+    g populations dominated by the ~3 r T larger eps part, and a one-ulp
+    change of the input moves the oracle's own step by ~1e-10."""
+    rng = np.random.default_rng(8)
+    po = oracle_params(pname)
+    n = 4099
+    want = oracle.init(*_wide_fields(rng, n, po, 1, 1.5), po)
+    say(f"broad-range step {pname} {tuning} n={n}")
+    lat = make_lattice(n, po, tuning)
+    f = torch.from_numpy(want.copy()).to(dev())
+    lat.step(f, 1)
+    err = _node_err(f.cpu().numpy(), oracle.step(want, po))
+    say(f"  {err:.2e}")
+    assert err < TOL
+
+
 @pytest.mark.parametrize("tuning", list(TUNINGS))
 @pytest.mark.parametrize("n", [3, 4, 5, 63, 64, 65, 255, 257, 1000, 4099, 20011])
 def test_one_step(tuning, n):
