@@ -25,7 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64, published
+FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64, published (FMA = 2 flops)
+# Vector ALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane
+# instructions/s, one wave64 instruction per SIMD every 4 clocks; every FP64
+# add, mul, FMA or transcendental takes one such slot (78.6 TFLOP/s / 2).
+LANE_INSTR_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 BYTES_PER_NODE_LAUNCH = 96.0   # read 6 + write 6 FP64 per node per launch
 METRIC = ("node-updates/s (GLUPS) FP64: plain vs batched vs fwd+adjoint; "
           "% HBM roofline")
@@ -48,8 +52,8 @@ def parse():
     ap.add_argument("--only", type=str, default=None,
                     help="comma list of extra legs to run: plain,batched,"
                          "adjoint,batched_adjoint")
-    ap.add_argument("--flops-per-node", type=float, default=None,
-                    help="override the FP64 flops per node-update")
+    ap.add_argument("--instr-per-node", type=float, default=None,
+                    help="override the FP64 instructions per node-update")
     ap.add_argument("--tuning", type=str, default=None,
                     help="P,K,W of the blocked kernel (default: library's)")
     return ap.parse_args()
@@ -76,10 +80,20 @@ def counter_record():
     return {}
 
 
-def flops_per_node_update() -> float:
-    """FP64 flops of one node-update (device log/exp/div included), from the
-    rocprofv3 counter run summarised under profiles/."""
-    return float(counter_record().get("flops_per_node_update", float("nan")))
+def per_node_update(key: str) -> float:
+    """Instructions (or flops) of one node-update of the blocked kernel, from
+    the rocprofv3 counter run summarised under profiles/: FP64 instructions
+    (device log/exp/reciprocals included), flops, all VALU instructions."""
+    return float(counter_record().get(key, float("nan")))
+
+
+def split_steps(nsteps: int, K: int) -> list:
+    """Steps per launch as the library splits a run (an even number of
+    launches of K or fewer steps)."""
+    L = -(-nsteps // K)
+    if L % 2 and nsteps > L:
+        L += 1
+    return [nsteps // L + (1 if i < nsteps % L else 0) for i in range(L)]
 
 
 def measured_traffic(kernel: str, tune: dict):
@@ -288,23 +302,38 @@ def main():
     log(f"bench: {value:.2f} GLUPS, {ms / args.steps:.1f} ms per run, "
         f"state finite and mass conserved: {ok}")
 
-    # launches of the blocked kernel per run (even count, as lbm_step splits)
-    K = tune["steps_per_launch"]
-    L = -(-T // K)
-    if L % 2 and T > L:
-        L += 1
+    # launches of the blocked kernel per run, and node-updates they compute
+    # (tiles of W nodes, W - 4k of them stored, for a launch of k steps)
+    P, K, Wg = (tune["nodes_per_lane"], tune["steps_per_launch"],
+                tune["waves_per_group"])
+    ks = split_steps(T, K)
+    L = len(ks)
+    W = 64 * P * Wg
+    computed = sum(-(-n // (W - 4 * k)) * W * k for k in ks)
     launch_ms = ms / (args.steps * L)
-    F = args.flops_per_node or flops_per_node_update()
-    kname = f"k_step_tile<{tune['nodes_per_lane']}>"
-    nodes_per_launch_update = n * T / L  # node-updates per launch
-    achieved_tflops = F * nodes_per_launch_update / (launch_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": achieved_tflops,
-            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved_tflops / FP64_PEAK_TFLOPS,
+    run_s = ms / args.steps * 1e-3
+    Fi = args.instr_per_node or per_node_update("fp64_instr_per_node_update")
+    Ff = per_node_update("flops_per_node_update")
+    Fv = per_node_update("valu_instr_per_node_update")
+    kname = f"k_step_tile<{P}>"
+    # algorithmic FP64 instructions per launch: per node-update figure times
+    # the node-updates one launch delivers (halo recomputation is overhead)
+    achieved = Fi * n * T / L / (launch_ms * 1e-3) / 1e12
+    flops = Ff * n * T / L / (launch_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": LANE_INSTR_PEAK_T,
+            "unit": "T FP64 instr/s", "frac": achieved / LANE_INSTR_PEAK_T,
             "traffic": measured_traffic(kname, tune),
             "kernel": kname,
             "launch_ms": launch_ms, "launches_per_run": L,
-            "flops_per_node_update": F,
+            "fp64_instr_per_node_update": Fi,
+            "counters_current": counter_record().get("source_hash") == source_hash(),
+            "flops": {"per_node_update": Ff, "achieved": flops,
+                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": flops / FP64_PEAK_TFLOPS},
+            # every VALU instruction (FP64, moves, DPP, compares) over the
+            # issue peak, halo node-updates included: how busy the SIMDs are
+            "valu_issue_frac": Fv * computed / run_s / (LANE_INSTR_PEAK_T * 1e12),
+            "algorithmic_bytes_per_launch": BYTES_PER_NODE_LAUNCH * n,
             "hbm_gbs_algorithmic": BYTES_PER_NODE_LAUNCH * n / (launch_ms * 1e-3) / 1e9}
     out = {
         "metric": METRIC, "value": value, "unit": "GLUPS", "n_gpus": 1,

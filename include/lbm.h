@@ -134,10 +134,13 @@ enum {
  * handle). */
 size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
 
-/* Kernel selection.  lbm_set_tuning validates the shape (P in {2,4},
+/* Kernel selection.  lbm_set_tuning validates the shape (P in {2,4,8},
  * 1 <= K, 4K < 64 P waves_per_group, waves_per_group in {1,2,4,8}).
  * The blocked kernel gives each workgroup of waves_per_group wavefronts a
- * tile of 64 P waves_per_group nodes held in registers for K steps. */
+ * tile of 64 P waves_per_group nodes held in registers for K steps.  The
+ * default is the blocked kernel with P = 8, K = 32, 4 wavefronts.  Every
+ * kernel and tile shape rounds each node-update identically: results are
+ * bitwise independent of the tuning. */
 int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);
 int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
 
@@ -225,8 +228,10 @@ int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
  * reverse step per launch, one node per thread (HBM-bound, 144 B per
  * node-step); LBM_KERNEL_BLOCKED keeps dL/df in registers for K reverse steps
  * of a forward-shaped tile (reads only the recomputed states, but needs about
- * 2.5x the arithmetic of a forward step per node).  Takes effect at the next
- * lbm_forward_ckpt. */
+ * 2.5x the arithmetic of a forward step per node; a P = 8 forward shape runs
+ * its reverse as P = 4 with twice the wavefronts, and P = 8 with 8 wavefronts
+ * is rejected with LBM_ENOTSUP by lbm_forward_ckpt).  Takes effect at the
+ * next lbm_forward_ckpt. */
 int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
 
 /* ------------------------------------------------- batches of lattices */

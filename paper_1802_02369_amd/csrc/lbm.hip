@@ -600,7 +600,8 @@ int launch_step_tile(const Consts& c, const double* fin, double* fout,
   switch (P) {
     case 2: rc = launch_tile_p<2>(c, fin, fout, n, K, wpg, s); break;
     case 4: rc = launch_tile_p<4>(c, fin, fout, n, K, wpg, s); break;
-    default: return set_err(LBM_EINVAL, "nodes_per_lane must be 2 or 4");
+    case 8: rc = launch_tile_p<8>(c, fin, fout, n, K, wpg, s); break;
+    default: return set_err(LBM_EINVAL, "nodes_per_lane must be 2, 4 or 8");
   }
   if (rc) return rc;
   return hip_check(hipGetLastError(), "k_step_tile");
@@ -668,6 +669,10 @@ int launch_batch_tile(const Consts* cs, const int64_t* offs,
   LBM_BATCH_CASE(4, 2)
   LBM_BATCH_CASE(4, 4)
   LBM_BATCH_CASE(4, 8)
+  LBM_BATCH_CASE(8, 1)
+  LBM_BATCH_CASE(8, 2)
+  LBM_BATCH_CASE(8, 4)
+  LBM_BATCH_CASE(8, 8)
 #undef LBM_BATCH_CASE
   return set_err(LBM_EINVAL, "unsupported tile shape P=%d waves=%d", P, wg);
 }

@@ -759,10 +759,13 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
         std::swap(cur, oth);
       }
     } else {
-      // up to Krec reverse steps per launch, with the forward tile shape
+      // up to Krec reverse steps per launch on the forward tiles; a P = 8
+      // forward shape runs as P = 4 with twice the wavefronts (same tile
+      // width, so the same tile table)
+      const int Padj = Prec == 8 ? 4 : Prec, Wadj = Prec == 8 ? 2 * Wrec : Wrec;
       for (int64_t hi = len; hi > 0;) {
         const int64_t lo = std::max<int64_t>(0, hi - Krec);
-        rc = launch_adjoint_tile(Prec, Wrec, cs, offs,
+        rc = launch_adjoint_tile(Padj, Wadj, cs, offs,
                                  at<TileRef>(ws, L.rec_tiles), L.n_rec, ck,
                                  at<double>(ws, L.seg), (int64_t)SD, (int)lo,
                                  (int)hi, cur, oth, b->n_total, 2 * Krec,
@@ -825,6 +828,11 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     return set_err(LBM_EINVAL, "f and ws overlap");
   if (((uintptr_t)f | (uintptr_t)ws) & 7)
     return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
+  if (!b->adj_plain && b->tune.nodes_per_lane == 8 && b->tune.waves_per_group == 8)
+    return set_err(LBM_ENOTSUP,
+                   "the blocked adjoint kernel has no form for the tile shape "
+                   "P = 8 with 8 wavefronts; use the one-step adjoint kernel "
+                   "or another tile shape");
   const hipStream_t s = b->stream;
   int rc = LBM_OK;
   const bool same = b->adj_ws == ws && b->adj_nsteps == nsteps &&

@@ -18,8 +18,8 @@ int check_tuning(const lbm_tuning* t) {
     return set_err(LBM_EINVAL, "unknown kernel %d", t->kernel);
   if (t->kernel == LBM_KERNEL_PLAIN) return LBM_OK;
   const int P = t->nodes_per_lane, K = t->steps_per_launch;
-  if (P != 2 && P != 4)
-    return set_err(LBM_EINVAL, "nodes_per_lane must be 2 or 4 (got %d)", P);
+  if (P != 2 && P != 4 && P != 8)
+    return set_err(LBM_EINVAL, "nodes_per_lane must be 2, 4 or 8 (got %d)", P);
   const int w = t->waves_per_group;
   if (w != 1 && w != 2 && w != 4 && w != 8)
     return set_err(LBM_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
@@ -41,12 +41,25 @@ std::vector<int> split_steps(int64_t nsteps, int K) {
 
 std::vector<lbm_tuning> tuning_candidates() {
   std::vector<lbm_tuning> v;
-  const int Ps[] = {2, 4}, Ws[] = {2, 4, 8}, Ks[] = {8, 12, 16, 24, 32};
+  const int Ps[] = {2, 4, 8}, Ws[] = {2, 4, 8}, Ks[] = {8, 12, 16, 24, 32};
   for (int P : Ps)
     for (int W : Ws)
       for (int K : Ks)
         if (16 * K <= 64 * P * W) v.push_back(lbm_tuning{LBM_KERNEL_BLOCKED, P, K, W});
   return v;
+}
+
+lbm_tuning default_tuning(int64_t len, int64_t total) {
+  // tile shapes from the widest down, with the K that measured best for each
+  static const lbm_tuning shapes[] = {
+      {LBM_KERNEL_BLOCKED, 8, 32, 4}, {LBM_KERNEL_BLOCKED, 4, 16, 4},
+      {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 8, 2},
+      {LBM_KERNEL_BLOCKED, 2, 8, 1}};
+  for (const lbm_tuning& t : shapes) {
+    const int64_t width = tile_width(t), out = width - 4 * t.steps_per_launch;
+    if (4 * width <= len && total >= 1024 * out) return t;
+  }
+  return shapes[sizeof shapes / sizeof shapes[0] - 1];
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -94,7 +107,7 @@ int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream) {
   x->p = *p;
   x->c = c;
   x->stream = (hipStream_t)stream;
-  x->tune = lbm_tuning{LBM_KERNEL_BLOCKED, 2, 16, 8};
+  x->tune = default_tuning(n, n);
   *h = x;
   return LBM_OK;
 }

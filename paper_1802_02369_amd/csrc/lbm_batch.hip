@@ -308,7 +308,7 @@ int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
     }
   }
   x->stream = (hipStream_t)stream;
-  x->tune = lbm_tuning{LBM_KERNEL_BLOCKED, 2, 16, 4};
+  x->tune = default_tuning(x->n_total / n_inst, x->n_total);
   *b = x;
   return LBM_OK;
 }

@@ -71,6 +71,7 @@ __device__ __forceinline__ double density(const Consts& c, double f0, double fp,
 // reciprocal estimate refined by two Newton-Raphson iterations
 // r <- r + r (1 - x r), within one ulp of 1/x (not always correctly rounded).
 __device__ __forceinline__ double recip(double x) {
+#pragma clang fp contract(off)
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(r, e, r);
@@ -93,6 +94,7 @@ constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
 // in two parts (the additive reduction of Cody & Waite).  Error a few ulp.
 // x <= 0 gives NaN; so do NaN and +inf.
 __device__ __forceinline__ double ln_pos(double x) {
+#pragma clang fp contract(off)
   double m = __builtin_amdgcn_frexp_mant(x);
   int k = __builtin_amdgcn_frexp_exp(x);
   if (m < kSqrtHalf) {
@@ -122,6 +124,7 @@ __device__ __forceinline__ double ln_pos(double x) {
 // Overflow gives +inf and underflow 0 (the hardware saturates n); NaN stays
 // NaN.
 __device__ __forceinline__ double exp_fin(double x) {
+#pragma clang fp contract(off)
   const double n = __builtin_rint(x * kLog2e);
   const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
   double q = 0x1.af38a71a18cb9p-26;
@@ -139,34 +142,68 @@ __device__ __forceinline__ double exp_fin(double x) {
   return __builtin_amdgcn_ldexp(q, (int)n);
 }
 
-// Thermodynamics from conserved moments: u, T and w = 1/T, plus X = ln(T/T0).
+// Every function below fixes its own rounding sequence: contraction of a
+// product and a sum into an FMA is off, and FMAs are written where wanted.
+// A node-update therefore rounds identically in every kernel that inlines
+// these functions (one-step, any tile shape, batched), and those kernels
+// produce bitwise identical states.
+
+// Thermodynamics from conserved moments: u, s and X = ln(T/T0), T.
 __device__ __forceinline__ void thermo(const Consts& c, double rho, double J,
                                        double zeta, double& u, double& s,
                                        double& X, double& T) {
+#pragma clang fp contract(off)
   const double ir = recip(rho);
   u = J * ir;
   s = zeta * ir;
-  X = c.gm1 * ln_pos(rho) + (c.gcp * s + c.xs0l);
+  X = fma(c.gm1, ln_pos(rho), fma(c.gcp, s, c.xs0l));
   T = c.T0 * exp_fin(X);
 }
 
 // Isentropic pressure p0 (rho/rho0)^gamma = rho r T0 (rho/rho0)^(gamma-1)
 // of the fluid D1Q3 scheme (sections 2-3).
 __device__ __forceinline__ double iso_pressure(const Consts& c, double rho) {
-  return rho * c.r * c.T0 * exp_fin(c.gm1 * ln_pos(rho * c.irho0));
+#pragma clang fp contract(off)
+  return ((rho * c.r) * c.T0) * exp_fin(c.gm1 * ln_pos(rho * c.irho0));
+}
+
+// Step (iv): equilibria of the non-conserved moments from rho, J, zeta and
+// the thermodynamic state.  EQ = 0 compiles the equilibria of section 8 only
+// (every lattice of the launch has eq_kind 0); EQ = -1 selects them per
+// lattice from c.eq_kind.
+template <int EQ>
+__device__ __forceinline__ void equilibria(const Consts& c, double rho,
+                                           double J, double zeta, double u,
+                                           double s, double X, double T,
+                                           double& e_eq, double& psi_eq,
+                                           double& eps_eq) {
+#pragma clang fp contract(off)
+  if (EQ == 0 || c.eq_kind == 0) {
+    const double p = (rho * c.r) * T;
+    e_eq = fma(3.0, fma(J, u, p), -(c.two_l2 * rho));
+    psi_eq = zeta * u;
+    eps_eq = fma(e_eq, s, (c.eps_c * rho) * X);
+  } else if (c.eq_kind == 2) {
+    e_eq = fma(3.0, fma(J, u, iso_pressure(c, rho)), -(c.two_l2 * rho));
+    psi_eq = 0.0;
+    eps_eq = 0.0;
+  } else {
+    e_eq = fma(c.lin[2], zeta, fma(c.lin[1], J, c.lin[0] * rho));
+    psi_eq = fma(c.lin[5], zeta, fma(c.lin[4], J, c.lin[3] * rho));
+    eps_eq = fma(c.lin[8], zeta, fma(c.lin[7], J, c.lin[6] * rho));
+  }
 }
 
 // Steps (ii)-(vi) at one node, in place on the six populations: moments,
 // equilibria, relaxation, back to populations.  Returns u, T and the two
-// factors the source needs: rw = rho / T and w = 1 / T.  EQ = 0 compiles the
-// equilibria of section 8 only (every lattice of the launch has eq_kind 0);
-// EQ = -1 selects them per lattice from c.eq_kind.
+// factors the source needs: rw = rho / T and w = 1 / T.
 template <int EQ>
 __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
                                               double& fp, double& fm,
                                               double& g0, double& gp,
                                               double& gm, double& u, double& T,
                                               double& rw, double& w) {
+#pragma clang fp contract(off)
   // (ii) the conserved moments, eq. M-d1q3q3
   const double rho = density(c, f0, fp, fm);
   const double J = c.mJ * (fp - fm);
@@ -175,28 +212,15 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
   double s, X;
   thermo(c, rho, J, zeta, u, s, X, T);
   double e_eq, psi_eq, eps_eq;
-  if (EQ == 0 || c.eq_kind == 0) {
-    const double p = rho * c.r * T;
-    e_eq = 3.0 * (J * u + p) - c.two_l2 * rho;
-    psi_eq = zeta * u;
-    eps_eq = c.eps_c * rho * X + e_eq * s;
-  } else if (c.eq_kind == 2) {
-    e_eq = 3.0 * (J * u + iso_pressure(c, rho)) - c.two_l2 * rho;
-    psi_eq = 0.0;
-    eps_eq = 0.0;
-  } else {
-    e_eq = c.lin[0] * rho + c.lin[1] * J + c.lin[2] * zeta;
-    psi_eq = c.lin[3] * rho + c.lin[4] * J + c.lin[5] * zeta;
-    eps_eq = c.lin[6] * rho + c.lin[7] * J + c.lin[8] * zeta;
-  }
+  equilibria<EQ>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq);
   // (v) relaxation (eq. relaxation-d1q3q3) and (vi) f* = M^-1 m*, combined:
   // only e, psi, eps change, so f* = f + M^-1 (m* - m).  With fb e =
   // (f+ + f- - 2 f0)/3, gc psi = (g+ - g-)/2 and gb eps = (g+ + g- - 2 g0)/3
   // (products of entries of M and M^-1), the changes are
   //   de = fb (e* - e) = s_e fb e_eq - s_e (f+ + f- - 2 f0)/3, etc.
-  const double de = fma(c.se_fb, e_eq, -c.se_3 * ((fp + fm) - 2.0 * f0));
-  const double dp = fma(c.sp_gc, psi_eq, -c.sp_2 * (gp - gm));
-  const double dx = fma(c.sx_gb, eps_eq, -c.sx_3 * ((gp + gm) - 2.0 * g0));
+  const double de = fma(c.se_fb, e_eq, -(c.se_3 * fma(-2.0, f0, fp + fm)));
+  const double dp = fma(c.sp_gc, psi_eq, -(c.sp_2 * (gp - gm)));
+  const double dx = fma(c.sx_gb, eps_eq, -(c.sx_3 * fma(-2.0, g0, gp + gm)));
   f0 = f0 - de;
   fp = fma(0.5, de, fp);
   fm = fma(0.5, de, fm);
@@ -211,6 +235,7 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
 __device__ __forceinline__ void node_uT(const Consts& c, double f0, double fp,
                                         double fm, double g0, double gp,
                                         double gm, double& u, double& T) {
+#pragma clang fp contract(off)
   const double rho = density(c, f0, fp, fm);
   const double J = c.mJ * (fp - fm);
   const double zeta = c.mz * (g0 + (gp + gm));
@@ -223,39 +248,28 @@ __device__ __forceinline__ void node_uT(const Consts& c, double f0, double fp,
 __device__ __forceinline__ double source_g(const Consts& c, double rw, double w,
                                            double uL, double uR, double TL,
                                            double TR) {
+#pragma clang fp contract(off)
   const double du = uR - uL;
   const double dT = TR - TL;
-  return c.src_g * rw * (du * du + c.cPr * (dT * dT) * w);
+  return (c.src_g * rw) * fma(du, du, (c.cPr * (dT * dT)) * w);
 }
 
 // Equilibrium populations from (rho, J, zeta).
 __device__ __forceinline__ void equilibrium(const Consts& c, double rho,
                                             double J, double zeta, double f[6]) {
+#pragma clang fp contract(off)
   double u, s, X, T;
   thermo(c, rho, J, zeta, u, s, X, T);
   double e_eq, psi_eq, eps_eq;
-  if (c.eq_kind == 0) {
-    const double p = rho * c.r * T;
-    e_eq = 3.0 * (J * u + p) - c.two_l2 * rho;
-    psi_eq = zeta * u;
-    eps_eq = c.eps_c * rho * X + e_eq * s;
-  } else if (c.eq_kind == 2) {
-    e_eq = 3.0 * (J * u + iso_pressure(c, rho)) - c.two_l2 * rho;
-    psi_eq = 0.0;
-    eps_eq = 0.0;
-  } else {
-    e_eq = c.lin[0] * rho + c.lin[1] * J + c.lin[2] * zeta;
-    psi_eq = c.lin[3] * rho + c.lin[4] * J + c.lin[5] * zeta;
-    eps_eq = c.lin[6] * rho + c.lin[7] * J + c.lin[8] * zeta;
-  }
+  equilibria<-1>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq);
   const double fr = c.fa * rho, fe = c.fb * e_eq, fj = c.fc * J;
   f[0] = fr - fe;
-  f[1] = fr + 0.5 * fe + fj;
-  f[2] = fr + 0.5 * fe - fj;
+  f[1] = fma(0.5, fe, fr) + fj;
+  f[2] = fma(0.5, fe, fr) - fj;
   const double gz = c.ga * zeta, ge = c.gb * eps_eq, gj = c.gc * psi_eq;
   f[3] = gz - ge;
-  f[4] = gz + 0.5 * ge + gj;
-  f[5] = gz + 0.5 * ge - gj;
+  f[4] = fma(0.5, ge, gz) + gj;
+  f[5] = fma(0.5, ge, gz) - gj;
 }
 
 // Cross-lane moves of a double over the whole 64-lane wavefront (DPP

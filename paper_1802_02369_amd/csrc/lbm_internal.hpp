@@ -51,6 +51,11 @@ int launch_batch_diag(const Consts* cs, const int64_t* offs, int64_t n_inst,
 // when nsteps >= 2 (so that ping-pong buffering ends in the caller's state).
 std::vector<int> split_steps(int64_t nsteps, int K);
 
+// Tile shape used until lbm_set_tuning / lbm_autotune: the widest tile at
+// most a quarter of the (mean) lattice length len that still leaves >= 1024
+// tiles in total (four workgroups per compute unit), else the narrowest.
+lbm_tuning default_tuning(int64_t len, int64_t total);
+
 // Tile shapes the autotuner tries (P, K, waves per tile).
 std::vector<lbm_tuning> tuning_candidates();
 

@@ -78,7 +78,8 @@ def test_init_and_workspace_and_tuning_host():
     assert L.lbm_workspace_bytes(None, lbm.WS_STEP) == 0
     for bad in [(lbm.KERNEL_BLOCKED, 3, 4, 4), (lbm.KERNEL_BLOCKED, 4, 256, 4),
                 (lbm.KERNEL_BLOCKED, 4, 0, 4), (lbm.KERNEL_BLOCKED, 2, 4, 3),
-                (lbm.KERNEL_BLOCKED, 8, 4, 4), (7, 2, 4, 4)]:
+                (lbm.KERNEL_BLOCKED, 6, 4, 4), (lbm.KERNEL_BLOCKED, 16, 4, 4),
+                (lbm.KERNEL_BLOCKED, 8, 512, 4), (7, 2, 4, 4)]:
         t = lbm.CTuning(*bad)
         assert L.lbm_set_tuning(h, ctypes.byref(t)) == lbm.LBM_EINVAL
     t = lbm.CTuning(lbm.KERNEL_BLOCKED, 4, 15, 2)
@@ -98,3 +99,34 @@ def test_init_and_workspace_and_tuning_host():
     assert L.lbm_step(h, ctypes.c_void_p(4096), ctypes.c_void_p(1 << 30), nb,
                       0) == lbm.LBM_OK
     L.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("n,shape", [
+    (1 << 24, (8, 32, 4)),   # wide tiles: 8739 tiles of 1920 output nodes
+    (1 << 21, (8, 32, 4)),
+    (1 << 20, (4, 16, 4)),   # too few P = 8 tiles for 4 workgroups per CU
+    (8192, (2, 8, 1)),       # small lattices: the narrowest tile
+    (3, (2, 8, 1))])
+def test_default_tuning_follows_lattice_length(n, shape):
+    rc, h = _init(n)
+    assert rc == lbm.LBM_OK
+    t = lbm.CTuning()
+    assert lbm.lib().lbm_get_tuning(h, ctypes.byref(t)) == lbm.LBM_OK
+    assert (t.kernel, t.nodes_per_lane, t.steps_per_launch,
+            t.waves_per_group) == (lbm.KERNEL_BLOCKED,) + shape
+    lbm.lib().lbm_destroy(h)
+
+
+def test_batch_default_tuning_uses_mean_length():
+    """4096 lattices of ~4.6k nodes: P = 8 tiles (2048 wide) would waste a
+    third of each lattice's work, so the default is the 1024-wide P = 4 tile."""
+    n_inst, L = 4096, 4615
+    offs = (ctypes.c_int64 * (n_inst + 1))(*[i * L for i in range(n_inst + 1)])
+    p = lbm.Params(s_psi=1.0).c()
+    ps = (type(p) * n_inst)(*([p] * n_inst))
+    b = ctypes.c_void_p()
+    assert lbm.lib().lbm_batch_init(ctypes.byref(b), n_inst, offs, ps, None) == lbm.LBM_OK
+    t = lbm.CTuning()
+    assert lbm.lib().lbm_batch_get_tuning(b, ctypes.byref(t)) == lbm.LBM_OK
+    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (4, 16, 4)
+    lbm.lib().lbm_batch_destroy(b)

@@ -66,7 +66,7 @@ def test_one_adjoint_step(pname, n, adj):
 
 
 @pytest.mark.parametrize("kernel", ["plain", "blocked", "blocked_p4w2k5",
-                                    "plainfwd"])
+                                    "blocked_p8w2k6", "plainfwd"])
 @pytest.mark.parametrize("pname,n,steps,ckpt", [
     ("paper", 64, 40, 7), ("odd", 300, 33, 33), ("nosource", 97, 25, 1),
     ("linear", 260, 18, 5), ("odd", 1200, 50, 8), ("fluid", 700, 37, 20),
@@ -88,6 +88,9 @@ def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
     elif kernel == "blocked_p4w2k5":
         lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
         lat.set_tuning(nodes_per_lane=4, steps_per_launch=5, waves_per_group=2)
+    elif kernel == "blocked_p8w2k6":
+        lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+        lat.set_tuning(nodes_per_lane=8, steps_per_launch=6, waves_per_group=2)
     aws = lat.adjoint_workspace(steps, ckpt, dev())
     r_, J_, z_ = T(rho), T(J), T(zeta)
     f = lat.equilibrium(r_, J_, z_)
@@ -100,6 +103,24 @@ def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
         w = np.abs(want).max()
         assert np.abs(got.cpu().numpy() - want).max() <= 1e-10 * w + 1e-300
     np.testing.assert_allclose(r, sb, rtol=1e-10, atol=1e-12 * np.abs(sb).max())
+
+
+def test_blocked_adjoint_rejects_p8_with_8_waves():
+    """The reverse tile kernel has no form for P = 8 with 8 wavefronts: the
+    checkpointed forward refuses it before any launch; the one-step adjoint
+    kernel accepts the same tile shape."""
+    po = oracle_params("paper")
+    n = 3000
+    lat = lbm().Lattice(n, gpu_params(po))
+    lat.set_tuning(nodes_per_lane=8, steps_per_launch=16, waves_per_group=8)
+    lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+    aws = lat.adjoint_workspace(10, 5, dev())
+    f = T(random_state(np.random.default_rng(3), n, po))
+    with pytest.raises(lbm().LBMError) as e:
+        lat.forward_ckpt(f, 10, 5, aws)
+    assert e.value.code == lbm().LBM_ENOTSUP
+    lat.set_adjoint_kernel(lbm().KERNEL_PLAIN)
+    lat.forward_ckpt(f, 10, 5, aws)
 
 
 def test_graph_adjoint_matches_direct():

@@ -49,7 +49,7 @@ def oracle_runs(states, params, steps, workers=16):
 
 RAGGED = [3, 5, 64, 100, 513, 1000, 2049, 7]
 PNAMES = ["paper", "odd", "nosource", "linear", "odd", "paper", "odd", "nosource"]
-SHAPES = [(2, 8, 4), (4, 5, 2), (2, 16, 8), (2, 1, 1)]
+SHAPES = [(2, 8, 4), (4, 5, 2), (2, 16, 8), (2, 1, 1), (8, 12, 2), (8, 32, 4)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -69,6 +69,36 @@ def test_ragged_batch(shape, steps):
     want = oracle_runs(states, params, steps)
     for i, (g, w) in enumerate(zip(got, want)):
         assert max_err(g, w) < TOL, (i, RAGGED[i], PNAMES[i])
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batch_bitwise_equals_single_lattice(mixed):
+    """A lattice advanced inside a batch (any neighbours, any tile shape)
+    ends bitwise equal to the same lattice advanced alone: the kernels share
+    one rounding sequence per node-update.  mixed: the batch also holds
+    lattices with linear equilibria (the per-lattice equilibrium switch)."""
+    rng = np.random.default_rng(5)
+    lens = [6007, 100, 4099, 3]
+    names = ["paper", "linear" if mixed else "odd", "odd", "paper"]
+    params = [oracle_params(p) for p in names]
+    states = [random_state(rng, L, p, amp=0.1, u=0.05, ds=0.1)
+              for L, p in zip(lens, params)]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    say(f"batch vs single bitwise mixed={mixed}")
+    singles = []
+    for s, p in zip(states, params):
+        lat = lbm().Lattice(s.shape[1], gpu_params(p))
+        f = torch.from_numpy(s.copy()).to(dev())
+        lat.step(f, 29)
+        singles.append(f.cpu().numpy())
+        assert np.isfinite(singles[-1]).all()
+    for shape in [(2, 8, 4), (8, 32, 4), (4, 5, 2)]:
+        b = lbm().Batch(offsets, [gpu_params(p) for p in params])
+        b.set_tuning(*shape)
+        f = torch.from_numpy(pack(states)).to(dev())
+        b.run(f, 29, use_graph=False)
+        for i, g in enumerate(unpack(f.cpu().numpy(), offsets)):
+            assert np.array_equal(g, singles[i]), (shape, i)
 
 
 def test_graph_replays_match_direct_launches():
