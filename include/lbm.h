@@ -138,7 +138,8 @@ size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
  * 1 <= K, 4K < 64 P waves_per_group, waves_per_group in {1,2,4,8}).
  * The blocked kernel gives each workgroup of waves_per_group wavefronts a
  * tile of 64 P waves_per_group nodes held in registers for K steps.  The
- * default is the blocked kernel with P = 8, K = 32, 4 wavefronts.  Every
+ * default depends on the lattice length (P = 8, K = 40, 4 wavefronts for long
+ * lattices; narrower tiles for short ones or few tiles).  Every
  * kernel and tile shape rounds each node-update identically: results are
  * bitwise independent of the tuning. */
 int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);

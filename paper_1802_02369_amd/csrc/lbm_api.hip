@@ -41,7 +41,7 @@ std::vector<int> split_steps(int64_t nsteps, int K) {
 
 std::vector<lbm_tuning> tuning_candidates() {
   std::vector<lbm_tuning> v;
-  const int Ps[] = {2, 4, 8}, Ws[] = {2, 4, 8}, Ks[] = {8, 12, 16, 24, 32};
+  const int Ps[] = {2, 4, 8}, Ws[] = {2, 4, 8}, Ks[] = {8, 12, 16, 24, 32, 40};
   for (int P : Ps)
     for (int W : Ws)
       for (int K : Ks)
@@ -52,7 +52,7 @@ std::vector<lbm_tuning> tuning_candidates() {
 lbm_tuning default_tuning(int64_t len, int64_t total) {
   // tile shapes from the widest down, with the K that measured best for each
   static const lbm_tuning shapes[] = {
-      {LBM_KERNEL_BLOCKED, 8, 32, 4}, {LBM_KERNEL_BLOCKED, 4, 16, 4},
+      {LBM_KERNEL_BLOCKED, 8, 40, 4}, {LBM_KERNEL_BLOCKED, 4, 16, 4},
       {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 8, 2},
       {LBM_KERNEL_BLOCKED, 2, 8, 1}};
   for (const lbm_tuning& t : shapes) {

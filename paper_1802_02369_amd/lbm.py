@@ -218,7 +218,7 @@ class Lattice:
         return self.ws
 
     def set_tuning(self, kernel=KERNEL_BLOCKED, nodes_per_lane=8,
-                   steps_per_launch=32, waves_per_group=4):
+                   steps_per_launch=40, waves_per_group=4):
         t = CTuning(kernel, nodes_per_lane, steps_per_launch, waves_per_group)
         check(lib().lbm_set_tuning(self._h, ctypes.byref(t)))
 

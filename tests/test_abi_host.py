@@ -102,8 +102,8 @@ def test_init_and_workspace_and_tuning_host():
 
 
 @pytest.mark.parametrize("n,shape", [
-    (1 << 24, (8, 32, 4)),   # wide tiles: 8739 tiles of 1920 output nodes
-    (1 << 21, (8, 32, 4)),
+    (1 << 24, (8, 40, 4)),   # wide tiles: 8887 tiles of 1888 output nodes
+    (1 << 21, (8, 40, 4)),
     (1 << 20, (4, 16, 4)),   # too few P = 8 tiles for 4 workgroups per CU
     (8192, (2, 8, 1)),       # small lattices: the narrowest tile
     (3, (2, 8, 1))])
