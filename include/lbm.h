@@ -113,7 +113,7 @@ int lbm_coupled_rates(double s_e, double gamma, double prandtl, double* s_psi,
 
 /* ----------------------------------------------------- single lattice */
 
-/* Creates a handle for one periodic lattice of n >= 3 nodes.  Validates the
+/* Creates a handle for one periodic lattice of 3 <= n <= 2^36 nodes.  Validates the
  * constants (all positive, gamma > 1, rates in (0, 2)).  stream: see above.
  * No device memory is allocated.  The handle owns host state only. */
 int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream);
@@ -172,12 +172,13 @@ int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,
                     double out[8]);
 
 /* Autotuner (synchronising).  Times the blocked kernel on the caller's state
- * f for probe_steps time steps with each candidate shape (P in {2,4}, waves
- * per tile in {2,4,8}, K in {8,12,16,24,32}, halo recomputation at most a
+ * f for probe_steps time steps with each candidate shape (P in {2,4,8}, waves
+ * per tile in {2,4,8}, K in {8,12,16,24,32,40}, halo recomputation at most a
  * quarter of the tile) plus the one-step kernel, keeps the fastest, and
  * restores f.  ws: lbm_workspace_bytes(h, LBM_WS_TUNE) bytes.  cache_path
- * (may be NULL) names a JSON file mapping "<gfx arch>/<kind>/<size class>"
- * to the chosen shape; a hit skips the timing, a miss adds the entry.  The
+ * (may be NULL) names a JSON file mapping "<gfx arch>/<kind>/<size class>/
+ * <kernel generation>" to the chosen shape; a hit skips the timing, a miss
+ * adds the entry.  The
  * chosen shape becomes the handle's tuning and is returned in *out (may be
  * NULL). */
 int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,

@@ -29,13 +29,14 @@ int check_tuning(const lbm_tuning* t) {
   return LBM_OK;
 }
 
-std::vector<int> split_steps(int64_t nsteps, int K) {
-  std::vector<int> out;
+StepSplit split_steps(int64_t nsteps, int K) {
+  StepSplit out;
   if (nsteps <= 0 || K < 1) return out;
   int64_t L = (nsteps + K - 1) / K;
   if ((L & 1) && nsteps > L) ++L;
-  const int64_t base = nsteps / L, extra = nsteps % L;
-  for (int64_t i = 0; i < L; ++i) out.push_back((int)(base + (i < extra ? 1 : 0)));
+  out.count = L;
+  out.base = nsteps / L;
+  out.extra = nsteps % L;
   return out;
 }
 
@@ -98,7 +99,8 @@ int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream) {
   *h = nullptr;
   if (n < 3) return set_err(LBM_EINVAL, "lattice needs n >= 3 nodes (got %lld)",
                             (long long)n);
-  if (n > (int64_t(1) << 40)) return set_err(LBM_EINVAL, "n too large");
+  if (n > kMaxNodes)
+    return set_err(LBM_EINVAL, "n = %lld exceeds 2^36 nodes", (long long)n);
   Consts c;
   int rc = make_consts(p, &c);
   if (rc) return rc;

@@ -195,6 +195,10 @@ namespace {
 
 int log2_class(double x) { return x > 1 ? (int)std::lround(std::log2(x)) : 0; }
 
+// Generation of the tile kernels, the last component of every tuning-cache
+// key: entries measured on kernels of another generation are not reused.
+constexpr const char* kKernelGeneration = "/k3";
+
 // Times `run(t)` for each candidate on the state f, restoring f from
 // `backup` before each run and at the end; returns the fastest.
 template <class Prepare, class Run>
@@ -257,7 +261,8 @@ int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
   if (overlaps(f, sbytes, ws, ws_bytes))
     return set_err(LBM_EINVAL, "f and ws overlap");
   const std::string key =
-      gpu_arch_name() + "/single/n" + std::to_string(log2_class((double)h->n));
+      gpu_arch_name() + "/single/n" + std::to_string(log2_class((double)h->n)) +
+      kKernelGeneration;
   lbm_tuning best{};
   if (!tune_cache_get(cache_path, key, &best)) {
     std::vector<lbm_tuning> cands = tuning_candidates();
@@ -292,8 +297,9 @@ int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
                      "lattice %lld has length %lld (offsets must increase by "
                      ">= 3)",
                      (long long)i, (long long)(offsets[i + 1] - offsets[i]));
-  if (offsets[n_inst] > (int64_t(1) << 40))
-    return set_err(LBM_EINVAL, "batch too large");
+  if (offsets[n_inst] > kMaxNodes)
+    return set_err(LBM_EINVAL, "batch of %lld nodes exceeds 2^36",
+                   (long long)offsets[n_inst]);
   lbm_batch* x = new lbm_batch;
   x->n_inst = n_inst;
   x->n_total = offsets[n_inst];
@@ -497,7 +503,7 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   const double mean_len = (double)b->n_total / (double)b->n_inst;
   const std::string key = gpu_arch_name() + "/batch/N" +
                           std::to_string(log2_class((double)b->n_total)) + "/L" +
-                          std::to_string(log2_class(mean_len));
+                          std::to_string(log2_class(mean_len)) + kKernelGeneration;
   lbm_tuning best = b->tune;
   if (!tune_cache_get(cache_path, key, &best)) {
     int64_t mx = 0;

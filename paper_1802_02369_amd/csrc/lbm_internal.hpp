@@ -47,9 +47,30 @@ int launch_batch_moments(const Consts* cs, const int64_t* offs, int64_t n_inst,
 int launch_batch_diag(const Consts* cs, const int64_t* offs, int64_t n_inst,
                       const double* f, int64_t S, double* out, hipStream_t s);
 
+// Largest lattice (or batch) in nodes: keeps every grid dimension and tile
+// index of every kernel within 32 bits (3.3 TB per state, beyond any device).
+constexpr int64_t kMaxNodes = int64_t(1) << 36;
+
 // Splits nsteps into launches of at most K steps, an even number of them
 // when nsteps >= 2 (so that ping-pong buffering ends in the caller's state).
-std::vector<int> split_steps(int64_t nsteps, int K);
+// The sizes are described, not stored: a run of any length costs O(1) host
+// memory; iterate with a range-for.
+struct StepSplit {
+  int64_t count = 0, base = 0, extra = 0;
+  struct It {
+    const StepSplit* s;
+    int64_t i;
+    int operator*() const { return (int)(s->base + (i < s->extra ? 1 : 0)); }
+    It& operator++() {
+      ++i;
+      return *this;
+    }
+    bool operator!=(const It& o) const { return i != o.i; }
+  };
+  It begin() const { return It{this, 0}; }
+  It end() const { return It{this, count}; }
+};
+StepSplit split_steps(int64_t nsteps, int K);
 
 // Tile shape used until lbm_set_tuning / lbm_autotune: the widest tile at
 // most a quarter of the (mean) lattice length len that still leaves >= 1024

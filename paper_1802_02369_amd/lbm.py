@@ -371,7 +371,7 @@ class Batch:
                                   device=device)
         return self.ws
 
-    def set_tuning(self, nodes_per_lane=2, steps_per_launch=16,
+    def set_tuning(self, nodes_per_lane=4, steps_per_launch=16,
                    waves_per_group=4, device="cuda"):
         t = CTuning(KERNEL_BLOCKED, nodes_per_lane, steps_per_launch,
                     waves_per_group)

@@ -51,6 +51,7 @@ def _init(n, **kw):
 @pytest.mark.parametrize("n,kw", [
     (2, {}),
     (0, {}),
+    ((1 << 36) + 1, {}),
     (16, dict(s_e=2.0)),
     (16, dict(s_e=0.0)),
     (16, dict(s_eps=-1.0)),
