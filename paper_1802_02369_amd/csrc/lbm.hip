@@ -105,6 +105,7 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->cp = cp;
   c->se_fb = p->s_e * c->fb;
   c->se_3 = p->s_e / 3.0;
+  c->se_il2 = p->s_e / (r0 * l * l);
   c->sp_gc = p->s_psi * c->gc;
   c->sp_2 = p->s_psi / 2.0;
   c->sx_gb = p->s_eps * c->gb;

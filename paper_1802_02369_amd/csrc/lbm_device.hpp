@@ -40,6 +40,7 @@ struct Consts {
   // Steps (v)-(vi) in population space (see collide_local): rate times the
   // M^-1 entry of each non-conserved moment, and rate / 3, rate / 2.
   double se_fb, se_3;  // s_e fb, s_e / 3
+  double se_il2;       // s_e / (rho0 lambda^2)
   double sp_gc, sp_2;  // s_psi gc, s_psi / 2
   double sx_gb, sx_3;  // s_eps gb, s_eps / 3
   double src_g;        // ga src_c: the source increment of each g population
@@ -96,11 +97,9 @@ constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
 __device__ __forceinline__ double ln_pos(double x) {
 #pragma clang fp contract(off)
   double m = __builtin_amdgcn_frexp_mant(x);
-  int k = __builtin_amdgcn_frexp_exp(x);
-  if (m < kSqrtHalf) {
-    m = m + m;
-    k -= 1;
-  }
+  const int lo = m < kSqrtHalf ? 1 : 0;
+  m = __builtin_amdgcn_ldexp(m, lo);  // exact doubling
+  const int k = __builtin_amdgcn_frexp_exp(x) - lo;
   const double z = (m - 1.0) * recip(m + 1.0);
   const double w = z * z;
   double q = 0x1.2b584c80de001p-3;
@@ -113,7 +112,10 @@ __device__ __forceinline__ double ln_pos(double x) {
   const double lm = fma(z * w, q, z + z);
   const double kd = (double)k;
   const double r = fma(kd, kLn2Hi, fma(kd, kLn2Lo, lm));
-  return x > 0.0 ? r : __builtin_nan("");
+  // x <= 0: replace the high word by a quiet-NaN pattern (one select)
+  const uint64_t b = __builtin_bit_cast(uint64_t, r);
+  const uint32_t hi = x > 0.0 ? (uint32_t)(b >> 32) : 0x7ff80000u;
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (b & 0xffffffffu));
 }
 
 // e^x for the moderate arguments of the equation of state.  Method (Cody &
@@ -171,23 +173,27 @@ __device__ __forceinline__ double iso_pressure(const Consts& c, double rho) {
 // the thermodynamic state.  EQ = 0 compiles the equilibria of section 8 only
 // (every lattice of the launch has eq_kind 0); EQ = -1 selects them per
 // lattice from c.eq_kind.
+// jup receives J u + p where e_eq = 3 (J u + p) - 2 lambda^2 rho (every kind
+// but the linear ones).
 template <int EQ>
 __device__ __forceinline__ void equilibria(const Consts& c, double rho,
                                            double J, double zeta, double u,
                                            double s, double X, double T,
                                            double& e_eq, double& psi_eq,
-                                           double& eps_eq) {
+                                           double& eps_eq, double& jup) {
 #pragma clang fp contract(off)
   if (EQ == 0 || c.eq_kind == 0) {
-    const double p = (rho * c.r) * T;
-    e_eq = fma(3.0, fma(J, u, p), -(c.two_l2 * rho));
+    jup = fma(J, u, (rho * c.r) * T);
+    e_eq = fma(3.0, jup, -(c.two_l2 * rho));
     psi_eq = zeta * u;
     eps_eq = fma(e_eq, s, (c.eps_c * rho) * X);
   } else if (c.eq_kind == 2) {
-    e_eq = fma(3.0, fma(J, u, iso_pressure(c, rho)), -(c.two_l2 * rho));
+    jup = fma(J, u, iso_pressure(c, rho));
+    e_eq = fma(3.0, jup, -(c.two_l2 * rho));
     psi_eq = 0.0;
     eps_eq = 0.0;
   } else {
+    jup = 0.0;
     e_eq = fma(c.lin[2], zeta, fma(c.lin[1], J, c.lin[0] * rho));
     psi_eq = fma(c.lin[5], zeta, fma(c.lin[4], J, c.lin[3] * rho));
     eps_eq = fma(c.lin[8], zeta, fma(c.lin[7], J, c.lin[6] * rho));
@@ -211,14 +217,21 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
   // (iv) equilibria
   double s, X;
   thermo(c, rho, J, zeta, u, s, X, T);
-  double e_eq, psi_eq, eps_eq;
-  equilibria<EQ>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq);
+  double e_eq, psi_eq, eps_eq, jup;
+  equilibria<EQ>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq, jup);
   // (v) relaxation (eq. relaxation-d1q3q3) and (vi) f* = M^-1 m*, combined:
   // only e, psi, eps change, so f* = f + M^-1 (m* - m).  With fb e =
   // (f+ + f- - 2 f0)/3, gc psi = (g+ - g-)/2 and gb eps = (g+ + g- - 2 g0)/3
   // (products of entries of M and M^-1), the changes are
   //   de = fb (e* - e) = s_e fb e_eq - s_e (f+ + f- - 2 f0)/3, etc.
-  const double de = fma(c.se_fb, e_eq, -(c.se_3 * fma(-2.0, f0, fp + fm)));
+  // When e_eq = 3 (J u + p) - 2 lambda^2 rho, fb e_eq = (J u + p)/(rho0
+  // lambda^2) - 2 (f0 + f+ + f-)/3 (rho = rho0 (f0 + f+ + f-)), and de
+  // reduces to s_e [(J u + p)/(rho0 lambda^2) - (f+ + f-)].
+  double de;
+  if (EQ == 0 || c.eq_kind != 1)
+    de = fma(c.se_il2, jup, -(c.s_e * (fp + fm)));
+  else
+    de = fma(c.se_fb, e_eq, -(c.se_3 * fma(-2.0, f0, fp + fm)));
   const double dp = fma(c.sp_gc, psi_eq, -(c.sp_2 * (gp - gm)));
   const double dx = fma(c.sx_gb, eps_eq, -(c.sx_3 * fma(-2.0, g0, gp + gm)));
   f0 = f0 - de;
@@ -260,8 +273,8 @@ __device__ __forceinline__ void equilibrium(const Consts& c, double rho,
 #pragma clang fp contract(off)
   double u, s, X, T;
   thermo(c, rho, J, zeta, u, s, X, T);
-  double e_eq, psi_eq, eps_eq;
-  equilibria<-1>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq);
+  double e_eq, psi_eq, eps_eq, jup;
+  equilibria<-1>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq, jup);
   const double fr = c.fa * rho, fe = c.fb * e_eq, fj = c.fc * J;
   f[0] = fr - fe;
   f[1] = fma(0.5, fe, fr) + fj;
