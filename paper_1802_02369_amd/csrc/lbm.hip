@@ -103,14 +103,13 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->gc = 1.0 / (2.0 * r0 * cp * l);
   c->gamma = g;
   c->cp = cp;
-  c->se_fb = p->s_e * c->fb;
   c->se_3 = p->s_e / 3.0;
-  c->se_il2 = p->s_e / (r0 * l * l);
-  c->sp_gc = p->s_psi * c->gc;
   c->sp_2 = p->s_psi / 2.0;
-  c->sx_gb = p->s_eps * c->gb;
   c->sx_3 = p->s_eps / 3.0;
-  c->src_g = c->ga * c->src_c;
+  c->hP = p->c0 * p->c0 / (g * l * l);
+  c->two_g = 2.0 / g;
+  c->hS = c->src_c * l * l / (3.0 * cp * c->T0);
+  c->hC = cp * c->T0 / (p->prandtl * l * l);
   c->xs0l = c->xs0 - c->gm1 * std::log(r0);
   c->eq_kind = p->eq_kind;
   if (p->eq_kind == 1) {
@@ -134,6 +133,18 @@ int make_consts(const lbm_params* p, Consts* c) {
     c->lin[5] = p->u0_lin;
     c->lin[8] = p->alpha * l * l;
   }
+  // the same linear equilibria in scaled moments: e / (rho0 lambda^2),
+  // psi / (rho0 cp lambda), eps / (rho0 cp lambda^2) in terms of
+  // rho / rho0, J / (rho0 lambda), zeta / (rho0 cp)
+  c->hlin[0] = c->lin[0] / (l * l);
+  c->hlin[1] = c->lin[1] / l;
+  c->hlin[2] = c->lin[2] * cp / (l * l);
+  c->hlin[3] = c->lin[3] / (cp * l);
+  c->hlin[4] = c->lin[4] / cp;
+  c->hlin[5] = c->lin[5] / l;
+  c->hlin[6] = c->lin[6] / (cp * l * l);
+  c->hlin[7] = c->lin[7] / (cp * l);
+  c->hlin[8] = c->lin[8] / (l * l);
   return LBM_OK;
 }
 

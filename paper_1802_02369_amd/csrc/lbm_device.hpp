@@ -37,14 +37,13 @@ struct Consts {
   // linear equilibria (section 7, and the thermal scheme of section 4):
   // e = l[0] rho + l[1] J + l[2] zeta, psi = l[3..5] . W, eps = l[6..8] . W
   double lin[9];
-  // Steps (v)-(vi) in population space (see collide_local): rate times the
-  // M^-1 entry of each non-conserved moment, and rate / 3, rate / 2.
-  double se_fb, se_3;  // s_e fb, s_e / 3
-  double se_il2;       // s_e / (rho0 lambda^2)
-  double sp_gc, sp_2;  // s_psi gc, s_psi / 2
-  double sx_gb, sx_3;  // s_eps gb, s_eps / 3
-  double src_g;        // ga src_c: the source increment of each g population
   double xs0l;         // xs0 - (gamma - 1) ln rho0
+  // The time step in scaled moments (see collide_local):
+  double se_3, sp_2, sx_3;  // s_e / 3, s_psi / 2, s_eps / 3
+  double hP;                // c0^2 / (gamma lambda^2) = p0 / (rho0 lambda^2)
+  double two_g;             // 2 / gamma
+  double hS, hC;            // source: src_c lambda^2 / (3 cp T0), cp T0 / (Pr lambda^2)
+  double hlin[9];           // linear equilibria in scaled moments
   int32_t eq_kind;  // 0 section 8, 1 linear, 2 isentropic fluid D1Q3
   int32_t pad;
 };
@@ -69,15 +68,14 @@ __device__ __forceinline__ double density(const Consts& c, double f0, double fp,
 }
 
 // 1/x for the positive normal numbers of the step (rho, T): the hardware
-// reciprocal estimate refined by two Newton-Raphson iterations
-// r <- r + r (1 - x r), within one ulp of 1/x (not always correctly rounded).
+// reciprocal estimate r (relative error e = 1 - x r below 2^-22) refined by
+// one third-order step r (1 + e + e^2) = (1 - e^3)/x, within one ulp of 1/x
+// (not always correctly rounded).
 __device__ __forceinline__ double recip(double x) {
 #pragma clang fp contract(off)
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 // ln 2 = kLn2Hi + kLn2Lo: kLn2Hi is ln 2 rounded to 42 significant bits, so
@@ -89,7 +87,7 @@ constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
 
 // Natural logarithm of a positive finite x.  Method: x = m 2^k with m in
 // [sqrt(1/2), sqrt(2)); ln m = 2 atanh(z) with z = (m-1)/(m+1), |z| < 0.172,
-// written 2z + z w Q(w), w = z^2, where Q is a degree-6 Chebyshev fit of
+// written z (2 + w Q(w)), w = z^2, where Q is a degree-6 Chebyshev fit of
 // (2 atanh(z) - 2z)/z^3 on [0, 0.02944] (relative error of the fit below
 // 5e-18; coefficients from csrc/gen_poly.py); ln x = k ln 2 + ln m with ln 2
 // in two parts (the additive reduction of Cody & Waite).  Error a few ulp.
@@ -109,7 +107,7 @@ __device__ __forceinline__ double ln_pos(double x) {
   q = fma(q, w, 0x1.2492492df14bfp-2);
   q = fma(q, w, 0x1.99999999952e2p-2);
   q = fma(q, w, 0x1.5555555555558p-1);
-  const double lm = fma(z * w, q, z + z);
+  const double lm = z * fma(w, q, 2.0);
   const double kd = (double)k;
   const double r = fma(kd, kLn2Hi, fma(kd, kLn2Lo, lm));
   // x <= 0: replace the high word by a quiet-NaN pattern (one select)
@@ -170,39 +168,56 @@ __device__ __forceinline__ double iso_pressure(const Consts& c, double rho) {
 }
 
 // Step (iv): equilibria of the non-conserved moments from rho, J, zeta and
-// the thermodynamic state.  EQ = 0 compiles the equilibria of section 8 only
-// (every lattice of the launch has eq_kind 0); EQ = -1 selects them per
-// lattice from c.eq_kind.
-// jup receives J u + p where e_eq = 3 (J u + p) - 2 lambda^2 rho (every kind
-// but the linear ones).
+// the thermodynamic state (physical units; the initialisation uses them).
 template <int EQ>
 __device__ __forceinline__ void equilibria(const Consts& c, double rho,
                                            double J, double zeta, double u,
                                            double s, double X, double T,
                                            double& e_eq, double& psi_eq,
-                                           double& eps_eq, double& jup) {
+                                           double& eps_eq) {
 #pragma clang fp contract(off)
   if (EQ == 0 || c.eq_kind == 0) {
-    jup = fma(J, u, (rho * c.r) * T);
-    e_eq = fma(3.0, jup, -(c.two_l2 * rho));
+    e_eq = fma(3.0, fma(J, u, (rho * c.r) * T), -(c.two_l2 * rho));
     psi_eq = zeta * u;
     eps_eq = fma(e_eq, s, (c.eps_c * rho) * X);
   } else if (c.eq_kind == 2) {
-    jup = fma(J, u, iso_pressure(c, rho));
-    e_eq = fma(3.0, jup, -(c.two_l2 * rho));
+    e_eq = fma(3.0, fma(J, u, iso_pressure(c, rho)), -(c.two_l2 * rho));
     psi_eq = 0.0;
     eps_eq = 0.0;
   } else {
-    jup = 0.0;
     e_eq = fma(c.lin[2], zeta, fma(c.lin[1], J, c.lin[0] * rho));
     psi_eq = fma(c.lin[5], zeta, fma(c.lin[4], J, c.lin[3] * rho));
     eps_eq = fma(c.lin[8], zeta, fma(c.lin[7], J, c.lin[6] * rho));
   }
 }
 
+// The time step works in scaled moments, which removes the scale factors
+// rho0, lambda, cp, T0 from the per-node arithmetic:
+//   rh = rho/rho0 = f0 + f+ + f-,  Jh = J/(rho0 lambda) = f+ - f-,
+//   zh = zeta/(rho0 cp) = g0 + g+ + g-,  uh = u/lambda,  sh = s/cp,
+//   Th = T/T0 = e^X,  X = (gamma-1) ln rh + gamma sh - gamma s0/cp,
+// and the equilibria divided by the scale of their moment (rho0 lambda^2 for
+// e, rho0 cp lambda for psi, rho0 cp lambda^2 for eps):
+//   eh = 3 (Jh uh + hP rh Th) - 2 rh,  psih = zh uh,
+//   epsh = (2/gamma) rh X + eh sh,  hP = c0^2/(gamma lambda^2).
+// (With rho0 = 1, rh is the density summed in the order of eq. M-d1q3q3.)
+__device__ __forceinline__ void thermo_scaled(const Consts& c, double rh,
+                                              double Jh, double zh, double& uh,
+                                              double& sh, double& X,
+                                              double& Th) {
+#pragma clang fp contract(off)
+  const double ir = recip(rh);
+  uh = Jh * ir;
+  sh = zh * ir;
+  X = fma(c.gm1, ln_pos(rh), fma(c.gamma, sh, c.xs0));
+  Th = exp_fin(X);
+}
+
 // Steps (ii)-(vi) at one node, in place on the six populations: moments,
-// equilibria, relaxation, back to populations.  Returns u, T and the two
-// factors the source needs: rw = rho / T and w = 1 / T.
+// equilibria, relaxation, back to populations.  Returns uh, Th and the two
+// factors the source needs: rw = rh / Th and w = 1 / Th.  EQ = 0 compiles
+// the equilibria of section 8 only (every lattice of the launch has
+// eq_kind 0); EQ = -1 selects them per lattice from c.eq_kind.
 template <int EQ>
 __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
                                               double& fp, double& fm,
@@ -210,30 +225,47 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
                                               double& gm, double& u, double& T,
                                               double& rw, double& w) {
 #pragma clang fp contract(off)
-  // (ii) the conserved moments, eq. M-d1q3q3
-  const double rho = density(c, f0, fp, fm);
-  const double J = c.mJ * (fp - fm);
-  const double zeta = c.mz * (g0 + (gp + gm));
+  // (ii) the conserved moments, eq. M-d1q3q3, scaled
+  const double rh = (f0 + fp) + fm;
+  const double Jh = fp - fm;
+  const double sg = gp + gm;
+  const double zh = g0 + sg;
   // (iv) equilibria
-  double s, X;
-  thermo(c, rho, J, zeta, u, s, X, T);
-  double e_eq, psi_eq, eps_eq, jup;
-  equilibria<EQ>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq, jup);
+  double sh, X;
+  thermo_scaled(c, rh, Jh, zh, u, sh, X, T);
+  double jup, eh, psih, epsh;
+  if (EQ == 0 || c.eq_kind == 0) {
+    jup = fma(Jh, u, (c.hP * rh) * T);
+    eh = fma(-2.0, rh, 3.0 * jup);
+    psih = zh * u;
+    epsh = fma(eh, sh, (c.two_g * rh) * X);
+  } else if (c.eq_kind == 2) {
+    jup = fma(Jh, u, (c.hP * rh) * exp_fin(c.gm1 * ln_pos(rh)));
+    eh = fma(-2.0, rh, 3.0 * jup);
+    psih = 0.0;
+    epsh = 0.0;
+  } else {
+    jup = 0.0;
+    eh = fma(c.hlin[2], zh, fma(c.hlin[1], Jh, c.hlin[0] * rh));
+    psih = fma(c.hlin[5], zh, fma(c.hlin[4], Jh, c.hlin[3] * rh));
+    epsh = fma(c.hlin[8], zh, fma(c.hlin[7], Jh, c.hlin[6] * rh));
+  }
   // (v) relaxation (eq. relaxation-d1q3q3) and (vi) f* = M^-1 m*, combined:
-  // only e, psi, eps change, so f* = f + M^-1 (m* - m).  With fb e =
-  // (f+ + f- - 2 f0)/3, gc psi = (g+ - g-)/2 and gb eps = (g+ + g- - 2 g0)/3
-  // (products of entries of M and M^-1), the changes are
-  //   de = fb (e* - e) = s_e fb e_eq - s_e (f+ + f- - 2 f0)/3, etc.
-  // When e_eq = 3 (J u + p) - 2 lambda^2 rho, fb e_eq = (J u + p)/(rho0
-  // lambda^2) - 2 (f0 + f+ + f-)/3 (rho = rho0 (f0 + f+ + f-)), and de
-  // reduces to s_e [(J u + p)/(rho0 lambda^2) - (f+ + f-)].
+  // only e, psi, eps change, so f* = f + M^-1 (m* - m).  The entries of M^-1
+  // turn the changes into
+  //   de = fb (e* - e) = (s_e/3) (eh - (f+ + f- - 2 f0)),
+  //   dp = gc (psi* - psi) = (s_psi/2) (psih - (g+ - g-)),
+  //   dx = gb (eps* - eps) = (s_eps/3) (epsh - (g+ + g- - 2 g0)),
+  // and f0 -= de, f+- += de/2; g0 -= dx, g+- += dx/2 +- dp.  When
+  // eh = 3 (Jh uh + hP rh Th) - 2 rh, de reduces to
+  // s_e (Jh uh + hP rh Th - (f+ + f-)) since rh = f0 + f+ + f-.
   double de;
   if (EQ == 0 || c.eq_kind != 1)
-    de = fma(c.se_il2, jup, -(c.s_e * (fp + fm)));
+    de = c.s_e * (jup - (fp + fm));
   else
-    de = fma(c.se_fb, e_eq, -(c.se_3 * fma(-2.0, f0, fp + fm)));
-  const double dp = fma(c.sp_gc, psi_eq, -(c.sp_2 * (gp - gm)));
-  const double dx = fma(c.sx_gb, eps_eq, -(c.sx_3 * fma(-2.0, g0, gp + gm)));
+    de = c.se_3 * (eh - fma(-2.0, f0, fp + fm));
+  const double dp = c.sp_2 * (psih - (gp - gm));
+  const double dx = c.sx_3 * (epsh - fma(-2.0, g0, sg));
   f0 = f0 - de;
   fp = fma(0.5, de, fp);
   fm = fma(0.5, de, fm);
@@ -241,30 +273,33 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
   gp = fma(0.5, dx, gp) + dp;
   gm = fma(0.5, dx, gm) - dp;
   w = recip(T);
-  rw = rho * w;
+  rw = rh * w;
 }
 
-// u and T of a node (used for the halo nodes of the one-step kernel).
+// uh and Th of a node (the halo nodes of the one-step kernel), rounded as in
+// collide_local.
 __device__ __forceinline__ void node_uT(const Consts& c, double f0, double fp,
                                         double fm, double g0, double gp,
                                         double gm, double& u, double& T) {
 #pragma clang fp contract(off)
-  const double rho = density(c, f0, fp, fm);
-  const double J = c.mJ * (fp - fm);
-  const double zeta = c.mz * (g0 + (gp + gm));
-  double s, X;
-  thermo(c, rho, J, zeta, u, s, X, T);
+  const double rh = (f0 + fp) + fm;
+  const double Jh = fp - fm;
+  const double zh = g0 + (gp + gm);
+  double sh, X;
+  thermo_scaled(c, rh, Jh, zh, u, sh, X, T);
 }
 
 // Step (vii): the increment of zeta at node j, already divided into the
-// M^-1 column of zeta (each of g0, g+, g- receives ga * dz).
+// M^-1 column of zeta (each of g0, g+, g- receives ga dt S_j), from scaled
+// quantities: ga dt S_j = hS rh wh [(uh_{j+1} - uh_{j-1})^2
+// + hC (Th_{j+1} - Th_{j-1})^2 wh] with wh = 1/Th_j.
 __device__ __forceinline__ double source_g(const Consts& c, double rw, double w,
                                            double uL, double uR, double TL,
                                            double TR) {
 #pragma clang fp contract(off)
   const double du = uR - uL;
   const double dT = TR - TL;
-  return (c.src_g * rw) * fma(du, du, (c.cPr * (dT * dT)) * w);
+  return (c.hS * rw) * fma(du, du, (c.hC * (dT * dT)) * w);
 }
 
 // Equilibrium populations from (rho, J, zeta).
@@ -273,8 +308,8 @@ __device__ __forceinline__ void equilibrium(const Consts& c, double rho,
 #pragma clang fp contract(off)
   double u, s, X, T;
   thermo(c, rho, J, zeta, u, s, X, T);
-  double e_eq, psi_eq, eps_eq, jup;
-  equilibria<-1>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq, jup);
+  double e_eq, psi_eq, eps_eq;
+  equilibria<-1>(c, rho, J, zeta, u, s, X, T, e_eq, psi_eq, eps_eq);
   const double fr = c.fa * rho, fe = c.fb * e_eq, fj = c.fc * J;
   f[0] = fr - fe;
   f[1] = fma(0.5, fe, fr) + fj;
