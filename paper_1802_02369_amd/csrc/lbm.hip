@@ -103,9 +103,12 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->gc = 1.0 / (2.0 * r0 * cp * l);
   c->gamma = g;
   c->cp = cp;
+  c->se_2 = p->s_e / 2.0;
   c->se_3 = p->s_e / 3.0;
+  c->se_6 = p->s_e / 6.0;
   c->sp_2 = p->s_psi / 2.0;
   c->sx_3 = p->s_eps / 3.0;
+  c->sx_6 = p->s_eps / 6.0;
   c->hP = p->c0 * p->c0 / (g * l * l);
   c->two_g = 2.0 / g;
   c->hS = c->src_c * l * l / (3.0 * cp * c->T0);

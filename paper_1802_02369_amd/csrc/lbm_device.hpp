@@ -39,7 +39,8 @@ struct Consts {
   double lin[9];
   double xs0l;         // xs0 - (gamma - 1) ln rho0
   // The time step in scaled moments (see collide_local):
-  double se_3, sp_2, sx_3;  // s_e / 3, s_psi / 2, s_eps / 3
+  double se_2, se_3, se_6;  // s_e / 2, s_e / 3, s_e / 6
+  double sp_2, sx_3, sx_6;  // s_psi / 2, s_eps / 3, s_eps / 6
   double hP;                // c0^2 / (gamma lambda^2) = p0 / (rho0 lambda^2)
   double two_g;             // 2 / gamma
   double hS, hC;            // source: src_c lambda^2 / (3 cp T0), cp T0 / (Pr lambda^2)
@@ -258,20 +259,24 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
   //   dx = gb (eps* - eps) = (s_eps/3) (epsh - (g+ + g- - 2 g0)),
   // and f0 -= de, f+- += de/2; g0 -= dx, g+- += dx/2 +- dp.  When
   // eh = 3 (Jh uh + hP rh Th) - 2 rh, de reduces to
-  // s_e (Jh uh + hP rh Th - (f+ + f-)) since rh = f0 + f+ + f-.
-  double de;
-  if (EQ == 0 || c.eq_kind != 1)
-    de = c.s_e * (jup - (fp + fm));
-  else
-    de = c.se_3 * (eh - fma(-2.0, f0, fp + fm));
-  const double dp = c.sp_2 * (psih - (gp - gm));
-  const double dx = c.sx_3 * (epsh - fma(-2.0, g0, sg));
-  f0 = f0 - de;
-  fp = fma(0.5, de, fp);
-  fm = fma(0.5, de, fm);
-  g0 = g0 - dx;
-  gp = fma(0.5, dx, gp) + dp;
-  gm = fma(0.5, dx, gm) - dp;
+  // s_e (Jh uh + hP rh Th - (f+ + f-)) since rh = f0 + f+ + f-.  The rates
+  // enter through the FMAs of the updates.
+  if (EQ == 0 || c.eq_kind != 1) {
+    const double d = jup - (fp + fm);
+    f0 = fma(-c.s_e, d, f0);
+    fp = fma(c.se_2, d, fp);
+    fm = fma(c.se_2, d, fm);
+  } else {
+    const double d = eh - fma(-2.0, f0, fp + fm);
+    f0 = fma(-c.se_3, d, f0);
+    fp = fma(c.se_6, d, fp);
+    fm = fma(c.se_6, d, fm);
+  }
+  const double dpr = psih - (gp - gm);
+  const double dxr = epsh - fma(-2.0, g0, sg);
+  g0 = fma(-c.sx_3, dxr, g0);
+  gp = fma(c.sp_2, dpr, fma(c.sx_6, dxr, gp));
+  gm = fma(-c.sp_2, dpr, fma(c.sx_6, dxr, gm));
   w = recip(T);
   rw = rh * w;
 }
