@@ -19,6 +19,12 @@ PARAM_SETS = {
     "fluid": dict(eq_kind=2, source_on=0, s_e=1.7, c0=0.55),
     "thermal": dict(eq_kind=3, source_on=0, u0_lin=0.2, alpha=-0.5, s_e=1.6,
                     s_psi=1.3),
+    # the single-distribution schemes away from unit scales (lambda, rho0,
+    # cp != 1), where the device's scaled moments differ from the physical
+    "fluid_odd": dict(eq_kind=2, source_on=0, s_e=1.5, lam=1.3, rho0=1.2,
+                      cp=1.7, c0=0.7, gamma=1.3),
+    "thermal_odd": dict(eq_kind=3, source_on=0, u0_lin=0.25, alpha=0.3,
+                        s_e=1.4, s_psi=1.2, lam=1.4, rho0=0.9, cp=2.1, c0=0.6),
 }
 
 

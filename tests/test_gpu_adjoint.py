@@ -41,7 +41,7 @@ def rel(a, b):
 
 @pytest.mark.parametrize("adj", ["plain", "blocked"])
 @pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear", "fluid",
-                                   "thermal"])
+                                   "thermal", "fluid_odd", "thermal_odd"])
 @pytest.mark.parametrize("n", [3, 5, 64, 251, 252, 253, 256, 1000, 3001])
 def test_one_adjoint_step(pname, n, adj):
     """fbar(t) and the rate partials of one step against the oracle's
@@ -70,7 +70,8 @@ def test_one_adjoint_step(pname, n, adj):
 @pytest.mark.parametrize("pname,n,steps,ckpt", [
     ("paper", 64, 40, 7), ("odd", 300, 33, 33), ("nosource", 97, 25, 1),
     ("linear", 260, 18, 5), ("odd", 1200, 50, 8), ("fluid", 700, 37, 20),
-    ("thermal", 500, 30, 30), ("odd", 5000, 70, 35)])
+    ("thermal", 500, 30, 30), ("odd", 5000, 70, 35), ("fluid_odd", 400, 25, 6),
+    ("thermal_odd", 600, 28, 9)])
 def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
     rng = np.random.default_rng(steps)
     po = oracle_params(pname)

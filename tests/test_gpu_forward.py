@@ -55,7 +55,7 @@ def make_lattice(n, po, tuning="p2k8w4"):
 
 
 @pytest.mark.parametrize("pname", ["paper", "odd", "nosource", "linear", "fluid",
-                                   "thermal"])
+                                   "thermal", "fluid_odd", "thermal_odd"])
 def test_equilibrium_and_moments(pname):
     rng = np.random.default_rng(100)
     po = oracle_params(pname)
@@ -126,7 +126,8 @@ def test_step_broad_thermodynamic_range(pname, tuning):
 @pytest.mark.parametrize("n", [3, 4, 5, 63, 64, 65, 255, 257, 1000, 4099, 20011])
 def test_one_step(tuning, n):
     rng = np.random.default_rng(n)
-    for pname in ("paper", "odd", "nosource", "linear", "fluid", "thermal"):
+    for pname in ("paper", "odd", "nosource", "linear", "fluid", "thermal",
+                  "fluid_odd", "thermal_odd"):
         po = oracle_params(pname)
         f0 = random_state(rng, n, po)
         say(f"one step {tuning} n={n} {pname}")
