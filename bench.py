@@ -176,10 +176,21 @@ def bench_batched(torch, lbm, workloads, stream, single_glups):
     d = b.diagnostics(f)
     ok = bool((d[:, 6] == 0).all() and (d[:, 7] == 0).all())
     g = b.n_total * steps / (ms * 1e-3) / 1e9
-    log(f"bench: batched {g:.2f} GLUPS, tuning {tune}, finite: {ok}")
+    shapes, group_of = b.get_groups()
+    groups = []
+    if shapes:
+        import numpy as np
+        lens = np.diff(np.asarray(bt.offsets))
+        for k, (P, K, W) in enumerate(shapes):
+            sel = group_of == k
+            groups.append({"nodes_per_lane": P, "steps_per_launch": K,
+                           "waves_per_group": W, "lattices": int(sel.sum()),
+                           "nodes": int(lens[sel].sum())})
+    log(f"bench: batched {g:.2f} GLUPS, tuning {tune}, groups {groups}, "
+        f"finite: {ok}")
     return {"value": g, "unit": "GLUPS", "n_inst": bt.n_inst,
             "n_nodes": b.n_total, "time_steps": steps, "ms": ms,
-            "tuning": tune, "graph": True, "valid": ok,
+            "tuning": tune, "groups": groups, "graph": True, "valid": ok,
             "vs_single_lattice": g / single_glups}
 
 

@@ -250,8 +250,29 @@ int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
                    const lbm_params* params, void* stream);
 void lbm_batch_destroy(lbm_batch* b);
 int lbm_batch_set_stream(lbm_batch* b, void* stream);
+/* Tile shape of the batch (as lbm_set_tuning; the blocked kernel only).
+ * Clears any shape groups. */
 int lbm_batch_set_tuning(lbm_batch* b, const lbm_tuning* t);
 int lbm_batch_get_tuning(const lbm_batch* b, lbm_tuning* t);
+
+/* Shape groups of lbm_batch_run.  A tile holds nodes of one lattice, so a
+ * lattice of L nodes costs ceil(L / (64 P W - 4K)) whole tiles: short
+ * lattices waste most of a wide tile, long ones run best on it.  With
+ * groups, lattice i runs with shapes[group_of[i]] (host arrays of n_groups
+ * and n_inst entries, 1 <= n_groups <= LBM_MAX_GROUPS), each group as its
+ * own sequence of launches on its own stream, forked from the batch's
+ * stream and joined back to it (also inside the graph of use_graph = 1).
+ * Results are bitwise those of a single shape.  n_groups = 0 returns to the
+ * single tuning.  Takes effect at the next lbm_batch_prepare; the adjoint
+ * calls keep using the single tuning.  lbm_batch_autotune sets groups when
+ * they time faster. */
+enum { LBM_MAX_GROUPS = 4 };
+int lbm_batch_set_groups(lbm_batch* b, int32_t n_groups,
+                         const lbm_tuning* shapes, const int32_t* group_of);
+/* *n_groups (0: single tuning); shapes (capacity LBM_MAX_GROUPS) and
+ * group_of (capacity n_inst) receive the assignment unless NULL. */
+int lbm_batch_get_groups(const lbm_batch* b, int32_t* n_groups,
+                         lbm_tuning* shapes, int32_t* group_of);
 /* Total nodes n_total of the batch (0 on a bad handle). */
 int64_t lbm_batch_total_nodes(const lbm_batch* b);
 size_t lbm_batch_workspace_bytes(const lbm_batch* b, int kind);

@@ -56,7 +56,9 @@ T* at(void* ws, size_t off) {
 
 int check_batch_ws(const lbm_batch* b, const void* ws, size_t ws_bytes) {
   if (!b || !ws) return set_err(LBM_EINVAL, "NULL argument");
-  if (b->prep_ws != ws || !same_tuning(b->prep_tune, b->tune))
+  if (b->prep_ws != ws || !same_tuning(b->prep_tune, b->tune) ||
+      !same_tunings(b->prep_group_tune, b->group_tune) ||
+      b->prep_group_of != b->group_of)
     return set_err(LBM_EINVAL,
                    "workspace not prepared for this tuning: call "
                    "lbm_batch_prepare");
@@ -65,25 +67,65 @@ int check_batch_ws(const lbm_batch* b, const void* ws, size_t ws_bytes) {
   return LBM_OK;
 }
 
-// Launch sequence of a batched run on stream s.
+// Launches of nsteps steps of the tiles [first, first + ntiles) of the table
+// with tuning t on stream s (ping-pong between f and the workspace state);
+// returns the number of launches in *launches.
+int enqueue_tiles(lbm_batch* b, const Layout& L, void* ws, double* f,
+                  int64_t nsteps, const lbm_tuning& t, int64_t first,
+                  int64_t ntiles, hipStream_t s, int64_t* launches) {
+  const Consts* cs = at<Consts>(ws, L.consts);
+  const int64_t* offs = at<int64_t>(ws, L.offs);
+  const TileRef* tiles = at<TileRef>(ws, L.tiles) + first;
+  double* a = f;
+  double* w = at<double>(ws, L.state2);
+  const int H = 2 * t.steps_per_launch;
+  *launches = 0;
+  for (int k : split_steps(nsteps, t.steps_per_launch)) {
+    int rc = launch_batch_tile(cs, offs, tiles, ntiles, a, w, b->n_total,
+                               t.nodes_per_lane, H, k, t.waves_per_group,
+                               b->eq_class(), s);
+    if (rc) return rc;
+    std::swap(a, w);
+    ++*launches;
+  }
+  return LBM_OK;
+}
+
+// Launch sequence of a batched run on stream s.  With shape groups, group 0
+// runs on s and group g > 0 on its own stream, forked from s and joined back
+// to it (inside a graph capture the side streams join the capture).  Every
+// group makes an even number of launches when nsteps >= 2 and one when
+// nsteps = 1, so the state ends in f, or entirely in the workspace state.
 int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
                   hipStream_t s) {
   const Layout L = layout(b, b->prep_tiles, false);
-  const Consts* cs = at<Consts>(ws, L.consts);
-  const int64_t* offs = at<int64_t>(ws, L.offs);
-  const TileRef* tiles = at<TileRef>(ws, L.tiles);
-  double* a = f;
-  double* w = at<double>(ws, L.state2);
-  const int H = 2 * b->tune.steps_per_launch;
   int64_t launches = 0;
-  for (int k : split_steps(nsteps, b->tune.steps_per_launch)) {
-    int rc = launch_batch_tile(cs, offs, tiles, b->prep_tiles, a, w,
-                               b->n_total, b->tune.nodes_per_lane, H, k,
-                               b->tune.waves_per_group, b->eq_class(), s);
-    if (rc) return rc;
-    std::swap(a, w);
-    ++launches;
+  int rc = LBM_OK;
+  if (b->prep_group_tune.empty()) {
+    rc = enqueue_tiles(b, L, ws, f, nsteps, b->tune, 0, b->prep_tiles, s,
+                       &launches);
+  } else {
+    const size_t ng = b->prep_group_tune.size();
+    rc = hip_check(hipEventRecord(b->gevents[0], s), "hipEventRecord");
+    for (size_t g = 1; g < ng && !rc; ++g)
+      rc = hip_check(hipStreamWaitEvent(b->gstreams[g - 1], b->gevents[0], 0),
+                     "hipStreamWaitEvent");
+    for (size_t g = 0; g < ng && !rc; ++g) {
+      const hipStream_t sg = g == 0 ? s : b->gstreams[g - 1];
+      const int64_t first = b->prep_group_first[g];
+      rc = enqueue_tiles(b, L, ws, f, nsteps, b->prep_group_tune[g], first,
+                         b->prep_group_first[g + 1] - first, sg, &launches);
+    }
+    // join every side stream even after a failure, so that a capture ends
+    for (size_t g = 1; g < ng; ++g) {
+      const int r1 = hip_check(hipEventRecord(b->gevents[g], b->gstreams[g - 1]),
+                               "hipEventRecord");
+      const int r2 = hip_check(hipStreamWaitEvent(s, b->gevents[g], 0),
+                               "hipStreamWaitEvent");
+      if (!rc) rc = r1 ? r1 : r2;
+    }
   }
+  if (rc) return rc;
   if (launches & 1)
     return hip_check(hipMemcpyAsync(f, at<double>(ws, L.state2),
                                     sizeof(double) * 6 * b->n_total,
@@ -106,12 +148,22 @@ void drop_graph(lbm_batch* b) {
   b->g_f = nullptr;
   b->g_ws = nullptr;
   b->g_nsteps = -1;
+  b->g_group_tune.clear();
+  b->g_group_of.clear();
 }
 
 // --------------------------------------------------------- tuning cache --
 
-std::map<std::string, lbm_tuning> read_cache(const char* path) {
-  std::map<std::string, lbm_tuning> m;
+// A tuning-cache entry: the shape and, for batches, optional shape groups
+// with their measured time per computed node-update.
+struct CacheEntry {
+  lbm_tuning t{};
+  std::vector<lbm_tuning> gshape;
+  std::vector<double> gcost;
+};
+
+std::map<std::string, CacheEntry> read_cache(const char* path) {
+  std::map<std::string, CacheEntry> m;
   FILE* fp = path ? std::fopen(path, "r") : nullptr;
   if (!fp) return m;
   std::string text;
@@ -132,14 +184,40 @@ std::map<std::string, lbm_tuning> read_cache(const char* path) {
       pos = end + 1;
       continue;
     }
-    lbm_tuning t{};
+    CacheEntry e;
+    lbm_tuning& t = e.t;
     const std::string body = text.substr(brace, close - brace + 1);
     if (std::sscanf(body.c_str(),
-                    "{ \"kernel\" : %d , \"P\" : %d , \"K\" : %d , \"W\" : %d }",
+                    "{ \"kernel\" : %d , \"P\" : %d , \"K\" : %d , \"W\" : %d",
                     &t.kernel, &t.nodes_per_lane, &t.steps_per_launch,
                     &t.waves_per_group) == 4 &&
-        check_tuning(&t) == LBM_OK)
-      m[key] = t;
+        check_tuning(&t) == LBM_OK) {
+      // optional "groups": [[P, K, W, seconds per node-update], ...]
+      const size_t gp = body.find("\"groups\"");
+      size_t q = gp == std::string::npos ? gp : body.find('[', gp);
+      if (q != std::string::npos) {
+        for (++q;;) {
+          const size_t o = body.find('[', q);
+          const size_t c = o == std::string::npos ? o : body.find(']', o);
+          if (c == std::string::npos) break;
+          lbm_tuning g{LBM_KERNEL_BLOCKED, 0, 0, 0};
+          double cost = 0;
+          if (std::sscanf(body.c_str() + o, "[ %d , %d , %d , %lf ]",
+                          &g.nodes_per_lane, &g.steps_per_launch,
+                          &g.waves_per_group, &cost) == 4 &&
+              check_tuning(&g) == LBM_OK && cost > 0) {
+            e.gshape.push_back(g);
+            e.gcost.push_back(cost);
+          }
+          q = c + 1;
+        }
+        if (e.gshape.size() < 2 || e.gshape.size() > LBM_MAX_GROUPS) {
+          e.gshape.clear();
+          e.gcost.clear();
+        }
+      }
+      m[key] = e;
+    }
     pos = close + 1;
   }
   return m;
@@ -149,29 +227,48 @@ std::map<std::string, lbm_tuning> read_cache(const char* path) {
 
 namespace lbm {
 
-bool tune_cache_get(const char* path, const std::string& key, lbm_tuning* t) {
+bool tune_cache_get(const char* path, const std::string& key, lbm_tuning* t,
+                    std::vector<lbm_tuning>* gshape, std::vector<double>* gcost) {
   auto m = read_cache(path);
   auto it = m.find(key);
   if (it == m.end()) return false;
-  *t = it->second;
+  *t = it->second.t;
+  if (gshape) *gshape = it->second.gshape;
+  if (gcost) *gcost = it->second.gcost;
   return true;
 }
 
 void tune_cache_put(const char* path, const std::string& key,
-                    const lbm_tuning& t) {
+                    const lbm_tuning& t, const std::vector<lbm_tuning>* gshape,
+                    const std::vector<double>* gcost) {
   if (!path) return;
   auto m = read_cache(path);
-  m[key] = t;
+  CacheEntry e;
+  e.t = t;
+  if (gshape && gcost) {
+    e.gshape = *gshape;
+    e.gcost = *gcost;
+  }
+  m[key] = e;
   const std::string tmp = std::string(path) + ".tmp";
   FILE* fp = std::fopen(tmp.c_str(), "w");
   if (!fp) return;
   std::fprintf(fp, "{\n");
   size_t i = 0;
   for (const auto& kv : m) {
-    std::fprintf(fp, "  \"%s\": {\"kernel\": %d, \"P\": %d, \"K\": %d, \"W\": %d}%s\n",
-                 kv.first.c_str(), kv.second.kernel, kv.second.nodes_per_lane,
-                 kv.second.steps_per_launch, kv.second.waves_per_group,
-                 ++i < m.size() ? "," : "");
+    const CacheEntry& x = kv.second;
+    std::fprintf(fp, "  \"%s\": {\"kernel\": %d, \"P\": %d, \"K\": %d, \"W\": %d",
+                 kv.first.c_str(), x.t.kernel, x.t.nodes_per_lane,
+                 x.t.steps_per_launch, x.t.waves_per_group);
+    if (!x.gshape.empty()) {
+      std::fprintf(fp, ", \"groups\": [");
+      for (size_t g = 0; g < x.gshape.size(); ++g)
+        std::fprintf(fp, "%s[%d, %d, %d, %.9e]", g ? ", " : "",
+                     x.gshape[g].nodes_per_lane, x.gshape[g].steps_per_launch,
+                     x.gshape[g].waves_per_group, x.gcost[g]);
+      std::fprintf(fp, "]");
+    }
+    std::fprintf(fp, "}%s\n", ++i < m.size() ? "," : "");
   }
   std::fprintf(fp, "}\n");
   std::fclose(fp);
@@ -195,16 +292,82 @@ namespace {
 
 int log2_class(double x) { return x > 1 ? (int)std::lround(std::log2(x)) : 0; }
 
+// Tile-table size the autotuner may need: any grouping of the candidates,
+// i.e. each lattice at its largest tile count, and the current settings.
+int64_t tune_tiles(const lbm_batch* b) {
+  int64_t mx = 0;
+  const std::vector<lbm_tuning> cands = tuning_candidates();
+  for (int64_t i = 0; i < b->n_inst; ++i) {
+    int64_t m = 0;
+    for (const lbm_tuning& t : cands) m = std::max(m, b->lattice_tiles(i, t));
+    mx += m;
+  }
+  return std::max(mx, std::max(b->run_tiles(), b->count_tiles(b->tune)));
+}
+
+// Modelled time of a grouping: lattice i costs tiles_i(s) * width(s) * c_s
+// on shape s, with c_s a measured time per computed node-update; each
+// lattice takes its cheapest shape (written to *of).  Returns the total.
+double assign_groups(const lbm_batch* b, const std::vector<lbm_tuning>& shapes,
+                     const std::vector<double>& cost, std::vector<int32_t>* of) {
+  double total = 0;
+  if (of) of->assign(b->n_inst, 0);
+  for (int64_t i = 0; i < b->n_inst; ++i) {
+    double best = INFINITY;
+    for (size_t g = 0; g < shapes.size(); ++g) {
+      const double c = (double)b->lattice_tiles(i, shapes[g]) *
+                       (double)tile_width(shapes[g]) * cost[g];
+      if (c < best) {
+        best = c;
+        if (of) (*of)[i] = (int32_t)g;
+      }
+    }
+    total += best;
+  }
+  return total;
+}
+
+}  // namespace
+
+extern "C" int lbm_batch_set_groups(lbm_batch* b, int32_t n_groups,
+                                    const lbm_tuning* shapes,
+                                    const int32_t* group_of);
+
+namespace {
+
+// Groups of the shapes gshape with costs gcost for this batch: each lattice on
+// its cheapest shape, unused shapes dropped.  Sets them on b.
+int apply_groups(lbm_batch* b, const std::vector<lbm_tuning>& gshape,
+                 const std::vector<double>& gcost) {
+  std::vector<int32_t> of;
+  assign_groups(b, gshape, gcost, &of);
+  std::vector<int32_t> remap(gshape.size(), -1);
+  std::vector<lbm_tuning> used;
+  for (int32_t& g : of) {
+    if (remap[g] < 0) {
+      remap[g] = (int32_t)used.size();
+      used.push_back(gshape[g]);
+    }
+    g = remap[g];
+  }
+  if (used.size() < 2) return lbm_batch_set_groups(b, 0, nullptr, nullptr);
+  return lbm_batch_set_groups(b, (int32_t)used.size(), used.data(), of.data());
+}
+
+
 // Generation of the tile kernels, the last component of every tuning-cache
 // key: entries measured on kernels of another generation are not reused.
 constexpr const char* kKernelGeneration = "/k3";
 
 // Times `run(t)` for each candidate on the state f, restoring f from
-// `backup` before each run and at the end; returns the fastest.
+// `backup` before each run and at the end; returns the fastest, and every
+// candidate's milliseconds in *times (when not NULL).
 template <class Prepare, class Run>
 int autotune_impl(hipStream_t s, double* f, double* backup, size_t bytes,
                   int64_t probe, const std::vector<lbm_tuning>& cands,
-                  Prepare prepare, Run run, lbm_tuning* best) {
+                  Prepare prepare, Run run, lbm_tuning* best,
+                  std::vector<float>* times = nullptr) {
+  if (times) times->assign(cands.size(), INFINITY);
   int rc = hip_check(hipMemcpyAsync(backup, f, bytes, hipMemcpyDeviceToDevice, s),
                      "hipMemcpyAsync");
   if (rc) return rc;
@@ -215,7 +378,8 @@ int autotune_impl(hipStream_t s, double* f, double* backup, size_t bytes,
     return rc;
   }
   float best_ms = INFINITY;
-  for (const lbm_tuning& t : cands) {
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    const lbm_tuning& t = cands[ci];
     if ((rc = prepare(t))) break;
     if ((rc = run(t, probe))) break;  // warm-up
     if ((rc = hip_check(hipMemcpyAsync(f, backup, bytes,
@@ -229,6 +393,7 @@ int autotune_impl(hipStream_t s, double* f, double* backup, size_t bytes,
       break;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    if (times) (*times)[ci] = ms;
     if (ms < best_ms) {
       best_ms = ms;
       *best = t;
@@ -324,6 +489,8 @@ void lbm_batch_destroy(lbm_batch* b) {
   drop_graph(b);
   lbm::drop_adjoint_graph(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (hipStream_t st : b->gstreams) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->gevents) (void)hipEventDestroy(ev);
   delete b;
 }
 
@@ -341,6 +508,8 @@ int lbm_batch_set_tuning(lbm_batch* b, const lbm_tuning* t) {
     return set_err(LBM_EINVAL, "batches run the blocked kernel only");
   b->tune = *t;
   b->tune.kernel = LBM_KERNEL_BLOCKED;
+  b->group_tune.clear();
+  b->group_of.clear();
   return LBM_OK;
 }
 
@@ -350,35 +519,95 @@ int lbm_batch_get_tuning(const lbm_batch* b, lbm_tuning* t) {
   return LBM_OK;
 }
 
+int lbm_batch_set_groups(lbm_batch* b, int32_t n_groups,
+                         const lbm_tuning* shapes, const int32_t* group_of) {
+  if (!b) return set_err(LBM_EINVAL, "batch is NULL");
+  if (n_groups == 0) {
+    b->group_tune.clear();
+    b->group_of.clear();
+    return LBM_OK;
+  }
+  if (n_groups < 0 || n_groups > LBM_MAX_GROUPS)
+    return set_err(LBM_EINVAL, "n_groups must lie in 0 .. %d", LBM_MAX_GROUPS);
+  if (!shapes || !group_of) return set_err(LBM_EINVAL, "NULL argument");
+  std::vector<lbm_tuning> gt(shapes, shapes + n_groups);
+  for (lbm_tuning& t : gt) {
+    const int rc = check_tuning(&t);
+    if (rc) return rc;
+    if (t.kernel == LBM_KERNEL_PLAIN)
+      return set_err(LBM_EINVAL, "batches run the blocked kernel only");
+    t.kernel = LBM_KERNEL_BLOCKED;
+  }
+  std::vector<int32_t> go(group_of, group_of + b->n_inst);
+  for (int64_t i = 0; i < b->n_inst; ++i)
+    if (go[i] < 0 || go[i] >= n_groups)
+      return set_err(LBM_EINVAL, "group_of[%lld] = %d is not a group",
+                     (long long)i, (int)go[i]);
+  // side streams (default priority) and fork/join events, created once
+  while ((int32_t)b->gstreams.size() < n_groups - 1) {
+    hipStream_t st;
+    const int rc = hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking),
+                             "hipStreamCreate");
+    if (rc) return rc;
+    b->gstreams.push_back(st);
+  }
+  while ((int32_t)b->gevents.size() < n_groups) {
+    hipEvent_t ev;
+    const int rc = hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming),
+                             "hipEventCreate");
+    if (rc) return rc;
+    b->gevents.push_back(ev);
+  }
+  b->group_tune = gt;
+  b->group_of = go;
+  return LBM_OK;
+}
+
+int lbm_batch_get_groups(const lbm_batch* b, int32_t* n_groups,
+                         lbm_tuning* shapes, int32_t* group_of) {
+  if (!b || !n_groups) return set_err(LBM_EINVAL, "NULL argument");
+  *n_groups = (int32_t)b->group_tune.size();
+  if (shapes)
+    std::copy(b->group_tune.begin(), b->group_tune.end(), shapes);
+  if (group_of)
+    std::copy(b->group_of.begin(), b->group_of.end(), group_of);
+  return LBM_OK;
+}
+
 int64_t lbm_batch_total_nodes(const lbm_batch* b) { return b ? b->n_total : 0; }
 
 size_t lbm_batch_workspace_bytes(const lbm_batch* b, int kind) {
   if (!b) return 0;
-  if (kind == LBM_WS_STEP) return layout(b, b->count_tiles(b->tune), false).total;
-  if (kind == LBM_WS_TUNE) {
-    int64_t mx = b->count_tiles(b->tune);
-    for (const lbm_tuning& t : tuning_candidates())
-      mx = std::max(mx, b->count_tiles(t));
-    return layout(b, mx, true).total;
-  }
+  if (kind == LBM_WS_STEP) return layout(b, b->run_tiles(), false).total;
+  if (kind == LBM_WS_TUNE) return layout(b, tune_tiles(b), true).total;
   return 0;
 }
 
 int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes) {
   if (!b || !ws) return set_err(LBM_EINVAL, "NULL argument");
-  const int64_t ntiles = b->count_tiles(b->tune);
+  const int64_t ntiles = b->run_tiles();
   const Layout L = layout(b, ntiles, false);
   if (ws_bytes < L.total)
     return set_err(LBM_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes,
                    L.total);
+  // one table per group (a single group: tune), concatenated
+  const bool grouped = !b->group_tune.empty();
+  const size_t ng = grouped ? b->group_tune.size() : 1;
   std::vector<TileRef> tiles;
   tiles.reserve(ntiles);
-  const int64_t out = tile_width(b->tune) - 4 * (int64_t)b->tune.steps_per_launch;
-  for (int64_t i = 0; i < b->n_inst; ++i) {
-    const int64_t n = b->offsets[i + 1] - b->offsets[i];
-    for (int64_t t = 0; t * out < n; ++t)
-      tiles.push_back(TileRef{(int32_t)i, (int32_t)t});
+  std::vector<int64_t> first(ng + 1, 0);
+  for (size_t g = 0; g < ng; ++g) {
+    first[g] = (int64_t)tiles.size();
+    const lbm_tuning& t = grouped ? b->group_tune[g] : b->tune;
+    const int64_t out = tile_width(t) - 4 * (int64_t)t.steps_per_launch;
+    for (int64_t i = 0; i < b->n_inst; ++i) {
+      if (grouped && b->group_of[i] != (int32_t)g) continue;
+      const int64_t n = b->offsets[i + 1] - b->offsets[i];
+      for (int64_t k = 0; k * out < n; ++k)
+        tiles.push_back(TileRef{(int32_t)i, (int32_t)k});
+    }
   }
+  first[ng] = (int64_t)tiles.size();
   int rc = hip_check(hipMemcpyAsync(at<char>(ws, L.consts), b->consts.data(),
                                     sizeof(Consts) * b->n_inst,
                                     hipMemcpyHostToDevice, b->stream),
@@ -398,6 +627,9 @@ int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes) {
   b->prep_ws = ws;
   b->prep_tune = b->tune;
   b->prep_tiles = (int64_t)tiles.size();
+  b->prep_group_tune = b->group_tune;
+  b->prep_group_of = b->group_of;
+  b->prep_group_first = grouped ? first : std::vector<int64_t>();
   return LBM_OK;
 }
 
@@ -426,7 +658,9 @@ int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   if (nsteps == 0) return LBM_OK;
   if (!use_graph) return enqueue_batch(b, f, ws, nsteps, b->stream);
   if (!(b->exec && b->g_f == f && b->g_ws == ws && b->g_nsteps == nsteps &&
-        same_tuning(b->g_tune, b->tune))) {
+        same_tuning(b->g_tune, b->tune) &&
+        same_tunings(b->g_group_tune, b->group_tune) &&
+        b->g_group_of == b->group_of)) {
     drop_graph(b);
     if (!b->cap &&
         (rc = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking),
@@ -455,6 +689,8 @@ int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     b->g_ws = ws;
     b->g_nsteps = nsteps;
     b->g_tune = b->tune;
+    b->g_group_tune = b->group_tune;
+    b->g_group_of = b->group_of;
   }
   return hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
 }
@@ -505,14 +741,17 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
                           std::to_string(log2_class((double)b->n_total)) + "/L" +
                           std::to_string(log2_class(mean_len)) + kKernelGeneration;
   lbm_tuning best = b->tune;
-  if (!tune_cache_get(cache_path, key, &best)) {
-    int64_t mx = 0;
-    for (const lbm_tuning& t : tuning_candidates())
-      mx = std::max(mx, b->count_tiles(t));
-    double* backup = at<double>(ws, layout(b, mx, true).backup);
+  std::vector<lbm_tuning> gshape;
+  std::vector<double> gcost;
+  if (!tune_cache_get(cache_path, key, &best, &gshape, &gcost)) {
+    const std::vector<lbm_tuning> cands = tuning_candidates();
+    double* backup = at<double>(ws, layout(b, tune_tiles(b), true).backup);
     const size_t sbytes = sizeof(double) * 6 * (size_t)b->n_total;
+    b->group_tune.clear();
+    b->group_of.clear();
+    std::vector<float> times;
     int rc = autotune_impl(
-        b->stream, f, backup, sbytes, probe_steps, tuning_candidates(),
+        b->stream, f, backup, sbytes, probe_steps, cands,
         [&](const lbm_tuning& t) {
           b->tune = t;
           return lbm_batch_prepare(b, ws, ws_bytes);
@@ -520,12 +759,77 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
         [&](const lbm_tuning&, int64_t k) {
           return lbm_batch_run(b, f, ws, ws_bytes, k, 0);
         },
-        &best);
+        &best, &times);
     if (rc) return rc;
-    tune_cache_put(cache_path, key, best);
+    // Shape groups: the measured time per computed node-update of each shape
+    // models a grouping; the best set of two or three among the eight
+    // fastest shapes is timed and kept if it beats the best single shape.
+    std::vector<double> cost(cands.size());
+    std::vector<size_t> order(cands.size());
+    size_t ib = 0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      cost[c] = (double)times[c] * 1e-3 /
+                ((double)b->count_tiles(cands[c]) * (double)tile_width(cands[c]) *
+                 (double)probe_steps);
+      order[c] = c;
+      if (same_tuning(cands[c], best)) ib = c;
+    }
+    std::sort(order.begin(), order.end(),
+              [&](size_t x, size_t y) { return times[x] < times[y]; });
+    const size_t top = std::min<size_t>(8, order.size());
+    const double single = assign_groups(b, {cands[ib]}, {cost[ib]}, nullptr);
+    double best_model = single;
+    std::vector<size_t> pick;
+    auto consider = [&](const std::vector<size_t>& set) {
+      std::vector<lbm_tuning> sh;
+      std::vector<double> co;
+      for (size_t c : set) {
+        sh.push_back(cands[c]);
+        co.push_back(cost[c]);
+      }
+      const double m = assign_groups(b, sh, co, nullptr);
+      if (m < best_model) {
+        best_model = m;
+        pick = set;
+      }
+    };
+    for (size_t x = 0; x < top; ++x)
+      for (size_t y = x + 1; y < top; ++y) {
+        consider({order[x], order[y]});
+        for (size_t z = y + 1; z < top; ++z) consider({order[x], order[y], order[z]});
+      }
+    if (!pick.empty() && best_model < 0.97 * single) {
+      std::vector<lbm_tuning> sh;
+      std::vector<double> co;
+      for (size_t c : pick) {
+        sh.push_back(cands[c]);
+        co.push_back(cost[c]);
+      }
+      b->tune = best;
+      std::vector<float> gt;
+      lbm_tuning unused = best;
+      rc = autotune_impl(
+          b->stream, f, backup, sbytes, probe_steps, {best},
+          [&](const lbm_tuning&) {
+            const int r = apply_groups(b, sh, co);
+            return r ? r : lbm_batch_prepare(b, ws, ws_bytes);
+          },
+          [&](const lbm_tuning&, int64_t k) {
+            return lbm_batch_run(b, f, ws, ws_bytes, k, 0);
+          },
+          &unused, &gt);
+      if (rc) return rc;
+      if (gt[0] < times[ib]) {
+        gshape = sh;
+        gcost = co;
+      }
+    }
+    tune_cache_put(cache_path, key, best, &gshape, &gcost);
   }
   b->tune = best;
-  int rc = lbm_batch_prepare(b, ws, ws_bytes);
+  int rc = gshape.empty() ? lbm_batch_set_groups(b, 0, nullptr, nullptr)
+                          : apply_groups(b, gshape, gcost);
+  if (!rc) rc = lbm_batch_prepare(b, ws, ws_bytes);
   if (rc) return rc;
   if (out) *out = best;
   return LBM_OK;

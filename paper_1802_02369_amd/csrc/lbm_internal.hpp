@@ -83,9 +83,15 @@ std::vector<lbm_tuning> tuning_candidates();
 bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 
 // Tuning cache: "<arch>/<kind>/<class>" -> shape, in a small JSON file.
-bool tune_cache_get(const char* path, const std::string& key, lbm_tuning* t);
+// Batch entries may carry shape groups with their measured time per computed
+// node-update (gshape, gcost); absent groups read back empty.
+bool tune_cache_get(const char* path, const std::string& key, lbm_tuning* t,
+                    std::vector<lbm_tuning>* gshape = nullptr,
+                    std::vector<double>* gcost = nullptr);
 void tune_cache_put(const char* path, const std::string& key,
-                    const lbm_tuning& t);
+                    const lbm_tuning& t,
+                    const std::vector<lbm_tuning>* gshape = nullptr,
+                    const std::vector<double>* gcost = nullptr);
 std::string gpu_arch_name();
 
 // Validates a tuning record for a lattice (or batch) of minimum length nmin.
@@ -98,6 +104,14 @@ inline bool same_tuning(const lbm_tuning& a, const lbm_tuning& b) {
   return a.kernel == b.kernel && a.nodes_per_lane == b.nodes_per_lane &&
          a.steps_per_launch == b.steps_per_launch &&
          a.waves_per_group == b.waves_per_group;
+}
+
+inline bool same_tunings(const std::vector<lbm_tuning>& a,
+                         const std::vector<lbm_tuning>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (!same_tuning(a[i], b[i])) return false;
+  return true;
 }
 
 inline int64_t tile_width(const lbm_tuning& t) {
@@ -127,12 +141,26 @@ struct lbm_batch {
   const void* prep_ws = nullptr;
   lbm_tuning prep_tune{};
   int64_t prep_tiles = 0;
+  // Shape groups of lbm_batch_run (lbm_batch_set_groups): lattice i runs with
+  // group_tune[group_of[i]], each group as its own launch sequence on its own
+  // stream.  Empty: every lattice runs with tune.
+  std::vector<lbm_tuning> group_tune;
+  std::vector<int32_t> group_of;
+  std::vector<hipStream_t> gstreams;  // groups 1.. (group 0: the run's stream)
+  std::vector<hipEvent_t> gevents;    // [0] fork, [g] end of group g
+  // the groups lbm_batch_prepare built the table for; the table holds each
+  // group's tiles from prep_group_first[g] to prep_group_first[g + 1]
+  std::vector<lbm_tuning> prep_group_tune;
+  std::vector<int32_t> prep_group_of;
+  std::vector<int64_t> prep_group_first;
   // captured graph of the last lbm_batch_run(use_graph = 1)
   hipGraphExec_t exec = nullptr;
   const double* g_f = nullptr;
   const void* g_ws = nullptr;
   int64_t g_nsteps = -1;
   lbm_tuning g_tune{};
+  std::vector<lbm_tuning> g_group_tune;
+  std::vector<int32_t> g_group_of;
   // adjoint workspace uploaded by lbm_batch_forward_ckpt
   const void* adj_ws = nullptr;
   int64_t adj_nsteps = -1, adj_ckpt = -1;
@@ -151,12 +179,25 @@ struct lbm_batch {
     return 0;
   }
 
-  // tiles of the current table for a tuning: sum of ceil(L_i / OUT)
-  int64_t count_tiles(const lbm_tuning& t) const {
+  // tiles of lattice i for a tuning: ceil(L_i / OUT)
+  int64_t lattice_tiles(int64_t i, const lbm_tuning& t) const {
     const int64_t out = lbm::tile_width(t) - 4 * (int64_t)t.steps_per_launch;
+    return (offsets[i + 1] - offsets[i] + out - 1) / out;
+  }
+
+  // tiles of the table for one tuning: sum of ceil(L_i / OUT)
+  int64_t count_tiles(const lbm_tuning& t) const {
+    int64_t s = 0;
+    for (int64_t i = 0; i < n_inst; ++i) s += lattice_tiles(i, t);
+    return s;
+  }
+
+  // tiles of the run's table: the groups' shapes, else tune
+  int64_t run_tiles() const {
+    if (group_tune.empty()) return count_tiles(tune);
     int64_t s = 0;
     for (int64_t i = 0; i < n_inst; ++i)
-      s += (offsets[i + 1] - offsets[i] + out - 1) / out;
+      s += lattice_tiles(i, group_tune[group_of[i]]);
     return s;
   }
 };

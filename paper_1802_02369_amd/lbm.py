@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_EWORKSPACE, LBM_ENONFINITE, LBM_ENOTSUP = \
     0, -1, -2, -3, -4, -5
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
+MAX_GROUPS = 4
 WS_STEP, WS_TUNE = 0, 1
 
 
@@ -82,6 +83,11 @@ def lib():
             "lbm_batch_set_stream": ([_vp, _vp], ctypes.c_int),
             "lbm_batch_set_tuning": ([_vp, ctypes.POINTER(CTuning)], ctypes.c_int),
             "lbm_batch_get_tuning": ([_vp, ctypes.POINTER(CTuning)], ctypes.c_int),
+            "lbm_batch_set_groups": ([_vp, ctypes.c_int32, ctypes.POINTER(CTuning),
+                                      ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "lbm_batch_get_groups": ([_vp, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(CTuning),
+                                      ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_batch_total_nodes": ([_vp], _i64),
             "lbm_batch_workspace_bytes": ([_vp, ctypes.c_int], _sz),
             "lbm_batch_prepare": ([_vp, _vp, _sz], ctypes.c_int),
@@ -427,6 +433,36 @@ class Batch:
         if rc != LBM_OK and (rc != LBM_ENONFINITE or raise_nonfinite):
             check(rc)
         return out.reshape(self.n_inst, 8)
+
+    def set_groups(self, shapes, group_of=None, device="cuda"):
+        """Shape groups of run(): lattice i with shapes[group_of[i]], each
+        shape a (P, K, W) triple; no shapes returns to the single tuning."""
+        import numpy as np
+        n = len(shapes)
+        if n == 0:
+            check(lib().lbm_batch_set_groups(self._h, 0, None, None))
+        else:
+            arr = (CTuning * n)(*[CTuning(KERNEL_BLOCKED, int(p), int(k), int(w))
+                                  for p, k, w in shapes])
+            go = np.ascontiguousarray(np.asarray(group_of, dtype=np.int32))
+            if go.shape != (self.n_inst,):
+                raise ValueError("group_of needs one entry per lattice")
+            check(lib().lbm_batch_set_groups(
+                self._h, n, arr, go.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        self.prepare(device)
+
+    def get_groups(self):
+        """([(P, K, W), ...], group_of array), or ([], None) without groups."""
+        import numpy as np
+        n = ctypes.c_int32()
+        arr = (CTuning * MAX_GROUPS)()
+        go = np.zeros(self.n_inst, dtype=np.int32)
+        check(lib().lbm_batch_get_groups(
+            self._h, ctypes.byref(n), arr,
+            go.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        shapes = [(arr[g].nodes_per_lane, arr[g].steps_per_launch,
+                   arr[g].waves_per_group) for g in range(n.value)]
+        return shapes, (go if n.value else None)
 
     def autotune(self, f: torch.Tensor, probe_steps: int = 32,
                  cache_path: str | None = None) -> dict:

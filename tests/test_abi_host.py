@@ -131,3 +131,34 @@ def test_batch_default_tuning_uses_mean_length():
     assert lbm.lib().lbm_batch_get_tuning(b, ctypes.byref(t)) == lbm.LBM_OK
     assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (4, 16, 4)
     lbm.lib().lbm_batch_destroy(b)
+
+
+def test_batch_groups_validation_host():
+    """Shape-group arguments are checked before any HIP call."""
+    n_inst, L = 6, 100
+    offs = (ctypes.c_int64 * (n_inst + 1))(*[i * L for i in range(n_inst + 1)])
+    p = lbm.Params(s_psi=1.0).c()
+    ps = (type(p) * n_inst)(*([p] * n_inst))
+    b = ctypes.c_void_p()
+    Lb = lbm.lib()
+    assert Lb.lbm_batch_init(ctypes.byref(b), n_inst, offs, ps, None) == lbm.LBM_OK
+    shapes = (lbm.CTuning * 2)(lbm.CTuning(lbm.KERNEL_BLOCKED, 2, 8, 1),
+                               lbm.CTuning(lbm.KERNEL_BLOCKED, 4, 8, 2))
+    good = (ctypes.c_int32 * n_inst)(0, 1, 0, 1, 0, 1)
+    bad = (ctypes.c_int32 * n_inst)(0, 1, 2, 1, 0, 1)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    assert Lb.lbm_batch_set_groups(None, 2, shapes, good) == lbm.LBM_EINVAL
+    assert Lb.lbm_batch_set_groups(b, lbm.MAX_GROUPS + 1, shapes, good) == lbm.LBM_EINVAL
+    assert Lb.lbm_batch_set_groups(b, -1, shapes, good) == lbm.LBM_EINVAL
+    assert Lb.lbm_batch_set_groups(b, 2, None, good) == lbm.LBM_EINVAL
+    assert Lb.lbm_batch_set_groups(b, 2, shapes, None) == lbm.LBM_EINVAL
+    assert Lb.lbm_batch_set_groups(b, 2, shapes, bad) == lbm.LBM_EINVAL
+    badshape = (lbm.CTuning * 2)(lbm.CTuning(lbm.KERNEL_BLOCKED, 3, 8, 1),
+                                 lbm.CTuning(lbm.KERNEL_BLOCKED, 4, 8, 2))
+    assert Lb.lbm_batch_set_groups(b, 2, badshape, good) == lbm.LBM_EINVAL
+    assert Lb.lbm_batch_set_groups(b, 0, None, None) == lbm.LBM_OK
+    n = ctypes.c_int32(-1)
+    assert Lb.lbm_batch_get_groups(b, ctypes.byref(n), None, None) == lbm.LBM_OK
+    assert n.value == 0
+    assert Lb.lbm_batch_get_groups(b, None, None, None) == lbm.LBM_EINVAL
+    Lb.lbm_batch_destroy(b)

@@ -101,6 +101,62 @@ def test_batch_bitwise_equals_single_lattice(mixed):
             assert np.array_equal(g, singles[i]), (shape, i)
 
 
+def _groups_by_length(lens, shapes):
+    """Assignment by length: the widest shape whose tile is at most a
+    quarter of the lattice, else the narrowest."""
+    import numpy as np
+    widths = [64 * P * W for P, K, W in shapes]
+    order = sorted(range(len(shapes)), key=lambda g: -widths[g])
+    out = []
+    for L in lens:
+        g = next((g for g in order if 4 * widths[g] <= L), order[-1])
+        out.append(g)
+    return np.asarray(out, dtype=np.int32)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 37])
+def test_shape_groups_bitwise_equal_single_shape(steps):
+    """Lattices split over three tile shapes, each group a launch sequence
+    on its own stream: the state equals the single-shape run bit for bit
+    (every shape rounds the same), for direct launches and graph replays;
+    steps = 1 takes the odd-launch path (result copied back after the join)."""
+    rng = np.random.default_rng(17)
+    lens = [9000, 60, 3001, 700, 20000, 5, 2048, 130, 4096, 11111, 640, 333]
+    names = ["paper", "odd", "linear", "paper", "odd", "nosource",
+             "paper", "odd", "paper", "fluid", "odd", "paper"]
+    params = [oracle_params(p) for p in names]
+    states = [random_state(rng, L, p, amp=0.1, u=0.05, ds=0.1)
+              for L, p in zip(lens, params)]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    say(f"shape groups steps={steps}")
+    b = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    b.set_tuning(4, 16, 4)
+    f0 = torch.from_numpy(pack(states)).to(dev())
+    ref = f0.clone()
+    b.run(ref, steps, use_graph=False)
+    shapes = [(8, 40, 4), (4, 16, 4), (2, 8, 1)]
+    b.set_groups(shapes, _groups_by_length(lens, shapes))
+    got_shapes, go = b.get_groups()
+    assert got_shapes == shapes and go is not None
+    f = f0.clone()
+    b.run(f, steps, use_graph=False)
+    assert torch.equal(f, ref)
+    for rep in range(3):
+        f = f0.clone()
+        _ = (f * 2).sum().item()
+        b.run(f, steps, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(f, ref), rep
+    # back to one shape
+    b.set_groups([])
+    f = f0.clone()
+    b.run(f, steps, use_graph=False)
+    assert torch.equal(f, ref)
+    want = oracle_runs(states, params, steps)
+    for i, (g, w) in enumerate(zip(unpack(ref.cpu().numpy(), offsets), want)):
+        assert max_err(g, w) < TOL, i
+
+
 def test_graph_replays_match_direct_launches():
     """The captured graph, replayed several times with eager work and
     synchronisations in between, gives bitwise the direct launches' result."""
@@ -219,6 +275,10 @@ def test_autotune_restores_state_and_caches(tmp_path):
     b2 = lbm().Batch(offsets, [gpu_params(p) for p in params])
     t2 = b2.autotune(f, probe_steps=16, cache_path=cache)
     assert t2 == t1
+    g1, g2 = b.get_groups(), b2.get_groups()
+    assert g1[0] == g2[0] and (g1[1] is None) == (g2[1] is None)
+    if g1[1] is not None:
+        assert np.array_equal(g1[1], g2[1]) and "groups" in val
     # the tuned batch still matches the oracle
     b2.run(f, 10)
     got = unpack(f.cpu().numpy(), offsets)
@@ -235,3 +295,36 @@ def test_autotune_restores_state_and_caches(tmp_path):
     assert len(json.load(open(cache))) == 2
     lat.step(g, 9)
     assert max_err(g.cpu().numpy(), oracle.run(s0, 9, po)) < TOL, t
+
+
+def test_autotune_shape_groups_wide_lengths(tmp_path):
+    """Lengths spread over 300 .. 30000 nodes (log-uniform): the autotuner
+    times single shapes and the best modelled grouping; whatever it keeps,
+    the state is restored, the cache round-trips, and the tuned run equals
+    the run of its single shape bit for bit."""
+    rng = np.random.default_rng(8)
+    lens = np.round(np.exp(rng.uniform(np.log(300), np.log(30000), 160))).astype(int)
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    params = [oracle_params("paper", s_e=float(s)) for s in rng.uniform(1.2, 1.8, len(lens))]
+    states = [random_state(rng, L, p, amp=0.05, u=0.02, ds=0.05) for L, p in zip(lens, params)]
+    say(f"autotune groups, {len(lens)} lattices, {offsets[-1]} nodes")
+    b = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    f0 = torch.from_numpy(pack(states)).to(dev())
+    f = f0.clone()
+    cache = str(tmp_path / "tune.json")
+    t = b.autotune(f, probe_steps=24, cache_path=cache)
+    assert torch.equal(f, f0)
+    shapes, go = b.get_groups()
+    say(f"  tuning {t}, groups {shapes}")
+    entry = next(iter(json.load(open(cache)).values()))
+    assert ("groups" in entry) == bool(shapes)
+    b.run(f, 13, use_graph=True)
+    single = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    single.set_tuning(t["nodes_per_lane"], t["steps_per_launch"], t["waves_per_group"])
+    g = f0.clone()
+    single.run(g, 13, use_graph=False)
+    assert torch.equal(f, g)
+    b2 = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    b2.autotune(f0.clone(), probe_steps=24, cache_path=cache)
+    s2, go2 = b2.get_groups()
+    assert s2 == shapes and ((go is None and go2 is None) or np.array_equal(go, go2))
