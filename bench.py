@@ -314,13 +314,15 @@ def main():
         f"state finite and mass conserved: {ok}")
 
     # launches of the blocked kernel per run, and node-updates they compute
-    # (tiles of W nodes, W - 4k of them stored, for a launch of k steps)
+    # (tiles of W = P (62 Wg + 2) nodes, W - 4k of them stored, for a launch
+    # of k steps; every tile computes 64 P Wg node-updates per step, the
+    # two-lane overlaps of its wavefronts included)
     P, K, Wg = (tune["nodes_per_lane"], tune["steps_per_launch"],
                 tune["waves_per_group"])
     ks = split_steps(T, K)
     L = len(ks)
-    W = 64 * P * Wg
-    computed = sum(-(-n // (W - 4 * k)) * W * k for k in ks)
+    W = P * (62 * Wg + 2)
+    computed = sum(-(-n // (W - 4 * k)) * 64 * P * Wg * k for k in ks)
     launch_ms = ms / (args.steps * L)
     run_s = ms / args.steps * 1e-3
     Fi = args.instr_per_node or per_node_update("fp64_instr_per_node_update")

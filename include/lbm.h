@@ -30,6 +30,10 @@
 #include <stddef.h>
 #include <stdint.h>
 
+/* Functions of this header are the library's only exported symbols (it is
+ * built with hidden visibility). */
+#define LBM_API __attribute__((visibility("default")))
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -102,26 +106,26 @@ typedef struct lbm_tuning {
 /* ----------------------------------------------------------------- misc */
 
 /* Message of the last failing call on this thread ("" if none). */
-const char* lbm_last_error(void);
+LBM_API const char* lbm_last_error(void);
 
 /* Relaxation coupling of section 7: sigma = 1/s - 1/2 (eq. henon),
  * sigma_psi = (3/2)(gamma/Pr) sigma_e (eq. lien-sigma-sigma), s_eps = 1.5
  * (step (iii) of section 8).  ds_psi_ds_e (may be NULL) receives the
  * derivative of s_psi with respect to s_e.  Host only. */
-int lbm_coupled_rates(double s_e, double gamma, double prandtl, double* s_psi,
-                      double* s_eps, double* ds_psi_ds_e);
+LBM_API int lbm_coupled_rates(double s_e, double gamma, double prandtl, double* s_psi,
+                              double* s_eps, double* ds_psi_ds_e);
 
 /* ----------------------------------------------------- single lattice */
 
 /* Creates a handle for one periodic lattice of 3 <= n <= 2^36 nodes.  Validates the
  * constants (all positive, gamma > 1, rates in (0, 2)).  stream: see above.
  * No device memory is allocated.  The handle owns host state only. */
-int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream);
-void lbm_destroy(lbm_handle* h);
+LBM_API int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream);
+LBM_API void lbm_destroy(lbm_handle* h);
 /* Changes the stream later calls enqueue on. */
-int lbm_set_stream(lbm_handle* h, void* stream);
+LBM_API int lbm_set_stream(lbm_handle* h, void* stream);
 /* Replaces the constants (same validation as lbm_init). */
-int lbm_set_params(lbm_handle* h, const lbm_params* p);
+LBM_API int lbm_set_params(lbm_handle* h, const lbm_params* p);
 
 /* Workspace kinds. */
 enum {
@@ -132,44 +136,46 @@ enum {
 };
 /* Bytes of caller workspace that calls of the given kind need (0 on a bad
  * handle). */
-size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
+LBM_API size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
 
 /* Kernel selection.  lbm_set_tuning validates the shape (P in {2,4,8},
- * 1 <= K, 4K < 64 P waves_per_group, waves_per_group in {1,2,4,8}).
- * The blocked kernel gives each workgroup of waves_per_group wavefronts a
- * tile of 64 P waves_per_group nodes held in registers for K steps.  The
+ * waves_per_group W in {1,2,4,8}, 1 <= K, 4K < P (62 W + 2)).
+ * The blocked kernel gives each workgroup of W wavefronts a tile of
+ * P (62 W + 2) nodes held in registers for K steps (64 P per wavefront,
+ * neighbouring wavefronts sharing two lanes) and stores its interior of
+ * P (62 W + 2) - 4K nodes.  The
  * default depends on the lattice length (P = 8, K = 40, 4 wavefronts for long
  * lattices; narrower tiles for short ones or few tiles).  Every
  * kernel and tile shape rounds each node-update identically: results are
  * bitwise independent of the tuning. */
-int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);
-int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
+LBM_API int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);
+LBM_API int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
 
 /* Equilibrium initialisation: f = M^-1 (rho, J, zeta, e_eq, psi_eq, eps_eq)
  * at every node, from device arrays rho, J, zeta of n doubles (the
  * equilibria of section 8, or of section 7 if eq_kind = 1).  f: device,
  * 6*n doubles. */
-int lbm_set_equilibrium(lbm_handle* h, const double* rho, const double* J,
-                        const double* zeta, double* f);
+LBM_API int lbm_set_equilibrium(lbm_handle* h, const double* rho, const double* J,
+                                const double* zeta, double* f);
 
 /* Advances the state f (device, 6*n doubles) by nsteps >= 0 time steps of the
  * algorithm of section 8, steps (i)-(viii), in place.  ws: device workspace
  * of lbm_workspace_bytes(h, LBM_WS_STEP) bytes, contents overwritten.
  * f and ws must not overlap. */
-int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
-             int64_t nsteps);
+LBM_API int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
+                     int64_t nsteps);
 
 /* Macroscopic moments of a state: m (device, 6*n doubles) = M f_d at every
  * node, in the order rho, J, zeta, e, psi, eps (eq. M-d1q3q3). */
-int lbm_moments(lbm_handle* h, const double* f, double* m);
+LBM_API int lbm_moments(lbm_handle* h, const double* f, double* m);
 
 /* Diagnostics of a state (synchronising): out[0..7] = sum rho, sum J,
  * sum zeta, sum rho E, min rho, min T, count of non-finite entries of f,
  * count of nodes with rho <= 0 or T <= 0; rho E = p/(gamma-1) + J^2/(2 rho)
  * (section 5).  Returns LBM_ENONFINITE when either count is non-zero
  * (out is still filled). */
-int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,
-                    double out[8]);
+LBM_API int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,
+                            double out[8]);
 
 /* Autotuner (synchronising).  Times the blocked kernel on the caller's state
  * f for probe_steps time steps with each candidate shape (P in {2,4,8}, waves
@@ -181,8 +187,8 @@ int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,
  * adds the entry.  The
  * chosen shape becomes the handle's tuning and is returned in *out (may be
  * NULL). */
-int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
-                 int64_t probe_steps, const char* cache_path, lbm_tuning* out);
+LBM_API int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
+                         int64_t probe_steps, const char* cache_path, lbm_tuning* out);
 
 /* ----------------------------------------------- gradients (reverse mode)
  *
@@ -198,43 +204,44 @@ int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
  * lbm_equilibrium_adjoint / lbm_moments_adjoint use for this nsteps and
  * ckpt_every (0 on bad arguments): ceil(nsteps/ckpt_every) checkpoints,
  * min(ckpt_every, nsteps) - 1 recomputed states, one more state and tables. */
-size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
-                                   int64_t ckpt_every);
+LBM_API size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
+                                           int64_t ckpt_every);
 /* Advances f (device, 6*n) by nsteps steps in place like lbm_step, keeping
  * the checkpoints in ws.  Required before the calls below with the same ws,
  * nsteps and ckpt_every. */
-int lbm_forward_ckpt(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
-                     int64_t nsteps, int64_t ckpt_every);
+LBM_API int lbm_forward_ckpt(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
+                             int64_t nsteps, int64_t ckpt_every);
 /* Reverse sweep (synchronising for rbar).  fbar (device, 6*n): on entry
  * dL/df(T), on return dL/df(0).  rbar (host, 3): dL/d(s_e, s_psi, s_eps).
  * use_graph = 1 captures the launch sequence into a hipGraph on first use
  * (re-captured when ws, nsteps, ckpt_every, fbar or the tuning change). */
-int lbm_adjoint(lbm_handle* h, void* ws, size_t ws_bytes, int64_t nsteps,
-                int64_t ckpt_every, double* fbar, double rbar[3],
-                int use_graph);
+LBM_API int lbm_adjoint(lbm_handle* h, void* ws, size_t ws_bytes, int64_t nsteps,
+                        int64_t ckpt_every, double* fbar, double rbar[3],
+                        int use_graph);
 /* L = 1/2 sum_j (rho_j - target_j)^2 of the state f (target: device n
  * doubles, or NULL for rho0 everywhere); *loss (host, synchronising) and
  * fbar = dL/df (device, 6*n). */
-int lbm_loss(lbm_handle* h, const double* f, const double* target, void* ws,
-             size_t ws_bytes, double* loss, double* fbar);
+LBM_API int lbm_loss(lbm_handle* h, const double* f, const double* target, void* ws,
+                     size_t ws_bytes, double* loss, double* fbar);
 /* Reverse of lbm_set_equilibrium: given fbar = dL/df(0), the adjoints of the
  * initial fields (device, n doubles each). */
-int lbm_equilibrium_adjoint(lbm_handle* h, const double* rho, const double* J,
-                            const double* zeta, const double* fbar,
-                            double* rho_bar, double* J_bar, double* zeta_bar,
-                            void* ws, size_t ws_bytes);
+LBM_API int lbm_equilibrium_adjoint(lbm_handle* h, const double* rho, const double* J,
+                                    const double* zeta, const double* fbar,
+                                    double* rho_bar, double* J_bar, double* zeta_bar,
+                                    void* ws, size_t ws_bytes);
 /* Reverse of lbm_moments: fbar = M^T mbar (device, 6*n each). */
-int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
-                        void* ws, size_t ws_bytes);
+LBM_API int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
+                                void* ws, size_t ws_bytes);
 /* Kernel of the reverse sweep: LBM_KERNEL_PLAIN (default, AUTO) runs one
  * reverse step per launch, one node per thread (HBM-bound, 144 B per
  * node-step); LBM_KERNEL_BLOCKED keeps dL/df in registers for K reverse steps
  * of a forward-shaped tile (reads only the recomputed states, but needs about
  * 2.5x the arithmetic of a forward step per node; a P = 8 forward shape runs
- * its reverse as P = 4 with twice the wavefronts, and P = 8 with 8 wavefronts
- * is rejected with LBM_ENOTSUP by lbm_forward_ckpt).  Takes effect at the
- * next lbm_forward_ckpt. */
-int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
+ * its reverse as P = 4 with twice the wavefronts, at most 8, on tiles of
+ * 64 P W nodes; lbm_forward_ckpt rejects with LBM_ENOTSUP a K whose halo
+ * leaves those tiles no interior, 4K >= 2048, possible only for P = 8 with 8
+ * wavefronts).  Takes effect at the next lbm_forward_ckpt. */
+LBM_API int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
 
 /* ------------------------------------------------- batches of lattices */
 
@@ -246,17 +253,17 @@ int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
  * array of a batch state of 6 * n_total doubles, n_total = offsets[n_inst]
  * (array k of the state is doubles [k*n_total, (k+1)*n_total)).  params
  * (host, n_inst records) are validated as in lbm_init.  Both are copied. */
-int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
-                   const lbm_params* params, void* stream);
-void lbm_batch_destroy(lbm_batch* b);
-int lbm_batch_set_stream(lbm_batch* b, void* stream);
+LBM_API int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
+                           const lbm_params* params, void* stream);
+LBM_API void lbm_batch_destroy(lbm_batch* b);
+LBM_API int lbm_batch_set_stream(lbm_batch* b, void* stream);
 /* Tile shape of the batch (as lbm_set_tuning; the blocked kernel only).
  * Clears any shape groups. */
-int lbm_batch_set_tuning(lbm_batch* b, const lbm_tuning* t);
-int lbm_batch_get_tuning(const lbm_batch* b, lbm_tuning* t);
+LBM_API int lbm_batch_set_tuning(lbm_batch* b, const lbm_tuning* t);
+LBM_API int lbm_batch_get_tuning(const lbm_batch* b, lbm_tuning* t);
 
 /* Shape groups of lbm_batch_run.  A tile holds nodes of one lattice, so a
- * lattice of L nodes costs ceil(L / (64 P W - 4K)) whole tiles: short
+ * lattice of L nodes costs ceil(L / (P (62 W + 2) - 4K)) whole tiles: short
  * lattices waste most of a wide tile, long ones run best on it.  With
  * groups, lattice i runs with shapes[group_of[i]] (host arrays of n_groups
  * and n_inst entries, 1 <= n_groups <= LBM_MAX_GROUPS), each group as its
@@ -267,65 +274,65 @@ int lbm_batch_get_tuning(const lbm_batch* b, lbm_tuning* t);
  * calls keep using the single tuning.  lbm_batch_autotune sets groups when
  * they time faster. */
 enum { LBM_MAX_GROUPS = 4 };
-int lbm_batch_set_groups(lbm_batch* b, int32_t n_groups,
-                         const lbm_tuning* shapes, const int32_t* group_of);
+LBM_API int lbm_batch_set_groups(lbm_batch* b, int32_t n_groups,
+                                 const lbm_tuning* shapes, const int32_t* group_of);
 /* *n_groups (0: single tuning); shapes (capacity LBM_MAX_GROUPS) and
  * group_of (capacity n_inst) receive the assignment unless NULL. */
-int lbm_batch_get_groups(const lbm_batch* b, int32_t* n_groups,
-                         lbm_tuning* shapes, int32_t* group_of);
+LBM_API int lbm_batch_get_groups(const lbm_batch* b, int32_t* n_groups,
+                                 lbm_tuning* shapes, int32_t* group_of);
 /* Total nodes n_total of the batch (0 on a bad handle). */
-int64_t lbm_batch_total_nodes(const lbm_batch* b);
-size_t lbm_batch_workspace_bytes(const lbm_batch* b, int kind);
+LBM_API int64_t lbm_batch_total_nodes(const lbm_batch* b);
+LBM_API size_t lbm_batch_workspace_bytes(const lbm_batch* b, int kind);
 /* Uploads the per-lattice constants, offsets and the tile table of the
  * current tuning into ws (synchronising).  Required before the calls below
  * whenever ws, the tuning or the constants change. */
-int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes);
+LBM_API int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes);
 /* Equilibrium initialisation of every lattice from device arrays rho, J,
  * zeta of n_total doubles (batch layout). */
-int lbm_batch_set_equilibrium(lbm_batch* b, const double* rho, const double* J,
-                              const double* zeta, double* f, void* ws,
-                              size_t ws_bytes);
+LBM_API int lbm_batch_set_equilibrium(lbm_batch* b, const double* rho, const double* J,
+                                      const double* zeta, double* f, void* ws,
+                                      size_t ws_bytes);
 /* Advances every lattice of the batch state f (device, 6*n_total doubles) by
  * nsteps time steps, in place.  With use_graph = 1 the launches are captured
  * once into a hipGraph (re-captured when f, ws, nsteps or the tuning change)
  * and replayed with one hipGraphLaunch on the stream. */
-int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
-                  int64_t nsteps, int use_graph);
+LBM_API int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
+                          int64_t nsteps, int use_graph);
 /* Moments m = M f of every node (device, 6*n_total doubles, moment order as
  * lbm_moments). */
-int lbm_batch_moments(lbm_batch* b, const double* f, double* m, void* ws,
-                      size_t ws_bytes);
+LBM_API int lbm_batch_moments(lbm_batch* b, const double* f, double* m, void* ws,
+                              size_t ws_bytes);
 /* Per-lattice diagnostics (synchronising): out (host, 8*n_inst doubles) gets
  * the eight values of lbm_diagnostics for each lattice.  Returns
  * LBM_ENONFINITE if any lattice has a non-finite or non-physical node. */
-int lbm_batch_diagnostics(lbm_batch* b, const double* f, void* ws,
-                          size_t ws_bytes, double* out);
+LBM_API int lbm_batch_diagnostics(lbm_batch* b, const double* f, void* ws,
+                                  size_t ws_bytes, double* out);
 /* Autotuner of the batch (as lbm_autotune; calls lbm_batch_prepare). */
-int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
-                       int64_t probe_steps, const char* cache_path,
-                       lbm_tuning* out);
+LBM_API int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
+                               int64_t probe_steps, const char* cache_path,
+                               lbm_tuning* out);
 
 /* Batch forms of the gradient calls: as above, lattice by lattice.  rbar
  * (device, 3*n_inst) holds dL_i/d(s_e, s_psi, s_eps) of lattice i; loss
  * (device, n_inst) the per-lattice losses.  Rate gradients are reduced in a
  * fixed order (deterministic). */
-size_t lbm_batch_adjoint_workspace_bytes(const lbm_batch* b, int64_t nsteps,
-                                         int64_t ckpt_every);
-int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
-                           int64_t nsteps, int64_t ckpt_every);
-int lbm_batch_adjoint(lbm_batch* b, void* ws, size_t ws_bytes, int64_t nsteps,
-                      int64_t ckpt_every, double* fbar, double* rbar,
-                      int use_graph);
-int lbm_batch_loss(lbm_batch* b, const double* f, const double* target,
-                   void* ws, size_t ws_bytes, double* loss, double* fbar);
-int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
-                                  const double* J, const double* zeta,
-                                  const double* fbar, double* rho_bar,
-                                  double* J_bar, double* zeta_bar, void* ws,
-                                  size_t ws_bytes);
-int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
-                              void* ws, size_t ws_bytes);
-int lbm_batch_set_adjoint_kernel(lbm_batch* b, int kernel);
+LBM_API size_t lbm_batch_adjoint_workspace_bytes(const lbm_batch* b, int64_t nsteps,
+                                                 int64_t ckpt_every);
+LBM_API int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
+                                   int64_t nsteps, int64_t ckpt_every);
+LBM_API int lbm_batch_adjoint(lbm_batch* b, void* ws, size_t ws_bytes, int64_t nsteps,
+                              int64_t ckpt_every, double* fbar, double* rbar,
+                              int use_graph);
+LBM_API int lbm_batch_loss(lbm_batch* b, const double* f, const double* target,
+                           void* ws, size_t ws_bytes, double* loss, double* fbar);
+LBM_API int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
+                                          const double* J, const double* zeta,
+                                          const double* fbar, double* rho_bar,
+                                          double* J_bar, double* zeta_bar, void* ws,
+                                          size_t ws_bytes);
+LBM_API int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
+                                      void* ws, size_t ws_bytes);
+LBM_API int lbm_batch_set_adjoint_kernel(lbm_batch* b, int kernel);
 
 #ifdef __cplusplus
 }

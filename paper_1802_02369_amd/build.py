@@ -20,6 +20,8 @@ HIPFLAGS = [
     # copy per polynomial coefficient held in a vector register
     "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
     "-Wno-unused-command-line-argument",
+    # only the functions of include/lbm.h are exported (LBM_API)
+    "-fvisibility=hidden",
 ]
 
 

@@ -4,13 +4,15 @@
 // Forward kernels:
 //   k_step_plain   one time step per launch, one node per thread; the
 //                  neighbours' u and T for the source term go through LDS.
-//   k_step_tile    K time steps per launch.  Each 64-lane wavefront owns a
-//                  tile of 64*P consecutive nodes (P per lane, contiguous)
-//                  held in VGPRs for all K steps; neighbour values move
-//                  between lanes with DPP wave shifts.  A step has radius 2
-//                  (the source reads u, T at j+-1 of the node whose
-//                  populations stream to j+-1), so a tile loads 2K halo
-//                  nodes on each side and stores its 64P - 4K interior nodes.
+//   k_step_tile    K time steps per launch.  Each 64-lane wavefront holds
+//                  64*P consecutive nodes (P per lane, contiguous) in VGPRs
+//                  for all K steps; neighbour values move between lanes with
+//                  DPP wave shifts, and the wavefronts of a workgroup overlap
+//                  by two lanes that are refreshed through LDS every P/2
+//                  steps.  A step has radius 2 (the source reads u, T at
+//                  j+-1 of the node whose populations stream to j+-1), so a
+//                  tile loads 2K halo nodes on each side and stores its
+//                  interior.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -242,22 +244,30 @@ __global__ __launch_bounds__(kPlainBlock) void k_step_plain(
 }
 
 // K time steps of one register-resident tile per workgroup (see the file
-// header).  The workgroup has WG wavefronts; wavefront w owns the 64P nodes
-// [w*64P, (w+1)*64P) of the tile, lane l of it the P consecutive nodes
-// starting at w*64P + l*P.  Tile t stores nodes [t*OUT, t*OUT + OUT) with
-// OUT = 64*P*WG - 4K and loads nodes [t*OUT - 2K, t*OUT + OUT + 2K)
+// header).  The workgroup has WG wavefronts of 64 lanes, lane l of wavefront
+// w holding the P consecutive nodes starting at tile index w*62P + (l-1)P
+// (l = 0..63; wavefront 0 starts at tile index 0).  Neighbouring wavefronts
+// overlap by two lanes: lane 0 of wavefront w > 0 mirrors lane 62 of w-1,
+// lane 63 of w < WG-1 mirrors lane 1 of w+1.  A tile thus spans
+// tile_nodes = P(62 WG + 2) nodes; tile t stores nodes [t*OUT, t*OUT + OUT)
+// with OUT = tile_nodes - 4K and loads [t*OUT - 2K, t*OUT + OUT + 2K)
 // (periodic).
 //
-// One time step of a register tile.  The source of node k needs u, T of k-1
-// and k+1, so the collisions run in the order P-1, 0, 1, ..., P-2 and each
-// source is applied as soon as its right neighbour exists; only a window of
-// three nodes' (u, T) stays live besides the populations.  With WG > 1 the
-// first and last lanes of a wavefront take their outside neighbours from the
-// adjacent wavefronts through LDS (two workgroup barriers per step; each
-// slot of `bnd` is written and read between the same pair of barriers).
-template <int P, int WG, int EQ>
-__device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
-                                          Boundary* bnd, int lane, int wave) {
+// Every step runs within the wavefront (lane neighbours through DPP).  The
+// outermost lanes have no neighbour there; as one step has radius 2, the
+// error this leaves at a mirror lane's outer end moves two nodes inwards per
+// step and reaches the wavefront's own lanes after P/2 steps.  So every P/2
+// steps the wavefronts copy their edge lanes 1 and 62 into the neighbours'
+// mirror lanes through LDS (one workgroup barrier per copy, double-buffered);
+// each wavefront stores only its own lanes.  The error at the tile's two
+// outer ends is what the halo of 2K nodes absorbs.
+//
+// One time step of a wavefront's nodes.  The source of node k needs u, T of
+// k-1 and k+1, so the collisions run in the order P-1, 0, 1, ..., P-2 and
+// each source is applied as soon as its right neighbour exists; only a window
+// of three nodes' (u, T) stays live besides the populations.
+template <int P, int EQ>
+__device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P]) {
   double uA, TA, rwA, wA;  // node P-1, collided first
   lbm::collide_local<EQ>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
                      f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
@@ -265,29 +275,8 @@ __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
   __builtin_amdgcn_sched_barrier(0);
   lbm::collide_local<EQ>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0], f[5][0],
                      um, Tm, rwm, wm);
-  if (WG > 1) {
-    if (lane == 63) {
-      bnd[wave].v[0] = uA;
-      bnd[wave].v[1] = TA;
-    }
-    if (lane == 0) {
-      bnd[wave].v[2] = um;
-      bnd[wave].v[3] = Tm;
-    }
-    __syncthreads();
-  }
   double ul = lbm::from_left(uA), Tl = lbm::from_left(TA);
-  double uR = lbm::from_right(um), TR = lbm::from_right(Tm);
-  if (WG > 1) {
-    if (lane == 0 && wave > 0) {
-      ul = bnd[wave - 1].v[0];
-      Tl = bnd[wave - 1].v[1];
-    }
-    if (lane == 63 && wave < WG - 1) {
-      uR = bnd[wave + 1].v[2];
-      TR = bnd[wave + 1].v[3];
-    }
-  }
+  const double uR = lbm::from_right(um), TR = lbm::from_right(Tm);
 #pragma unroll
   for (int k = 0; k < P; ++k) {
     double ur, Tr, rwr = 0.0, wr = 0.0;
@@ -318,29 +307,10 @@ __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
     wm = wr;
   }
   // (viii) streaming: + populations move one node right, - one node left.
-  double fpL = lbm::from_left(f[1][P - 1]);
-  double gpL = lbm::from_left(f[4][P - 1]);
-  double fmR = lbm::from_right(f[2][0]);
-  double gmR = lbm::from_right(f[5][0]);
-  if (WG > 1) {
-    if (lane == 63) {
-      bnd[wave].v[4] = f[1][P - 1];
-      bnd[wave].v[5] = f[4][P - 1];
-    }
-    if (lane == 0) {
-      bnd[wave].v[6] = f[2][0];
-      bnd[wave].v[7] = f[5][0];
-    }
-    __syncthreads();
-    if (lane == 0 && wave > 0) {
-      fpL = bnd[wave - 1].v[4];
-      gpL = bnd[wave - 1].v[5];
-    }
-    if (lane == 63 && wave < WG - 1) {
-      fmR = bnd[wave + 1].v[6];
-      gmR = bnd[wave + 1].v[7];
-    }
-  }
+  const double fpL = lbm::from_left(f[1][P - 1]);
+  const double gpL = lbm::from_left(f[4][P - 1]);
+  const double fmR = lbm::from_right(f[2][0]);
+  const double gmR = lbm::from_right(f[5][0]);
 #pragma unroll
   for (int k = P - 1; k > 0; --k) {
     f[1][k] = f[1][k - 1];
@@ -357,11 +327,39 @@ __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P],
   f[5][P - 1] = gmR;
 }
 
+// Refresh of the mirror lanes: lanes 1 and 62 publish their populations in
+// `edge` (one buffer of the double-buffered pair: a buffer is written again
+// only after the next refresh's barrier, which every reader of its previous
+// contents has passed), then lane 0 takes lane 62 of the wavefront to its
+// left and lane 63 lane 1 of the wavefront to its right.
+template <int P, int WG>
+__device__ __forceinline__ void mirror_refresh(double (&f)[6][P],
+                                               double (*edge)[2][6 * P],
+                                               int lane, int wave) {
+  if (lane == 1 || lane == 62) {
+    double* d = edge[wave][lane == 62];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) d[q * P + k] = f[q][k];
+  }
+  __syncthreads();
+  const bool left = lane == 0 && wave > 0, right = lane == 63 && wave < WG - 1;
+  if (left || right) {
+    const double* e = left ? edge[wave - 1][1] : edge[wave + 1][0];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[q][k] = e[q * P + k];
+  }
+}
+
 // Tile t of a lattice of n nodes (array stride S) starting at lattice index
-// `start` = t*OUT - H, OUT = W - 2H: load, K <= H/2 steps, store of the
-// interior [H, W - H) (one step has radius 2, so K steps need H >= 2K).
-// With every_step, the interior is stored after each step s = 1..K into the
-// state fout + (s-1)*state_stride (the states a reverse sweep needs).
+// `start` = t*OUT - H, OUT = tile_nodes - 2H: load, K <= H/2 steps, store of
+// the interior [H, tile_nodes - H) (one step has radius 2, so K steps need
+// H >= 2K).  With every_step, the interior is stored after each step
+// s = 1..K into the state fout + (s-1)*state_stride (the states a reverse
+// sweep needs).
 template <int P, int WG, int EQ>
 __device__ __forceinline__ void tile_run(const Consts& c,
                                          const double* __restrict__ fin,
@@ -369,25 +367,34 @@ __device__ __forceinline__ void tile_run(const Consts& c,
                                          int64_t n, int64_t start, int H,
                                          int K, bool every_step = false,
                                          int64_t state_stride = 0) {
-  constexpr int WW = 64 * P;
-  constexpr int W = WG * WW;
+  constexpr int WW = 64 * P;       // nodes of one wavefront
+  constexpr int WS = 62 * P;       // wavefront stride in the tile
+  constexpr int W = lbm::tile_nodes(P, WG);
   __shared__ double stage[WG * (WW + 64)];
-  __shared__ Boundary bnd[WG];
+  __shared__ double edge[2][WG][2][6 * P];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* lds = stage + wave * (WW + 64);
-  const int64_t wstart = start + wave * WW;
+  const int64_t wstart = start + wave * WS;
   const bool inside = start >= 0 && start + W <= n;
   const bool small = n < W;
   double f[6][P];
   tile_load<P>(fin, S, n, wstart, inside, small, lane, lds, f);
-  // tile indices [H, W - H) are valid; in this wavefront's numbering:
-  const int lo = H - wave * WW, hi = W - H - wave * WW;
+  // the tile's valid indices [H, W - H), in this wavefront's numbering and
+  // restricted to its own lanes (the mirror lanes belong to the neighbours)
+  const int lo = max(H - wave * WS, wave > 0 ? P : 0);
+  const int hi = min(W - H - wave * WS, wave < WG - 1 ? WW - P : WW);
+  int since = 0, buf = 0;
   for (int step = 0; step < K; ++step) {
-    tile_step<P, WG, EQ>(c, f, bnd, lane, wave);
+    tile_step<P, EQ>(c, f);
     if (every_step)
       tile_store<P>(fout + step * state_stride, S, n, wstart, lo, hi, lane,
                     lds, f);
+    if (WG > 1 && ++since == P / 2 && step + 1 < K) {
+      mirror_refresh<P, WG>(f, edge[buf], lane, wave);
+      buf ^= 1;
+      since = 0;
+    }
   }
   if (!every_step) tile_store<P>(fout, S, n, wstart, lo, hi, lane, lds, f);
 }
@@ -398,7 +405,7 @@ __global__ __launch_bounds__(64 * WG, P == 2 ? 4 : 1) void k_step_tile(
     int64_t n, int K, int64_t ntiles) {
   const int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;  // uniform over the workgroup
-  const int OUT = 64 * P * WG - 4 * K;
+  const int OUT = lbm::tile_nodes(P, WG) - 4 * K;
   tile_run<P, WG, EQ>(c, fin, fout, n, n, tile * OUT - 2 * K, 2 * K, K);
 }
 
@@ -420,7 +427,7 @@ __global__ __launch_bounds__(64 * WG, P == 2 ? 4 : 1) void k_batch_tile(
   const int64_t off = offs[tr.inst];
   const int64_t n = offs[tr.inst + 1] - off;
   const Consts c = cs[tr.inst];
-  const int OUT = 64 * P * WG - 2 * H;
+  const int OUT = lbm::tile_nodes(P, WG) - 2 * H;
   tile_run<P, WG, EQ>(c, fin + off, fout + off, S, n, (int64_t)tr.t * OUT - H, H,
                   K, EVERY, state_stride);
 }
@@ -582,7 +589,7 @@ int launch_step_plain(const Consts& c, const double* fin, double* fout,
   return hip_check(hipGetLastError(), "k_step_plain");
 }
 
-int64_t tile_out(int P, int K, int wg) { return 64 * P * wg - 4 * K; }
+int64_t tile_out(int P, int K, int wg) { return tile_nodes(P, wg) - 4 * K; }
 
 template <int P, int WG>
 static void launch_tile_t(const Consts& c, const double* fin, double* fout,
@@ -668,7 +675,7 @@ int launch_batch_tile(const Consts* cs, const int64_t* offs,
                       double* fout, int64_t S, int P, int H, int K, int wg,
                       int eq, hipStream_t s, int64_t state_stride) {
   if (ntiles <= 0) return LBM_OK;
-  if (K < 1 || 2 * K > H || 2 * H >= 64 * P * wg)
+  if (K < 1 || 2 * K > H || 2 * H >= tile_nodes(P, wg))
     return set_err(LBM_EINVAL, "bad batched tile geometry H=%d K=%d", H, K);
 #define LBM_BATCH_CASE(PP, WW)                                              \
   if (P == PP && wg == WW) {                                                \

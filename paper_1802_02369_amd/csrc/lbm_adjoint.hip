@@ -611,13 +611,43 @@ __global__ void k_rbar_reduce(const int64_t* __restrict__ first,
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct AdjLayout {
-  int64_t n_fwd, n_rec, n_adj, n_ck, n_seg;
-  size_t consts, offs, fwd_tiles, rec_tiles, adj_tiles, adj_first, rec_first,
+  int64_t n_fwd, n_rec, n_rev, n_adj, n_ck, n_seg;
+  size_t consts, offs, fwd_tiles, rec_tiles, rev_tiles, adj_tiles, adj_first,
+      rev_first,
       rslots, scratch, pp, ckpt, seg, total;
 };
 
 // The recompute runs with the forward tile shape and stores every step.
 lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
+
+// Tile shape of the blocked reverse kernel for a forward tuning: the same P
+// and wavefronts, except that P = 8 (too many registers for the reverse
+// step) runs as P = 4 with twice the wavefronts, at most 8.  Its tiles span
+// 64 P W nodes (no overlap between wavefronts) with the forward halo 2K.
+lbm_tuning rev_tuning(const lbm_tuning& t) {
+  lbm_tuning r = t;
+  if (t.nodes_per_lane == 8) {
+    r.nodes_per_lane = 4;
+    r.waves_per_group = std::min(2 * t.waves_per_group, 8);
+  }
+  return r;
+}
+
+int64_t rev_out(const lbm_tuning& t) {
+  const lbm_tuning r = rev_tuning(t);
+  return 64 * (int64_t)r.nodes_per_lane * r.waves_per_group -
+         4 * (int64_t)t.steps_per_launch;
+}
+
+// Tiles of `out` output nodes covering every lattice (0 if out < 1: such a
+// shape is refused before any table is built).
+int64_t tiles_of(const lbm_batch* b, int64_t out) {
+  if (out < 1) return 0;
+  int64_t s = 0;
+  for (int64_t i = 0; i < b->n_inst; ++i)
+    s += (b->offsets[i + 1] - b->offsets[i] + out - 1) / out;
+  return s;
+}
 
 int64_t adj_tile_count(const lbm_batch* b) {
   int64_t s = 0;
@@ -630,6 +660,7 @@ AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C) {
   AdjLayout L{};
   L.n_fwd = b->count_tiles(b->tune);
   L.n_rec = b->count_tiles(rec_tuning(b->tune));
+  L.n_rev = tiles_of(b, rev_out(b->tune));
   L.n_adj = adj_tile_count(b);
   L.n_ck = nsteps > 0 ? (nsteps + C - 1) / C : 1;
   L.n_seg = std::max<int64_t>(0, std::min(C, nsteps) - 1);
@@ -643,15 +674,17 @@ AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C) {
   o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_fwd));
   L.rec_tiles = o;
   o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_rec));
+  L.rev_tiles = o;
+  o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_rev));
   L.adj_tiles = o;
   o = align256(o + sizeof(TileRef) * std::max<int64_t>(1, L.n_adj));
   L.adj_first = o;
   o = align256(o + sizeof(int64_t) * (b->n_inst + 1));
-  L.rec_first = o;
+  L.rev_first = o;
   o = align256(o + sizeof(int64_t) * (b->n_inst + 1));
   L.rslots = o;
   o = align256(o + sizeof(double) * 3 *
-                       std::max<int64_t>(1, std::max(L.n_adj, L.n_rec)));
+                       std::max<int64_t>(1, std::max(L.n_adj, L.n_rev)));
   L.scratch = o;  // per-lattice loss / rbar staging
   o = align256(o + sizeof(double) * 3 * b->n_inst);
   L.pp = o;
@@ -671,6 +704,7 @@ T* at(void* ws, size_t off) {
 
 std::vector<TileRef> tile_table(const lbm_batch* b, int64_t out) {
   std::vector<TileRef> v;
+  if (out < 1) return v;
   for (int64_t i = 0; i < b->n_inst; ++i) {
     const int64_t n = b->offsets[i + 1] - b->offsets[i];
     for (int64_t t = 0; t * out < n; ++t) v.push_back(TileRef{(int32_t)i, (int32_t)t});
@@ -723,7 +757,7 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
   const int64_t* offs = at<int64_t>(ws, L.offs);
   const size_t SD = 6 * (size_t)b->n_total;
   double* slots = at<double>(ws, L.rslots);
-  const int64_t nsl = 3 * std::max<int64_t>(1, std::max(L.n_adj, L.n_rec));
+  const int64_t nsl = 3 * std::max<int64_t>(1, std::max(L.n_adj, L.n_rev));
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((nsl + 255) / 256)), dim3(256), 0,
                      s, slots, nsl, 0.0);
   int rc = hip_check(hipGetLastError(), "k_fill");
@@ -759,14 +793,13 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
         std::swap(cur, oth);
       }
     } else {
-      // up to Krec reverse steps per launch on the forward tiles; a P = 8
-      // forward shape runs as P = 4 with twice the wavefronts (same tile
-      // width, so the same tile table)
-      const int Padj = Prec == 8 ? 4 : Prec, Wadj = Prec == 8 ? 2 * Wrec : Wrec;
+      // up to Krec reverse steps per launch on the reverse tile shape
+      const lbm_tuning rt = rev_tuning(b->tune);
+      const int Padj = rt.nodes_per_lane, Wadj = rt.waves_per_group;
       for (int64_t hi = len; hi > 0;) {
         const int64_t lo = std::max<int64_t>(0, hi - Krec);
         rc = launch_adjoint_tile(Padj, Wadj, cs, offs,
-                                 at<TileRef>(ws, L.rec_tiles), L.n_rec, ck,
+                                 at<TileRef>(ws, L.rev_tiles), L.n_rev, ck,
                                  at<double>(ws, L.seg), (int64_t)SD, (int)lo,
                                  (int)hi, cur, oth, b->n_total, 2 * Krec,
                                  slots, s);
@@ -783,7 +816,7 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
     return rc;
   hipLaunchKernelGGL(k_rbar_reduce, dim3((unsigned)((b->n_inst + 255) / 256)),
                      dim3(256), 0, s,
-                     at<int64_t>(ws, b->adj_plain ? L.adj_first : L.rec_first),
+                     at<int64_t>(ws, b->adj_plain ? L.adj_first : L.rev_first),
                      b->n_inst, (const double*)slots, rbar);
   return hip_check(hipGetLastError(), "k_rbar_reduce");
 }
@@ -828,11 +861,12 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     return set_err(LBM_EINVAL, "f and ws overlap");
   if (((uintptr_t)f | (uintptr_t)ws) & 7)
     return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
-  if (!b->adj_plain && b->tune.nodes_per_lane == 8 && b->tune.waves_per_group == 8)
+  if (!b->adj_plain && rev_out(b->tune) < 1)
     return set_err(LBM_ENOTSUP,
-                   "the blocked adjoint kernel has no form for the tile shape "
-                   "P = 8 with 8 wavefronts; use the one-step adjoint kernel "
-                   "or another tile shape");
+                   "the blocked adjoint kernel's tiles (P = 4, 8 wavefronts "
+                   "for this shape) cannot hold a halo of 2K = %d nodes; use "
+                   "the one-step adjoint kernel or a smaller K",
+                   2 * b->tune.steps_per_launch);
   const hipStream_t s = b->stream;
   int rc = LBM_OK;
   const bool same = b->adj_ws == ws && b->adj_nsteps == nsteps &&
@@ -840,11 +874,13 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
                     same_tuning(b->adj_tune, b->tune) &&
                     b->adj_plain_up == b->adj_plain;
   if (!same) {
-    // tables of this workspace layout: forward tiles, recompute tiles
-    // (one step, halo 2), adjoint tiles and each lattice's first adjoint tile
+    // tables of this workspace layout: forward and recompute tiles (the
+    // forward tile shape), tiles of the blocked and of the one-step reverse
+    // kernels, and each lattice's first tile in the two reverse tables
     const auto fwd = tile_table(b, tile_width(b->tune) - 4 * b->tune.steps_per_launch);
-    const auto rec =
-        tile_table(b, tile_width(b->tune) - 4 * b->tune.steps_per_launch);
+    const auto rec = tile_table(
+        b, tile_width(rec_tuning(b->tune)) - 4 * b->tune.steps_per_launch);
+    const auto rev = tile_table(b, rev_out(b->tune));
     const auto adj = tile_table(b, kAdjOut);
     auto firsts = [&](const std::vector<TileRef>& tab) {
       std::vector<int64_t> first(b->n_inst + 1, 0);
@@ -853,7 +889,7 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
       return first;
     };
     const auto first = firsts(adj);
-    const auto rfirst = firsts(rec);
+    const auto rfirst = firsts(rev);
     auto up = [&](size_t off, const void* src, size_t bytes) {
       if (!rc && bytes)
         rc = hip_check(hipMemcpyAsync(at<char>(ws, off), src, bytes,
@@ -864,9 +900,10 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     up(L.offs, b->offsets.data(), sizeof(int64_t) * (b->n_inst + 1));
     up(L.fwd_tiles, fwd.data(), sizeof(TileRef) * fwd.size());
     up(L.rec_tiles, rec.data(), sizeof(TileRef) * rec.size());
+    up(L.rev_tiles, rev.data(), sizeof(TileRef) * rev.size());
     up(L.adj_tiles, adj.data(), sizeof(TileRef) * adj.size());
     up(L.adj_first, first.data(), sizeof(int64_t) * first.size());
-    up(L.rec_first, rfirst.data(), sizeof(int64_t) * rfirst.size());
+    up(L.rev_first, rfirst.data(), sizeof(int64_t) * rfirst.size());
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (rc) return rc;
     drop_adjoint_graph(b);

@@ -23,9 +23,10 @@ int check_tuning(const lbm_tuning* t) {
   const int w = t->waves_per_group;
   if (w != 1 && w != 2 && w != 4 && w != 8)
     return set_err(LBM_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
-  if (K < 1 || 4 * K >= 64 * P * w)
+  if (K < 1 || 4 * K >= tile_nodes(P, w))
     return set_err(LBM_EINVAL,
-                   "steps_per_launch must satisfy 1 <= K < 16 P waves_per_group");
+                   "steps_per_launch must satisfy 1 <= K < P (62 "
+                   "waves_per_group + 2) / 4");
   return LBM_OK;
 }
 
@@ -46,7 +47,7 @@ std::vector<lbm_tuning> tuning_candidates() {
   for (int P : Ps)
     for (int W : Ws)
       for (int K : Ks)
-        if (16 * K <= 64 * P * W) v.push_back(lbm_tuning{LBM_KERNEL_BLOCKED, P, K, W});
+        if (16 * K <= tile_nodes(P, W)) v.push_back(lbm_tuning{LBM_KERNEL_BLOCKED, P, K, W});
   return v;
 }
 

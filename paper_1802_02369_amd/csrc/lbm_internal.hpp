@@ -114,8 +114,14 @@ inline bool same_tunings(const std::vector<lbm_tuning>& a,
   return true;
 }
 
+// Nodes spanned by a register tile of wg wavefronts of P nodes per lane:
+// neighbouring wavefronts share two lanes (one mirror lane each).
+__host__ __device__ constexpr int tile_nodes(int P, int wg) {
+  return P * (62 * wg + 2);
+}
+
 inline int64_t tile_width(const lbm_tuning& t) {
-  return 64 * (int64_t)t.nodes_per_lane * t.waves_per_group;
+  return tile_nodes(t.nodes_per_lane, t.waves_per_group);
 }
 }  // namespace lbm
 

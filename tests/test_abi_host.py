@@ -103,7 +103,7 @@ def test_init_and_workspace_and_tuning_host():
 
 
 @pytest.mark.parametrize("n,shape", [
-    (1 << 24, (8, 40, 4)),   # wide tiles: 8887 tiles of 1888 output nodes
+    (1 << 24, (8, 40, 4)),   # wide tiles: 9119 tiles of 1840 output nodes
     (1 << 21, (8, 40, 4)),
     (1 << 20, (4, 16, 4)),   # too few P = 8 tiles for 4 workgroups per CU
     (8192, (2, 8, 1)),       # small lattices: the narrowest tile
@@ -162,3 +162,29 @@ def test_batch_groups_validation_host():
     assert n.value == 0
     assert Lb.lbm_batch_get_groups(b, None, None, None) == lbm.LBM_EINVAL
     Lb.lbm_batch_destroy(b)
+
+
+@pytest.mark.parametrize("shape,ok", [
+    ((8, 40, 4), True), ((8, 9, 8), True), ((8, 511, 8), True),
+    ((8, 512, 8), False), ((4, 63, 1), True), ((2, 60, 8), True)])
+def test_blocked_adjoint_shape_check_host(shape, ok):
+    """Workspace sizes exist for every valid forward shape; the checkpointed
+    forward with the blocked reverse kernel refuses, before any HIP call, a
+    shape whose halo leaves the reverse tiles (P = 4 with up to 8 wavefronts
+    for P = 8, else the forward P and wavefronts; 64 P W nodes) no interior:
+    4K >= 2048 for P = 8 with 8 wavefronts."""
+    rc, h = _init(5000)
+    assert rc == lbm.LBM_OK
+    L = lbm.lib()
+    P, K, W = shape
+    t = lbm.CTuning(lbm.KERNEL_BLOCKED, P, K, W)
+    assert L.lbm_set_tuning(h, ctypes.byref(t)) == lbm.LBM_OK
+    assert L.lbm_set_adjoint_kernel(h, lbm.KERNEL_BLOCKED) == lbm.LBM_OK
+    nb = L.lbm_adjoint_workspace_bytes(h, 10, 5)
+    assert nb >= 6 * 5000 * 8
+    if not ok:
+        rc = L.lbm_forward_ckpt(h, ctypes.c_void_p(4096),
+                                ctypes.c_void_p(1 << 40), nb, 10, 5)
+        assert rc == lbm.LBM_ENOTSUP
+        assert b"halo" in L.lbm_last_error()
+    L.lbm_destroy(h)

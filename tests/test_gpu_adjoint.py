@@ -66,7 +66,8 @@ def test_one_adjoint_step(pname, n, adj):
 
 
 @pytest.mark.parametrize("kernel", ["plain", "blocked", "blocked_p4w2k5",
-                                    "blocked_p8w2k6", "plainfwd"])
+                                    "blocked_p8w2k6", "blocked_p8w8k9",
+                                    "plainfwd"])
 @pytest.mark.parametrize("pname,n,steps,ckpt", [
     ("paper", 64, 40, 7), ("odd", 300, 33, 33), ("nosource", 97, 25, 1),
     ("linear", 260, 18, 5), ("odd", 1200, 50, 8), ("fluid", 700, 37, 20),
@@ -92,6 +93,9 @@ def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
     elif kernel == "blocked_p8w2k6":
         lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
         lat.set_tuning(nodes_per_lane=8, steps_per_launch=6, waves_per_group=2)
+    elif kernel == "blocked_p8w8k9":
+        lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+        lat.set_tuning(nodes_per_lane=8, steps_per_launch=9, waves_per_group=8)
     aws = lat.adjoint_workspace(steps, ckpt, dev())
     r_, J_, z_ = T(rho), T(J), T(zeta)
     f = lat.equilibrium(r_, J_, z_)
@@ -106,14 +110,16 @@ def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
     np.testing.assert_allclose(r, sb, rtol=1e-10, atol=1e-12 * np.abs(sb).max())
 
 
-def test_blocked_adjoint_rejects_p8_with_8_waves():
-    """The reverse tile kernel has no form for P = 8 with 8 wavefronts: the
-    checkpointed forward refuses it before any launch; the one-step adjoint
-    kernel accepts the same tile shape."""
+def test_blocked_adjoint_rejects_halo_beyond_reverse_tile():
+    """P = 8 with 8 wavefronts runs its reverse on tiles of 2048 nodes (P = 4,
+    8 wavefronts): a forward K of 512 is a valid forward shape (tiles of 3984
+    nodes) but leaves the reverse tiles no interior, so the checkpointed
+    forward refuses it before any launch; the one-step adjoint kernel accepts
+    the same tile shape."""
     po = oracle_params("paper")
     n = 3000
     lat = lbm().Lattice(n, gpu_params(po))
-    lat.set_tuning(nodes_per_lane=8, steps_per_launch=16, waves_per_group=8)
+    lat.set_tuning(nodes_per_lane=8, steps_per_launch=512, waves_per_group=8)
     lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
     aws = lat.adjoint_workspace(10, 5, dev())
     f = T(random_state(np.random.default_rng(3), n, po))

@@ -105,7 +105,7 @@ def _groups_by_length(lens, shapes):
     """Assignment by length: the widest shape whose tile is at most a
     quarter of the lattice, else the narrowest."""
     import numpy as np
-    widths = [64 * P * W for P, K, W in shapes]
+    widths = [P * (62 * W + 2) for P, K, W in shapes]
     order = sorted(range(len(shapes)), key=lambda g: -widths[g])
     out = []
     for L in lens:
