@@ -93,13 +93,27 @@ constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;  // sqrt(1/2)
 // 5e-18; coefficients from csrc/gen_poly.py); ln x = k ln 2 + ln m with ln 2
 // in two parts (the additive reduction of Cody & Waite).  Error a few ulp.
 // x <= 0 gives NaN; so do NaN and +inf.
-__device__ __forceinline__ double ln_pos(double x) {
+//
+// ln_reduce splits x: the hardware mantissa mh in [1/2, 1) and a = 2 when
+// mh < sqrt(1/2), else 1, so that m = a mh exactly; m - 1 and m + 1 are
+// then single FMAs (a mh - 1 is exact).  ln_finish completes ln x from z.
+struct LnReduced {
+  double mh, a;
+  int k;
+};
+
+__device__ __forceinline__ LnReduced ln_reduce(double x) {
+  LnReduced r;
+  r.mh = __builtin_amdgcn_frexp_mant(x);
+  const bool lo = r.mh < kSqrtHalf;
+  r.a = lo ? 2.0 : 1.0;
+  r.k = __builtin_amdgcn_frexp_exp(x) - (lo ? 1 : 0);
+  return r;
+}
+
+__device__ __forceinline__ double ln_finish(double x, const LnReduced& rd,
+                                            double z) {
 #pragma clang fp contract(off)
-  double m = __builtin_amdgcn_frexp_mant(x);
-  const int lo = m < kSqrtHalf ? 1 : 0;
-  m = __builtin_amdgcn_ldexp(m, lo);  // exact doubling
-  const int k = __builtin_amdgcn_frexp_exp(x) - lo;
-  const double z = (m - 1.0) * recip(m + 1.0);
   const double w = z * z;
   double q = 0x1.2b584c80de001p-3;
   q = fma(q, w, 0x1.39fe603f8739ep-3);
@@ -109,12 +123,33 @@ __device__ __forceinline__ double ln_pos(double x) {
   q = fma(q, w, 0x1.99999999952e2p-2);
   q = fma(q, w, 0x1.5555555555558p-1);
   const double lm = z * fma(w, q, 2.0);
-  const double kd = (double)k;
+  const double kd = (double)rd.k;
   const double r = fma(kd, kLn2Hi, fma(kd, kLn2Lo, lm));
   // x <= 0: replace the high word by a quiet-NaN pattern (one select)
   const uint64_t b = __builtin_bit_cast(uint64_t, r);
   const uint32_t hi = x > 0.0 ? (uint32_t)(b >> 32) : 0x7ff80000u;
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (b & 0xffffffffu));
+}
+
+__device__ __forceinline__ double ln_pos(double x) {
+#pragma clang fp contract(off)
+  const LnReduced rd = ln_reduce(x);
+  const double z = fma(rd.a, rd.mh, -1.0) * recip(fma(rd.a, rd.mh, 1.0));
+  return ln_finish(x, rd, z);
+}
+
+// ln x and 1/x of a positive finite x with one reciprocal: R = 1/(x (m+1))
+// gives 1/x = R (m+1) and 1/(m+1) = R x (each within about two ulp: the
+// rounding of x (m+1), of R and of the product).  Non-positive, NaN or
+// infinite x give a NaN logarithm, as ln_pos.
+__device__ __forceinline__ double ln_inv(double x, double& inv) {
+#pragma clang fp contract(off)
+  const LnReduced rd = ln_reduce(x);
+  const double d = fma(rd.a, rd.mh, 1.0);
+  const double R = recip(x * d);
+  inv = R * d;
+  const double z = fma(rd.a, rd.mh, -1.0) * (R * x);
+  return ln_finish(x, rd, z);
 }
 
 // e^x for the moderate arguments of the equation of state.  Method (Cody &
@@ -202,15 +237,17 @@ __device__ __forceinline__ void equilibria(const Consts& c, double rho,
 //   eh = 3 (Jh uh + hP rh Th) - 2 rh,  psih = zh uh,
 //   epsh = (2/gamma) rh X + eh sh,  hP = c0^2/(gamma lambda^2).
 // (With rho0 = 1, rh is the density summed in the order of eq. M-d1q3q3.)
+// lr returns ln rh.
 __device__ __forceinline__ void thermo_scaled(const Consts& c, double rh,
                                               double Jh, double zh, double& uh,
                                               double& sh, double& X,
-                                              double& Th) {
+                                              double& Th, double& lr) {
 #pragma clang fp contract(off)
-  const double ir = recip(rh);
+  double ir;
+  lr = ln_inv(rh, ir);
   uh = Jh * ir;
   sh = zh * ir;
-  X = fma(c.gm1, ln_pos(rh), fma(c.gamma, sh, c.xs0));
+  X = fma(c.gm1, lr, fma(c.gamma, sh, c.xs0));
   Th = exp_fin(X);
 }
 
@@ -232,8 +269,8 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
   const double sg = gp + gm;
   const double zh = g0 + sg;
   // (iv) equilibria
-  double sh, X;
-  thermo_scaled(c, rh, Jh, zh, u, sh, X, T);
+  double sh, X, lr;
+  thermo_scaled(c, rh, Jh, zh, u, sh, X, T, lr);
   double jup, eh, psih, epsh;
   if (EQ == 0 || c.eq_kind == 0) {
     jup = fma(Jh, u, (c.hP * rh) * T);
@@ -241,7 +278,7 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
     psih = zh * u;
     epsh = fma(eh, sh, (c.two_g * rh) * X);
   } else if (c.eq_kind == 2) {
-    jup = fma(Jh, u, (c.hP * rh) * exp_fin(c.gm1 * ln_pos(rh)));
+    jup = fma(Jh, u, (c.hP * rh) * exp_fin(c.gm1 * lr));
     eh = fma(-2.0, rh, 3.0 * jup);
     psih = 0.0;
     epsh = 0.0;
@@ -290,8 +327,8 @@ __device__ __forceinline__ void node_uT(const Consts& c, double f0, double fp,
   const double rh = (f0 + fp) + fm;
   const double Jh = fp - fm;
   const double zh = g0 + (gp + gm);
-  double sh, X;
-  thermo_scaled(c, rh, Jh, zh, u, sh, X, T);
+  double sh, X, lr;
+  thermo_scaled(c, rh, Jh, zh, u, sh, X, T, lr);
 }
 
 // Step (vii): the increment of zeta at node j, already divided into the
