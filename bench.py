@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -126,9 +127,11 @@ def time_runs(fn, reset, runs: int, torch, stream):
     return total
 
 
-def cpu_baseline(n: int, steps: int = 3):
+def cpu_baseline(n: int, min_s: float = 12.0, max_steps: int = 20):
     """The oracle (single thread, as it stands) on a bounded sample of the
-    same workload: `steps` time steps of the full N = 2^24 lattice."""
+    same workload: whole time steps of the full N = 2^24 lattice, about
+    min_s seconds of them (one step timed first to size the rest, at most
+    max_steps in all)."""
     import numpy as np  # noqa: F401
 
     import oracle
@@ -139,8 +142,13 @@ def cpu_baseline(n: int, steps: int = 3):
     p = oracle.Params(s_e=cfg["s_e"], s_psi=s_psi, s_eps=s_eps)
     f = oracle.init(fl.rho, fl.J, fl.zeta, p)
     t0 = time.perf_counter()
-    oracle.run(f, steps, p)
+    f = oracle.run(f, 1, p)
+    t1 = time.perf_counter() - t0
+    more = max(0, min(max_steps - 1, int(math.ceil(min_s / t1)) - 1))
+    if more:
+        oracle.run(f, more, p)
     dt = time.perf_counter() - t0
+    steps = 1 + more
     return {"value": n * steps / dt / 1e9, "unit": "GLUPS", "cores": 1,
             "kind": "oracle",
             "sample": f"{steps} time steps of the N={n} lattice "
@@ -391,7 +399,7 @@ def main():
                                                        stream)
 
     if not args.no_cpu_baseline:
-        log("bench: oracle CPU baseline (about 15 s)")
+        log("bench: oracle CPU baseline (10 to 30 s)")
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
 

@@ -144,8 +144,12 @@ LBM_API size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
  * P (62 W + 2) nodes held in registers for K steps (64 P per wavefront,
  * neighbouring wavefronts sharing two lanes) and stores its interior of
  * P (62 W + 2) - 4K nodes.  The
- * default depends on the lattice length (P = 8, K = 40, 4 wavefronts for long
- * lattices; narrower tiles for short ones or few tiles).  Every
+ * default depends on the lattice length and the equilibria: for eq_kind 0,
+ * P = 8, K = 40, 4 wavefronts for long lattices; for eq_kind 1 or 2 (kernels
+ * that select the equilibria per lattice and need more registers at P = 8)
+ * P = 4, K = 24, 4 wavefronts; narrower tiles for short lattices or few
+ * tiles.  lbm_set_params re-derives the default unless lbm_set_tuning or
+ * lbm_autotune chose the shape.  Every
  * kernel and tile shape rounds each node-update identically: results are
  * bitwise independent of the tuning. */
 LBM_API int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);
@@ -183,8 +187,8 @@ LBM_API int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_
  * quarter of the tile) plus the one-step kernel, keeps the fastest, and
  * restores f.  ws: lbm_workspace_bytes(h, LBM_WS_TUNE) bytes.  cache_path
  * (may be NULL) names a JSON file mapping "<gfx arch>/<kind>/<size class>/
- * <kernel generation>" to the chosen shape; a hit skips the timing, a miss
- * adds the entry.  The
+ * <equilibrium class>/<kernel generation>" to the chosen shape; a hit skips
+ * the timing, a miss adds the entry.  The
  * chosen shape becomes the handle's tuning and is returned in *out (may be
  * NULL). */
 LBM_API int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,

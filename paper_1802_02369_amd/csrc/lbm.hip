@@ -400,7 +400,7 @@ __device__ __forceinline__ void tile_run(const Consts& c,
 }
 
 template <int P, int WG, int EQ>
-__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : 1) void k_step_tile(
+__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : (EQ == 0 ? 2 : 1)) void k_step_tile(
     Consts c, const double* __restrict__ fin, double* __restrict__ fout,
     int64_t n, int K, int64_t ntiles) {
   const int64_t tile = blockIdx.x;
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(64 * WG, P == 2 ? 4 : 1) void k_step_tile(
 // EVERY: store the state after every step, step s into
 // fout + (s-1)*state_stride.
 template <int P, int WG, int EQ, bool EVERY>
-__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : 1) void k_batch_tile(
+__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : (EQ == 0 && !EVERY ? 2 : 1)) void k_batch_tile(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const lbm::TileRef* __restrict__ tiles, const double* __restrict__ fin,
     double* __restrict__ fout, int64_t S, int H, int K, int64_t ntiles,

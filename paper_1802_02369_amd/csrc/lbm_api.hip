@@ -51,17 +51,27 @@ std::vector<lbm_tuning> tuning_candidates() {
   return v;
 }
 
-lbm_tuning default_tuning(int64_t len, int64_t total) {
-  // tile shapes from the widest down, with the K that measured best for each
-  static const lbm_tuning shapes[] = {
+lbm_tuning default_tuning(int64_t len, int64_t total, int eq) {
+  // tile shapes from the widest down, with the K that measured best for
+  // each.  The kernels that select the equilibria per lattice (eq != 0)
+  // need over 256 VGPRs at P = 8, i.e. one wavefront per SIMD, and run
+  // best at P = 4.
+  static const lbm_tuning sec8[] = {
       {LBM_KERNEL_BLOCKED, 8, 40, 4}, {LBM_KERNEL_BLOCKED, 4, 16, 4},
       {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 8, 2},
       {LBM_KERNEL_BLOCKED, 2, 8, 1}};
-  for (const lbm_tuning& t : shapes) {
+  static const lbm_tuning any[] = {
+      {LBM_KERNEL_BLOCKED, 4, 24, 4}, {LBM_KERNEL_BLOCKED, 4, 16, 4},
+      {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 8, 2},
+      {LBM_KERNEL_BLOCKED, 2, 8, 1}};
+  const lbm_tuning* shapes = eq == 0 ? sec8 : any;
+  const int count = 5;
+  for (int i = 0; i < count; ++i) {
+    const lbm_tuning& t = shapes[i];
     const int64_t width = tile_width(t), out = width - 4 * t.steps_per_launch;
     if (4 * width <= len && total >= 1024 * out) return t;
   }
-  return shapes[sizeof shapes / sizeof shapes[0] - 1];
+  return shapes[count - 1];
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -110,7 +120,8 @@ int lbm_init(lbm_handle** h, int64_t n, const lbm_params* p, void* stream) {
   x->p = *p;
   x->c = c;
   x->stream = (hipStream_t)stream;
-  x->tune = default_tuning(n, n);
+  x->tune = default_tuning(n, n, p->eq_kind == 0 ? 0 : -1);
+  x->tune_default = true;
   *h = x;
   return LBM_OK;
 }
@@ -135,6 +146,7 @@ int lbm_set_params(lbm_handle* h, const lbm_params* p) {
   if (rc) return rc;
   h->p = *p;
   h->c = c;
+  if (h->tune_default) h->tune = default_tuning(h->n, h->n, p->eq_kind == 0 ? 0 : -1);
   lbm_batch_destroy(h->one);  // rebuilt with the new constants when needed
   h->one = nullptr;
   return LBM_OK;
@@ -154,6 +166,7 @@ int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
   int rc = check_tuning(t);
   if (rc) return rc;
   h->tune = *t;
+  h->tune_default = false;
   if (h->tune.kernel == LBM_KERNEL_AUTO) h->tune.kernel = LBM_KERNEL_BLOCKED;
   return LBM_OK;
 }

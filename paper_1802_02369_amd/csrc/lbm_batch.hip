@@ -357,7 +357,7 @@ int apply_groups(lbm_batch* b, const std::vector<lbm_tuning>& gshape,
 
 // Generation of the tile kernels, the last component of every tuning-cache
 // key: entries measured on kernels of another generation are not reused.
-constexpr const char* kKernelGeneration = "/k3";
+constexpr const char* kKernelGeneration = "/k4";
 
 // Times `run(t)` for each candidate on the state f, restoring f from
 // `backup` before each run and at the end; returns the fastest, and every
@@ -427,13 +427,14 @@ int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
     return set_err(LBM_EINVAL, "f and ws overlap");
   const std::string key =
       gpu_arch_name() + "/single/n" + std::to_string(log2_class((double)h->n)) +
-      kKernelGeneration;
+      (h->p.eq_kind == 0 ? "/eq8" : "/eqsel") + kKernelGeneration;
   lbm_tuning best{};
   if (!tune_cache_get(cache_path, key, &best)) {
     std::vector<lbm_tuning> cands = tuning_candidates();
     cands.push_back(lbm_tuning{LBM_KERNEL_PLAIN, 0, 1, 1});
     double* backup = static_cast<double*>(ws) + 6 * h->n + diag_ws_doubles();
     const size_t step_ws = lbm_workspace_bytes(h, LBM_WS_STEP);
+    const lbm_tuning prev = h->tune;
     int rc = autotune_impl(
         h->stream, f, backup, sbytes, probe_steps, cands,
         [&](const lbm_tuning& t) { h->tune = t; return LBM_OK; },
@@ -441,10 +442,14 @@ int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
           return lbm_step(h, f, ws, step_ws, k);
         },
         &best);
-    if (rc) return rc;
+    if (rc) {
+      h->tune = prev;  // a failed search leaves the tuning as it was
+      return rc;
+    }
     tune_cache_put(cache_path, key, best);
   }
   h->tune = best;
+  h->tune_default = false;
   if (out) *out = best;
   return LBM_OK;
 }
@@ -479,7 +484,7 @@ int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
     }
   }
   x->stream = (hipStream_t)stream;
-  x->tune = default_tuning(x->n_total / n_inst, x->n_total);
+  x->tune = default_tuning(x->n_total / n_inst, x->n_total, x->eq_class());
   *b = x;
   return LBM_OK;
 }
@@ -739,7 +744,9 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   const double mean_len = (double)b->n_total / (double)b->n_inst;
   const std::string key = gpu_arch_name() + "/batch/N" +
                           std::to_string(log2_class((double)b->n_total)) + "/L" +
-                          std::to_string(log2_class(mean_len)) + kKernelGeneration;
+                          std::to_string(log2_class(mean_len)) +
+                          (b->eq_class() == 0 ? "/eq8" : "/eqsel") +
+                          kKernelGeneration;
   lbm_tuning best = b->tune;
   std::vector<lbm_tuning> gshape;
   std::vector<double> gcost;
@@ -747,6 +754,16 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     const std::vector<lbm_tuning> cands = tuning_candidates();
     double* backup = at<double>(ws, layout(b, tune_tiles(b), true).backup);
     const size_t sbytes = sizeof(double) * 6 * (size_t)b->n_total;
+    // a failed search leaves the tuning and the groups as they were
+    const lbm_tuning prev = b->tune;
+    const std::vector<lbm_tuning> prev_gt = b->group_tune;
+    const std::vector<int32_t> prev_go = b->group_of;
+    auto fail = [&](int code) {
+      b->tune = prev;
+      b->group_tune = prev_gt;
+      b->group_of = prev_go;
+      return code;
+    };
     b->group_tune.clear();
     b->group_of.clear();
     std::vector<float> times;
@@ -760,7 +777,7 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
           return lbm_batch_run(b, f, ws, ws_bytes, k, 0);
         },
         &best, &times);
-    if (rc) return rc;
+    if (rc) return fail(rc);
     // Shape groups: the measured time per computed node-update of each shape
     // models a grouping; the best set of two or three among the eight
     // fastest shapes is timed and kept if it beats the best single shape.
@@ -818,7 +835,7 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
             return lbm_batch_run(b, f, ws, ws_bytes, k, 0);
           },
           &unused, &gt);
-      if (rc) return rc;
+      if (rc) return fail(rc);
       if (gt[0] < times[ib]) {
         gshape = sh;
         gcost = co;

@@ -75,7 +75,9 @@ StepSplit split_steps(int64_t nsteps, int K);
 // Tile shape used until lbm_set_tuning / lbm_autotune: the widest tile at
 // most a quarter of the (mean) lattice length len that still leaves >= 1024
 // tiles in total (four workgroups per compute unit), else the narrowest.
-lbm_tuning default_tuning(int64_t len, int64_t total);
+// Default tile shape for lattices of (mean) length len, total nodes total,
+// equilibrium class eq (0: every lattice has eq_kind 0, else -1).
+lbm_tuning default_tuning(int64_t len, int64_t total, int eq);
 
 // Tile shapes the autotuner tries (P, K, waves per tile).
 std::vector<lbm_tuning> tuning_candidates();
@@ -131,6 +133,7 @@ struct lbm_handle {
   lbm::Consts c;
   hipStream_t stream;
   lbm_tuning tune;
+  bool tune_default = true;  // tune is the default for n and the equilibria
   int32_t adj_kernel = LBM_KERNEL_PLAIN;  // reverse-sweep kernel
   lbm_batch* one = nullptr;  // batch of this one lattice, for the adjoint
 };

@@ -188,3 +188,55 @@ def test_blocked_adjoint_shape_check_host(shape, ok):
         assert rc == lbm.LBM_ENOTSUP
         assert b"halo" in L.lbm_last_error()
     L.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("kw,shape", [
+    (dict(), (8, 40, 4)),
+    (dict(eq_kind=1), (4, 24, 4)),
+    (dict(eq_kind=2, source_on=0), (4, 24, 4))])
+def test_default_tuning_follows_equilibria(kw, shape):
+    """Lattices whose kernels select the equilibria per lattice (eq_kind 1,
+    2) default to P = 4: at P = 8 those kernels need more than 256 VGPRs."""
+    rc, h = _init(1 << 24, **kw)
+    assert rc == lbm.LBM_OK
+    t = lbm.CTuning()
+    assert lbm.lib().lbm_get_tuning(h, ctypes.byref(t)) == lbm.LBM_OK
+    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == shape
+    lbm.lib().lbm_destroy(h)
+
+
+def test_set_params_rederives_only_the_default_tuning():
+    L = lbm.lib()
+    rc, h = _init(1 << 24)
+    assert rc == lbm.LBM_OK
+    t = lbm.CTuning()
+    p1 = lbm.Params(s_psi=1.0, eq_kind=1).c()
+    assert L.lbm_set_params(h, ctypes.byref(p1)) == lbm.LBM_OK
+    L.lbm_get_tuning(h, ctypes.byref(t))
+    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (4, 24, 4)
+    p0 = lbm.Params(s_psi=1.0).c()
+    assert L.lbm_set_params(h, ctypes.byref(p0)) == lbm.LBM_OK
+    L.lbm_get_tuning(h, ctypes.byref(t))
+    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (8, 40, 4)
+    mine = lbm.CTuning(lbm.KERNEL_BLOCKED, 2, 8, 2)
+    assert L.lbm_set_tuning(h, ctypes.byref(mine)) == lbm.LBM_OK
+    assert L.lbm_set_params(h, ctypes.byref(p1)) == lbm.LBM_OK
+    L.lbm_get_tuning(h, ctypes.byref(t))
+    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (2, 8, 2)
+    L.lbm_destroy(h)
+
+
+def test_batch_default_tuning_follows_equilibria():
+    """One lattice with linear equilibria puts the whole batch on the
+    per-lattice equilibrium kernels, hence the P = 4 defaults."""
+    n_inst, Ln = 4096, 4615
+    offs = (ctypes.c_int64 * (n_inst + 1))(*[i * Ln for i in range(n_inst + 1)])
+    p = lbm.Params(s_psi=1.0).c()
+    q = lbm.Params(s_psi=1.0, eq_kind=1).c()
+    ps = (type(p) * n_inst)(*([q] + [p] * (n_inst - 1)))
+    b = ctypes.c_void_p()
+    assert lbm.lib().lbm_batch_init(ctypes.byref(b), n_inst, offs, ps, None) == lbm.LBM_OK
+    t = lbm.CTuning()
+    assert lbm.lib().lbm_batch_get_tuning(b, ctypes.byref(t)) == lbm.LBM_OK
+    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (4, 24, 4)
+    lbm.lib().lbm_batch_destroy(b)
