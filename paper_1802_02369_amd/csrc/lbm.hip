@@ -3,7 +3,8 @@
 //
 // Forward kernels:
 //   k_step_plain   one time step per launch, one node per thread; the
-//                  neighbours' u and T for the source term go through LDS.
+//                  neighbours' u and T for the source term and the streamed
+//                  populations go through LDS, so every store is aligned.
 //   k_step_tile    K time steps per launch.  Each 64-lane wavefront holds
 //                  64*P consecutive nodes (P per lane, contiguous) in VGPRs
 //                  for all K steps; neighbour values move between lanes with
@@ -191,56 +192,99 @@ __global__ __launch_bounds__(256) void k_moments(Consts c,
   m[5 * n + j] = c.meps * (sg - 2.0 * g0);
 }
 
-// One time step, one node per thread, push streaming.  Block b owns nodes
-// [b*B, b*B + B); threads 0 and 1 also compute u, T of the two halo nodes.
-template <int EQ>
-__global__ __launch_bounds__(kPlainBlock) void k_step_plain(
+// One time step, one node per thread.  Block b stores nodes
+// [b*B, b*B + B) (B = kPlainBlock), each thread its own node with aligned
+// stores: the streamed values f+(j) = f+*(j-1) and f-(j) = f-*(j+1) come
+// through LDS.  A fifth wavefront handles the four halo nodes: b*B - 1 and
+// b*B + B are collided too (their f+* and f-* stream into the block), and
+// b*B - 2, b*B + B + 1 give u, T for those two nodes' sources.  LDS slot s
+// holds node b*B - 2 + s.  NT: non-temporal loads and stores, for states far
+// larger than the caches (measured on a 6-array copy: 6.1 against 5.6 TB/s;
+// with stores shifted by one node, as push streaming writes them, 5.5).
+template <int EQ, bool NT>
+__global__ __launch_bounds__(kPlainBlock + 64) void k_step_plain(
     Consts c, const double* __restrict__ fin, double* __restrict__ fout,
     int64_t n) {
-  __shared__ double su[kPlainBlock + 2], sT[kPlainBlock + 2];
+  constexpr int NS = kPlainBlock + 4;
+  __shared__ double su[NS], sT[NS], sfp[NS], sgp[NS], sfm[NS], sgm[NS];
   const int tid = threadIdx.x;
   const int64_t b0 = (int64_t)blockIdx.x * kPlainBlock;
   const int64_t rem = n - b0;
   const int nloc = rem < kPlainBlock ? (int)rem : kPlainBlock;
-  const int64_t j = b0 + tid;
-  const bool act = tid < nloc;
-  double f0 = 0, fp = 0, fm = 0, g0 = 0, gp = 0, gm = 0, u, T, rw = 0, w = 0;
-  if (act) {
-    f0 = fin[j];
-    fp = fin[n + j];
-    fm = fin[2 * n + j];
-    g0 = fin[3 * n + j];
-    gp = fin[4 * n + j];
-    gm = fin[5 * n + j];
-    lbm::collide_local<EQ>(c, f0, fp, fm, g0, gp, gm, u, T, rw, w);
-    su[tid + 1] = u;
-    sT[tid + 1] = T;
+  // this thread's node and LDS slot; -1: no node
+  int slot = -1;
+  int64_t j = 0;
+  if (tid < kPlainBlock) {
+    if (tid < nloc) {
+      slot = tid + 2;
+      j = b0 + tid;
+    }
+  } else if (tid < kPlainBlock + 4) {
+    const int h = tid - kPlainBlock;  // b0-2, b0-1, b0+nloc, b0+nloc+1
+    slot = h < 2 ? h : nloc + h;
+    j = lbm::wrap_mod(b0 - 2 + slot, n);
   }
-  if (tid < 2) {
-    const int64_t h = tid == 0 ? (b0 == 0 ? n - 1 : b0 - 1)
-                               : (b0 + nloc == n ? 0 : b0 + nloc);
-    double hu, hT;
-    lbm::node_uT(c, fin[h], fin[n + h], fin[2 * n + h], fin[3 * n + h],
-                 fin[4 * n + h], fin[5 * n + h], hu, hT);
-    const int slot = tid == 0 ? 0 : nloc + 1;
-    su[slot] = hu;
-    sT[slot] = hT;
+  const bool own = tid < nloc;
+  const bool collide = slot >= 1 && slot <= nloc + 2;
+  double f0 = 0, fp = 0, fm = 0, g0 = 0, gp = 0, gm = 0, u = 0, T = 0, rw = 0,
+         w = 0;
+  if (slot >= 0) {
+    if (NT) {
+      f0 = __builtin_nontemporal_load(&fin[j]);
+      fp = __builtin_nontemporal_load(&fin[n + j]);
+      fm = __builtin_nontemporal_load(&fin[2 * n + j]);
+      g0 = __builtin_nontemporal_load(&fin[3 * n + j]);
+      gp = __builtin_nontemporal_load(&fin[4 * n + j]);
+      gm = __builtin_nontemporal_load(&fin[5 * n + j]);
+    } else {
+      f0 = fin[j];
+      fp = fin[n + j];
+      fm = fin[2 * n + j];
+      g0 = fin[3 * n + j];
+      gp = fin[4 * n + j];
+      gm = fin[5 * n + j];
+    }
+    if (collide)
+      lbm::collide_local<EQ>(c, f0, fp, fm, g0, gp, gm, u, T, rw, w);
+    else
+      lbm::node_uT(c, f0, fp, fm, g0, gp, gm, u, T);
+    su[slot] = u;
+    sT[slot] = T;
   }
   __syncthreads();
-  if (!act) return;
-  const double add = lbm::source_g(c, rw, w, su[tid], su[tid + 2], sT[tid],
-                                   sT[tid + 2]);
-  g0 += add;
-  gp += add;
-  gm += add;
-  const int64_t jr = j + 1 == n ? 0 : j + 1;
-  const int64_t jl = j == 0 ? n - 1 : j - 1;
-  fout[j] = f0;
-  fout[n + jr] = fp;
-  fout[2 * n + jl] = fm;
-  fout[3 * n + j] = g0;
-  fout[4 * n + jr] = gp;
-  fout[5 * n + jl] = gm;
+  if (collide) {
+    const double add = lbm::source_g(c, rw, w, su[slot - 1], su[slot + 1],
+                                     sT[slot - 1], sT[slot + 1]);
+    g0 += add;
+    gp += add;
+    gm += add;
+    sfp[slot] = fp;
+    sgp[slot] = gp;
+    sfm[slot] = fm;
+    sgm[slot] = gm;
+  }
+  __syncthreads();
+  if (!own) return;
+  // (viii) streaming, pulled from the neighbours' post-collision values
+  fp = sfp[slot - 1];
+  gp = sgp[slot - 1];
+  fm = sfm[slot + 1];
+  gm = sgm[slot + 1];
+  if (NT) {
+    __builtin_nontemporal_store(f0, &fout[j]);
+    __builtin_nontemporal_store(fp, &fout[n + j]);
+    __builtin_nontemporal_store(fm, &fout[2 * n + j]);
+    __builtin_nontemporal_store(g0, &fout[3 * n + j]);
+    __builtin_nontemporal_store(gp, &fout[4 * n + j]);
+    __builtin_nontemporal_store(gm, &fout[5 * n + j]);
+  } else {
+    fout[j] = f0;
+    fout[n + j] = fp;
+    fout[2 * n + j] = fm;
+    fout[3 * n + j] = g0;
+    fout[4 * n + j] = gp;
+    fout[5 * n + j] = gm;
+  }
 }
 
 // K time steps of one register-resident tile per workgroup (see the file
@@ -581,11 +625,18 @@ int launch_equilibrium(const Consts& c, const double* rho, const double* J,
 
 int launch_step_plain(const Consts& c, const double* fin, double* fout,
                       int64_t n, hipStream_t s) {
-  const dim3 grid((unsigned)cdiv(n, kPlainBlock)), block(kPlainBlock);
-  if (c.eq_kind == 0)
-    hipLaunchKernelGGL(k_step_plain<0>, grid, block, 0, s, c, fin, fout, n);
+  const dim3 grid((unsigned)cdiv(n, kPlainBlock)), block(kPlainBlock + 64);
+  // non-temporal accesses once the two states (96 B per node) outgrow the
+  // 256 MB of on-die cache
+  const bool nt = 96 * n > (int64_t(256) << 20);
+  if (c.eq_kind == 0 && nt)
+    hipLaunchKernelGGL((k_step_plain<0, true>), grid, block, 0, s, c, fin, fout, n);
+  else if (c.eq_kind == 0)
+    hipLaunchKernelGGL((k_step_plain<0, false>), grid, block, 0, s, c, fin, fout, n);
+  else if (nt)
+    hipLaunchKernelGGL((k_step_plain<-1, true>), grid, block, 0, s, c, fin, fout, n);
   else
-    hipLaunchKernelGGL(k_step_plain<-1>, grid, block, 0, s, c, fin, fout, n);
+    hipLaunchKernelGGL((k_step_plain<-1, false>), grid, block, 0, s, c, fin, fout, n);
   return hip_check(hipGetLastError(), "k_step_plain");
 }
 
