@@ -170,6 +170,35 @@ def test_results_independent_of_tuning(pname):
     assert max_err(ref, oracle.run(f0, 45, po)) < TOL
 
 
+def test_plain_kernel_large_state_bitwise():
+    """States above 256 MB take the one-step kernel's non-temporal form
+    (n = 3000017: 403 MB for the two states, a ragged last block).  Five
+    steps of it equal five steps of a tile kernel bitwise, and a sample of
+    nodes matches the oracle run on its own dependency window."""
+    rng = np.random.default_rng(23)
+    po = oracle_params("paper")
+    n = 3000017
+    f0 = random_state(rng, n, po, amp=0.1, u=0.05, ds=0.1)
+    say(f"plain kernel, large state n={n}")
+    outs = []
+    for tuning in ({"kernel": lbm().KERNEL_PLAIN},
+                   {"nodes_per_lane": 8, "steps_per_launch": 5,
+                    "waves_per_group": 4}):
+        lat = lbm().Lattice(n, gpu_params(po))
+        lat.set_tuning(**tuning)
+        (f,) = to_dev(f0)
+        lat.step(f, 5)
+        outs.append(f.cpu().numpy())
+    assert np.isfinite(outs[0]).all()
+    assert np.array_equal(outs[0], outs[1])
+    # window of radius 2*5 around sampled nodes (block edges and the wrap)
+    for j in (0, 1, 255, 256, 257, 511, 1234567, n - 258, n - 2, n - 1):
+        idx = (np.arange(j - 10, j + 11)) % n
+        want = oracle.run(f0[:, idx], 5, po)
+        # periodic window: only the centre is exact
+        assert max_err(outs[0][:, idx][:, 10:11], want[:, 10:11]) < TOL, j
+
+
 @pytest.mark.parametrize("tuning", list(TUNINGS))
 @pytest.mark.parametrize("n,steps", [(37, 9), (512, 17), (3001, 40), (700, 2)])
 def test_multi_step(tuning, n, steps):
