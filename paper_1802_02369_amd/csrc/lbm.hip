@@ -379,7 +379,7 @@ __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P]) {
 template <int P, int WG>
 __device__ __forceinline__ void mirror_refresh(double (&f)[6][P],
                                                double (*edge)[2][6 * P],
-                                               int lane, int wave) {
+                                               int lane, int wave, int nw) {
   if (lane == 1 || lane == 62) {
     double* d = edge[wave][lane == 62];
 #pragma unroll
@@ -388,7 +388,7 @@ __device__ __forceinline__ void mirror_refresh(double (&f)[6][P],
       for (int k = 0; k < P; ++k) d[q * P + k] = f[q][k];
   }
   __syncthreads();
-  const bool left = lane == 0 && wave > 0, right = lane == 63 && wave < WG - 1;
+  const bool left = lane == 0 && wave > 0, right = lane == 63 && wave < nw - 1;
   if (left || right) {
     const double* e = left ? edge[wave - 1][1] : edge[wave + 1][0];
 #pragma unroll
@@ -398,10 +398,26 @@ __device__ __forceinline__ void mirror_refresh(double (&f)[6][P],
   }
 }
 
+// Active wavefronts of a tile that starts at lattice index `start` (halo H)
+// in a lattice of n nodes: the fewest of the WG whose span P(62 nw + 2)
+// still covers the nodes the tile stores plus both halos.  Only a lattice's
+// last tile, or a lattice shorter than one tile, needs fewer than WG.
+template <int P, int WG>
+__device__ __forceinline__ int active_waves(int64_t n, int64_t start, int H) {
+  const int64_t store = n - (start + H);  // nodes from the tile's first output
+  const int64_t need = store + 2 * H - 2 * P;  // span - 2P the tile needs
+  if (need >= (int64_t)62 * P * WG) return WG;
+  const int nw = (int)((need + 62 * P - 1) / (62 * P));
+  return nw < 1 ? 1 : nw;
+}
+
 // Tile t of a lattice of n nodes (array stride S) starting at lattice index
 // `start` = t*OUT - H, OUT = tile_nodes - 2H: load, K <= H/2 steps, store of
-// the interior [H, tile_nodes - H) (one step has radius 2, so K steps need
-// H >= 2K).  With every_step, the interior is stored after each step
+// the interior [H, span - H) (one step has radius 2, so K steps need
+// H >= 2K).  Only the first nw wavefronts work (span P(62 nw + 2)); the
+// others end at once, which a workgroup barrier allows (it waits for the
+// wavefronts that have not ended), and leave their SIMDs to other
+// workgroups.  With every_step, the interior is stored after each step
 // s = 1..K into the state fout + (s-1)*state_stride (the states a reverse
 // sweep needs).
 template <int P, int WG, int EQ>
@@ -413,11 +429,13 @@ __device__ __forceinline__ void tile_run(const Consts& c,
                                          int64_t state_stride = 0) {
   constexpr int WW = 64 * P;       // nodes of one wavefront
   constexpr int WS = 62 * P;       // wavefront stride in the tile
-  constexpr int W = lbm::tile_nodes(P, WG);
   __shared__ double stage[WG * (WW + 64)];
   __shared__ double edge[2][WG][2][6 * P];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = active_waves<P, WG>(n, start, H);
+  if (wave >= nw) return;  // uniform over the wavefront
+  const int W = lbm::tile_nodes(P, nw);
   double* lds = stage + wave * (WW + 64);
   const int64_t wstart = start + wave * WS;
   const bool inside = start >= 0 && start + W <= n;
@@ -427,7 +445,7 @@ __device__ __forceinline__ void tile_run(const Consts& c,
   // the tile's valid indices [H, W - H), in this wavefront's numbering and
   // restricted to its own lanes (the mirror lanes belong to the neighbours)
   const int lo = max(H - wave * WS, wave > 0 ? P : 0);
-  const int hi = min(W - H - wave * WS, wave < WG - 1 ? WW - P : WW);
+  const int hi = min(W - H - wave * WS, wave < nw - 1 ? WW - P : WW);
   int since = 0, buf = 0;
   for (int step = 0; step < K; ++step) {
     tile_step<P, EQ>(c, f);
@@ -435,7 +453,7 @@ __device__ __forceinline__ void tile_run(const Consts& c,
       tile_store<P>(fout + step * state_stride, S, n, wstart, lo, hi, lane,
                     lds, f);
     if (WG > 1 && ++since == P / 2 && step + 1 < K) {
-      mirror_refresh<P, WG>(f, edge[buf], lane, wave);
+      mirror_refresh<P, WG>(f, edge[buf], lane, wave, nw);
       buf ^= 1;
       since = 0;
     }
