@@ -182,10 +182,11 @@ LBM_API int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_
                             double out[8]);
 
 /* Autotuner (synchronising).  Times the blocked kernel on the caller's state
- * f for probe_steps time steps with each candidate shape (P in {2,4,8}, waves
- * per tile in {2,4,8}, K in {8,12,16,24,32,40}, halo recomputation at most a
- * quarter of the tile) plus the one-step kernel, keeps the fastest, and
- * restores f.  ws: lbm_workspace_bytes(h, LBM_WS_TUNE) bytes.  cache_path
+ * f with each candidate shape (P in {2,4,8}, waves per tile in {2,4,8}, K in
+ * {8,12,16,24,32,40}, halo recomputation at most a quarter of the tile) for
+ * probe_steps time steps rounded up to a multiple of 2K (so that every launch
+ * runs the candidate's own K), plus the one-step kernel for probe_steps,
+ * keeps the fastest per step, and restores f.  ws: lbm_workspace_bytes(h, LBM_WS_TUNE) bytes.  cache_path
  * (may be NULL) names a JSON file mapping "<gfx arch>/<kind>/<size class>/
  * <equilibrium class>/<kernel generation>" to the chosen shape; a hit skips
  * the timing, a miss adds the entry.  The
@@ -267,8 +268,10 @@ LBM_API int lbm_batch_set_tuning(lbm_batch* b, const lbm_tuning* t);
 LBM_API int lbm_batch_get_tuning(const lbm_batch* b, lbm_tuning* t);
 
 /* Shape groups of lbm_batch_run.  A tile holds nodes of one lattice, so a
- * lattice of L nodes costs ceil(L / (P (62 W + 2) - 4K)) whole tiles: short
- * lattices waste most of a wide tile, long ones run best on it.  With
+ * lattice of L nodes costs ceil(L / (P (62 W + 2) - 4K)) tiles, the last of
+ * them (or the only one, for a lattice shorter than a tile) running just the
+ * wavefronts its nodes and halos need: short lattices still waste part of a
+ * wide tile, long ones run best on it.  With
  * groups, lattice i runs with shapes[group_of[i]] (host arrays of n_groups
  * and n_inst entries, 1 <= n_groups <= LBM_MAX_GROUPS), each group as its
  * own sequence of launches on its own stream, forked from the batch's

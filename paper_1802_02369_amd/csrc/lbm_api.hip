@@ -54,19 +54,14 @@ std::vector<lbm_tuning> tuning_candidates() {
 lbm_tuning default_tuning(int64_t len, int64_t total, int eq) {
   // tile shapes from the widest down, with the K that measured best for
   // each.  The kernels that select the equilibria per lattice (eq != 0)
-  // need over 256 VGPRs at P = 8, i.e. one wavefront per SIMD, and run
-  // best at P = 4.
-  static const lbm_tuning sec8[] = {
-      {LBM_KERNEL_BLOCKED, 8, 40, 4}, {LBM_KERNEL_BLOCKED, 4, 16, 4},
+  // need over 256 VGPRs at P = 8, i.e. one wavefront per SIMD, so they
+  // start at P = 4.
+  static const lbm_tuning shapes[] = {
+      {LBM_KERNEL_BLOCKED, 8, 40, 4}, {LBM_KERNEL_BLOCKED, 4, 24, 4},
       {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 8, 2},
       {LBM_KERNEL_BLOCKED, 2, 8, 1}};
-  static const lbm_tuning any[] = {
-      {LBM_KERNEL_BLOCKED, 4, 24, 4}, {LBM_KERNEL_BLOCKED, 4, 16, 4},
-      {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 8, 2},
-      {LBM_KERNEL_BLOCKED, 2, 8, 1}};
-  const lbm_tuning* shapes = eq == 0 ? sec8 : any;
   const int count = 5;
-  for (int i = 0; i < count; ++i) {
+  for (int i = eq == 0 ? 0 : 1; i < count; ++i) {
     const lbm_tuning& t = shapes[i];
     const int64_t width = tile_width(t), out = width - 4 * t.steps_per_launch;
     if (4 * width <= len && total >= 1024 * out) return t;

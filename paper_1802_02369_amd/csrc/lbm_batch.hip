@@ -305,9 +305,10 @@ int64_t tune_tiles(const lbm_batch* b) {
   return std::max(mx, std::max(b->run_tiles(), b->count_tiles(b->tune)));
 }
 
-// Modelled time of a grouping: lattice i costs tiles_i(s) * width(s) * c_s
-// on shape s, with c_s a measured time per computed node-update; each
-// lattice takes its cheapest shape (written to *of).  Returns the total.
+// Modelled time of a grouping: lattice i costs work_i(s) * c_s on shape s,
+// work_i(s) its lane-nodes per step and c_s a measured time per computed
+// node-update; each lattice takes its cheapest shape (written to *of).
+// Returns the total.
 double assign_groups(const lbm_batch* b, const std::vector<lbm_tuning>& shapes,
                      const std::vector<double>& cost, std::vector<int32_t>* of) {
   double total = 0;
@@ -315,8 +316,7 @@ double assign_groups(const lbm_batch* b, const std::vector<lbm_tuning>& shapes,
   for (int64_t i = 0; i < b->n_inst; ++i) {
     double best = INFINITY;
     for (size_t g = 0; g < shapes.size(); ++g) {
-      const double c = (double)b->lattice_tiles(i, shapes[g]) *
-                       (double)tile_width(shapes[g]) * cost[g];
+      const double c = (double)b->lattice_work(i, shapes[g]) * cost[g];
       if (c < best) {
         best = c;
         if (of) (*of)[i] = (int32_t)g;
@@ -357,7 +357,7 @@ int apply_groups(lbm_batch* b, const std::vector<lbm_tuning>& gshape,
 
 // Generation of the tile kernels, the last component of every tuning-cache
 // key: entries measured on kernels of another generation are not reused.
-constexpr const char* kKernelGeneration = "/k4";
+constexpr const char* kKernelGeneration = "/k5";
 
 // Times `run(t)` for each candidate on the state f, restoring f from
 // `backup` before each run and at the end; returns the fastest, and every
@@ -380,19 +380,28 @@ int autotune_impl(hipStream_t s, double* f, double* backup, size_t bytes,
   float best_ms = INFINITY;
   for (size_t ci = 0; ci < cands.size(); ++ci) {
     const lbm_tuning& t = cands[ci];
+    // a blocked shape runs whole pairs of its own K (a shorter run would be
+    // split into shorter launches), at least `probe` steps; times are
+    // compared per step, scaled to `probe` steps
+    int64_t steps = probe;
+    if (t.kernel == LBM_KERNEL_BLOCKED) {
+      const int64_t k2 = 2 * (int64_t)t.steps_per_launch;
+      steps = (std::max(probe, k2) + k2 - 1) / k2 * k2;
+    }
     if ((rc = prepare(t))) break;
-    if ((rc = run(t, probe))) break;  // warm-up
+    if ((rc = run(t, steps))) break;  // warm-up
     if ((rc = hip_check(hipMemcpyAsync(f, backup, bytes,
                                        hipMemcpyDeviceToDevice, s),
                         "hipMemcpyAsync")))
       break;
     (void)hipEventRecord(e0, s);
-    if ((rc = run(t, probe))) break;
+    if ((rc = run(t, steps))) break;
     (void)hipEventRecord(e1, s);
     if ((rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize")))
       break;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    ms = ms * (float)probe / (float)steps;
     if (times) (*times)[ci] = ms;
     if (ms < best_ms) {
       best_ms = ms;
@@ -786,8 +795,7 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     size_t ib = 0;
     for (size_t c = 0; c < cands.size(); ++c) {
       cost[c] = (double)times[c] * 1e-3 /
-                ((double)b->count_tiles(cands[c]) * (double)tile_width(cands[c]) *
-                 (double)probe_steps);
+                ((double)b->count_work(cands[c]) * (double)probe_steps);
       order[c] = c;
       if (same_tuning(cands[c], best)) ib = c;
     }

@@ -125,6 +125,24 @@ __host__ __device__ constexpr int tile_nodes(int P, int wg) {
 inline int64_t tile_width(const lbm_tuning& t) {
   return tile_nodes(t.nodes_per_lane, t.waves_per_group);
 }
+
+// Lane-nodes a lattice of L nodes computes per step with tuning t: its
+// ceil(L/OUT) tiles, each running the wavefronts it needs (the device's
+// active-wave rule: the fewest whose span covers the tile's stored nodes
+// and both halos of 2K), 64 P per wavefront.
+inline int64_t lattice_lane_nodes(int64_t L, const lbm_tuning& t) {
+  const int64_t P = t.nodes_per_lane, W = t.waves_per_group,
+                H = 2 * (int64_t)t.steps_per_launch;
+  const int64_t out = tile_width(t) - 2 * H;
+  int64_t s = 0;
+  for (int64_t first = 0; first < L; first += out) {
+    const int64_t need = (L - first) + 2 * H - 2 * P;
+    int64_t nw = (need + 62 * P - 1) / (62 * P);
+    nw = nw < 1 ? 1 : (nw > W ? W : nw);
+    s += 64 * P * nw;
+  }
+  return s;
+}
 }  // namespace lbm
 
 struct lbm_handle {
@@ -192,6 +210,18 @@ struct lbm_batch {
   int64_t lattice_tiles(int64_t i, const lbm_tuning& t) const {
     const int64_t out = lbm::tile_width(t) - 4 * (int64_t)t.steps_per_launch;
     return (offsets[i + 1] - offsets[i] + out - 1) / out;
+  }
+
+  // lane-nodes lattice i computes per step with tuning t
+  int64_t lattice_work(int64_t i, const lbm_tuning& t) const {
+    return lbm::lattice_lane_nodes(offsets[i + 1] - offsets[i], t);
+  }
+
+  // lane-nodes of the whole batch per step with tuning t
+  int64_t count_work(const lbm_tuning& t) const {
+    int64_t s = 0;
+    for (int64_t i = 0; i < n_inst; ++i) s += lattice_work(i, t);
+    return s;
   }
 
   // tiles of the table for one tuning: sum of ceil(L_i / OUT)

@@ -105,7 +105,7 @@ def test_init_and_workspace_and_tuning_host():
 @pytest.mark.parametrize("n,shape", [
     (1 << 24, (8, 40, 4)),   # wide tiles: 9119 tiles of 1840 output nodes
     (1 << 21, (8, 40, 4)),
-    (1 << 20, (4, 16, 4)),   # too few P = 8 tiles for 4 workgroups per CU
+    (1 << 20, (4, 24, 4)),   # too few P = 8 tiles for 4 workgroups per CU
     (8192, (2, 8, 1)),       # small lattices: the narrowest tile
     (3, (2, 8, 1))])
 def test_default_tuning_follows_lattice_length(n, shape):
@@ -119,8 +119,8 @@ def test_default_tuning_follows_lattice_length(n, shape):
 
 
 def test_batch_default_tuning_uses_mean_length():
-    """4096 lattices of ~4.6k nodes: P = 8 tiles (2048 wide) would waste a
-    third of each lattice's work, so the default is the 1024-wide P = 4 tile."""
+    """4096 lattices of ~4.6k nodes: P = 8 tiles (2000 wide) would waste a
+    third of each lattice's work, so the default is the 1000-wide P = 4 tile."""
     n_inst, L = 4096, 4615
     offs = (ctypes.c_int64 * (n_inst + 1))(*[i * L for i in range(n_inst + 1)])
     p = lbm.Params(s_psi=1.0).c()
@@ -129,7 +129,7 @@ def test_batch_default_tuning_uses_mean_length():
     assert lbm.lib().lbm_batch_init(ctypes.byref(b), n_inst, offs, ps, None) == lbm.LBM_OK
     t = lbm.CTuning()
     assert lbm.lib().lbm_batch_get_tuning(b, ctypes.byref(t)) == lbm.LBM_OK
-    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (4, 16, 4)
+    assert (t.nodes_per_lane, t.steps_per_launch, t.waves_per_group) == (4, 24, 4)
     lbm.lib().lbm_batch_destroy(b)
 
 
