@@ -237,15 +237,18 @@ LBM_API int lbm_equilibrium_adjoint(lbm_handle* h, const double* rho, const doub
 /* Reverse of lbm_moments: fbar = M^T mbar (device, 6*n each). */
 LBM_API int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
                                 void* ws, size_t ws_bytes);
-/* Kernel of the reverse sweep: LBM_KERNEL_PLAIN (default, AUTO) runs one
- * reverse step per launch, one node per thread (HBM-bound, 144 B per
- * node-step); LBM_KERNEL_BLOCKED keeps dL/df in registers for K reverse steps
- * of a forward-shaped tile (reads only the recomputed states, but needs about
- * 2.5x the arithmetic of a forward step per node; a P = 8 forward shape runs
- * its reverse as P = 4 with twice the wavefronts, at most 8, on tiles of
- * 64 P W nodes; lbm_forward_ckpt rejects with LBM_ENOTSUP a K whose halo
- * leaves those tiles no interior, 4K >= 2048, possible only for P = 8 with 8
- * wavefronts).  Takes effect at the next lbm_forward_ckpt. */
+/* Kernel of the reverse sweep.  LBM_KERNEL_BLOCKED keeps dL/df in registers
+ * for up to K reverse steps of a tile of 64 P W nodes (P = 2 with W the
+ * forward's wavefronts, or P W / 2 for P = 4, 8, at most 8; halo 2K), reading
+ * only the recomputed forward states, the next step's prefetched while the
+ * current one computes (about 2.4x the arithmetic of a forward step per
+ * node-step).  LBM_KERNEL_PLAIN runs one reverse step per launch, one node
+ * per thread (HBM-bound, 144 B per node-step).  LBM_KERNEL_AUTO (the
+ * default) takes the blocked kernel wherever its tiles can hold the halo,
+ * else the one-step kernel.  A halo too wide for P = 2 tiles (4K >= 128 W)
+ * falls back to P = 4 with 8 wavefronts; lbm_forward_ckpt rejects with
+ * LBM_ENOTSUP an explicit LBM_KERNEL_BLOCKED whose halo leaves even those
+ * no interior (4K >= 2048).  Takes effect at the next lbm_forward_ckpt. */
 LBM_API int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
 
 /* ------------------------------------------------- batches of lattices */

@@ -130,13 +130,21 @@ __device__ __forceinline__ void equilibria_adjoint(const Consts& c,
   rb -= q.s * sb * ir;
 }
 
+// Sum of v over the 64 lanes of the wavefront (xor butterfly); lane 0's
+// result has a fixed summation order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const TileRef* __restrict__ tiles, int64_t ntiles,
     const double* __restrict__ f, const double* __restrict__ fbn,
     double* __restrict__ fbo, int64_t S, double* __restrict__ rslots) {
   __shared__ double su[kAdjBlock], sT[kAdjBlock], sA[kAdjBlock], sB[kAdjBlock];
-  __shared__ double red[3][kAdjBlock];
+  __shared__ double wsum[3][kAdjBlock / 64];
   const int64_t b = blockIdx.x;
   if (b >= ntiles) return;  // uniform over the workgroup
   const TileRef tr = tiles[b];
@@ -206,19 +214,22 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
     O[4 * S + j] = c.mz * zb + c.mpsi * psib + c.meps * epsb;
     O[5 * S + j] = c.mz * zb - c.mpsi * psib + c.meps * epsb;
   }
-  red[0][t] = r0;
-  red[1][t] = r1;
-  red[2][t] = r2;
-  __syncthreads();
-  for (int w = kAdjBlock / 2; w > 0; w >>= 1) {
-    if (t < w) {
-      red[0][t] += red[0][t + w];
-      red[1][t] += red[1][t + w];
-      red[2][t] += red[2][t + w];
-    }
-    __syncthreads();
+  // rate partials: a butterfly sum inside each wavefront (lane 0's total,
+  // a fixed order), then the wavefronts' totals in order
+  r0 = wave_sum(r0);
+  r1 = wave_sum(r1);
+  r2 = wave_sum(r2);
+  if ((t & 63) == 0) {
+    wsum[0][t >> 6] = r0;
+    wsum[1][t >> 6] = r1;
+    wsum[2][t >> 6] = r2;
   }
-  if (t < 3) rslots[3 * b + t] += red[t][0];
+  __syncthreads();
+  if (t < 3) {
+    double a = wsum[t][0];
+    for (int w = 1; w < kAdjBlock / 64; ++w) a += wsum[t][w];
+    rslots[3 * b + t] += a;
+  }
 }
 
 // ------------------------------------------------ register-tile adjoint --
@@ -425,7 +436,7 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   const int64_t n = offs[tr.inst + 1] - off;
   const Consts c = cs[tr.inst];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* lds = stage + wave * (WW + 64);
   const int OUT = W - 2 * H;
   const int64_t start = (int64_t)tr.t * OUT - H;
@@ -438,13 +449,23 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
     const int it = wave * WW + lane * P + k;
     own[k] = it >= H && it < W - H && start + it < n;
   }
-  double fb[6][P];
-  tile_load<P>(fbn + off, S, n, wstart, inside, small, lane, lds, fb);
+  // the segment's global indices are the same in every state
+  int64_t gi[P];
+  tile_index<P>(n, wstart, inside, small, lane, gi);
+  double fb[6][P], raw[6][P];
+  tile_fetch<P>(fbn + off, S, gi, raw);
+  tile_transpose<P>(lane, lds, raw, fb);
+  auto state = [&](int i) {
+    return (i == 0 ? ck : seg + (int64_t)(i - 1) * SD) + off;
+  };
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  // the forward state of the next (earlier) step is fetched while this
+  // step computes
+  tile_fetch<P>(state(i_hi - 1), S, gi, raw);
   for (int i = i_hi - 1; i >= i_lo; --i) {
-    const double* st = (i == 0 ? ck : seg + (int64_t)(i - 1) * SD) + off;
     double ft[6][P];
-    tile_load<P>(st, S, n, wstart, inside, small, lane, lds, ft);
+    tile_transpose<P>(lane, lds, raw, ft);
+    if (i > i_lo) tile_fetch<P>(state(i - 1), S, gi, raw);
     adjoint_tile_step<P, WG>(c, ft, fb, bnd, bab, lane, wave, own, r0, r1, r2);
   }
   tile_store<P>(fbo + off, S, n, wstart, H - wave * WW, W - H - wave * WW,
@@ -620,15 +641,20 @@ struct AdjLayout {
 // The recompute runs with the forward tile shape and stores every step.
 lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
 
-// Tile shape of the blocked reverse kernel for a forward tuning: the same P
-// and wavefronts, except that P = 8 (too many registers for the reverse
-// step) runs as P = 4 with twice the wavefronts, at most 8.  Its tiles span
-// 64 P W nodes (no overlap between wavefronts) with the forward halo 2K.
+// Tile shape of the blocked reverse kernel for a forward tuning.  Its tiles
+// span 64 P W nodes (no overlap between wavefronts) with the forward halo 2K.
+// P = 2 keeps two wavefronts per SIMD (the reverse step needs about 220
+// VGPRs at P = 2, over 256 at P = 4), with the wavefronts that give about
+// the forward tile's width (at least the forward's, at most 8); a halo too
+// wide for those tiles (4K >= 128 W) falls back to P = 4 with 8 wavefronts.
 lbm_tuning rev_tuning(const lbm_tuning& t) {
   lbm_tuning r = t;
-  if (t.nodes_per_lane == 8) {
+  r.nodes_per_lane = 2;
+  r.waves_per_group = std::min(
+      8, std::max(t.waves_per_group, t.nodes_per_lane * t.waves_per_group / 2));
+  if (4 * t.steps_per_launch >= 64 * 2 * r.waves_per_group) {
     r.nodes_per_lane = 4;
-    r.waves_per_group = std::min(2 * t.waves_per_group, 8);
+    r.waves_per_group = 8;
   }
   return r;
 }
@@ -861,6 +887,10 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     return set_err(LBM_EINVAL, "f and ws overlap");
   if (((uintptr_t)f | (uintptr_t)ws) & 7)
     return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
+  // AUTO: the blocked reverse kernel (a prefetching K-step tile) wherever
+  // its tiles can hold the forward halo, else the one-step kernel
+  b->adj_plain = b->adj_kernel == LBM_KERNEL_PLAIN ||
+                 (b->adj_kernel == LBM_KERNEL_AUTO && rev_out(b->tune) < 1);
   if (!b->adj_plain && rev_out(b->tune) < 1)
     return set_err(LBM_ENOTSUP,
                    "the blocked adjoint kernel's tiles (P = 4, 8 wavefronts "
@@ -1014,7 +1044,7 @@ int lbm_batch_set_adjoint_kernel(lbm_batch* b, int kernel) {
   if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_PLAIN &&
       kernel != LBM_KERNEL_BLOCKED)
     return set_err(LBM_EINVAL, "unknown adjoint kernel %d", kernel);
-  b->adj_plain = kernel != LBM_KERNEL_BLOCKED;
+  b->adj_kernel = kernel;
   return LBM_OK;
 }
 
@@ -1025,7 +1055,7 @@ int lbm_set_adjoint_kernel(lbm_handle* h, int kernel) {
   if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_PLAIN &&
       kernel != LBM_KERNEL_BLOCKED)
     return set_err(LBM_EINVAL, "unknown adjoint kernel %d", kernel);
-  h->adj_kernel = kernel == LBM_KERNEL_BLOCKED ? LBM_KERNEL_BLOCKED : LBM_KERNEL_PLAIN;
+  h->adj_kernel = kernel;
   return LBM_OK;
 }
 
@@ -1044,7 +1074,7 @@ int lbm_forward_ckpt(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
   if (!b) return LBM_EINVAL;
   if (h->tune.kernel == LBM_KERNEL_BLOCKED && !same_tuning(b->tune, h->tune))
     lbm_batch_set_tuning(b, &h->tune);
-  b->adj_plain = h->adj_kernel != LBM_KERNEL_BLOCKED;
+  b->adj_kernel = h->adj_kernel;
   return lbm_batch_forward_ckpt(b, f, ws, ws_bytes, nsteps, ckpt_every);
 }
 

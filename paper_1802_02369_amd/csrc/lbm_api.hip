@@ -56,11 +56,13 @@ lbm_tuning default_tuning(int64_t len, int64_t total, int eq) {
   // each.  The kernels that select the equilibria per lattice (eq != 0)
   // need over 256 VGPRs at P = 8, i.e. one wavefront per SIMD, so they
   // start at P = 4.
+  // Small lattices are bound by launch latency, so their one-wavefront tile
+  // takes K = 16 (fewer launches) rather than the width's best; at
+  // n = 8192 to 131072 it beats every other shape.
   static const lbm_tuning shapes[] = {
       {LBM_KERNEL_BLOCKED, 8, 40, 4}, {LBM_KERNEL_BLOCKED, 4, 24, 4},
-      {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 8, 2},
-      {LBM_KERNEL_BLOCKED, 2, 8, 1}};
-  const int count = 5;
+      {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 16, 1}};
+  const int count = 4;
   for (int i = eq == 0 ? 0 : 1; i < count; ++i) {
     const lbm_tuning& t = shapes[i];
     const int64_t width = tile_width(t), out = width - 4 * t.steps_per_launch;

@@ -152,7 +152,7 @@ struct lbm_handle {
   hipStream_t stream;
   lbm_tuning tune;
   bool tune_default = true;  // tune is the default for n and the equilibria
-  int32_t adj_kernel = LBM_KERNEL_PLAIN;  // reverse-sweep kernel
+  int32_t adj_kernel = LBM_KERNEL_AUTO;  // reverse-sweep kernel
   lbm_batch* one = nullptr;  // batch of this one lattice, for the adjoint
 };
 
@@ -192,7 +192,10 @@ struct lbm_batch {
   const void* adj_ws = nullptr;
   int64_t adj_nsteps = -1, adj_ckpt = -1;
   lbm_tuning adj_tune{};
-  bool adj_plain = true;      // one reverse step per launch (else K per launch)
+  int32_t adj_kernel = LBM_KERNEL_AUTO;  // requested reverse-sweep kernel
+  // the kernel lbm_batch_forward_ckpt resolved it to: one reverse step per
+  // launch (else K per launch)
+  bool adj_plain = false;
   bool adj_plain_up = false;  // the value the uploaded tables were built for
   // captured graph of the last lbm_batch_adjoint(use_graph = 1)
   hipGraphExec_t adj_exec = nullptr;

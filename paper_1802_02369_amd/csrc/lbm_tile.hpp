@@ -49,6 +49,46 @@ __device__ __forceinline__ void tile_load(const double* __restrict__ fin,
   }
 }
 
+// tile_load in three parts, for a kernel that reloads the same segment of
+// successive states: the global indices of the coalesced order (computed
+// once), the global loads into registers in that order (which may be issued
+// a step ahead), and the pass through LDS into the register order.
+template <int P>
+__device__ __forceinline__ void tile_index(int64_t n, int64_t start,
+                                           bool inside, bool small, int lane,
+                                           int64_t (&gi)[P]) {
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int i = k * 64 + lane;
+    gi[k] = inside ? start + i : wrap_near(start + i, n, small);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void tile_fetch(const double* __restrict__ fin,
+                                           int64_t S, const int64_t (&gi)[P],
+                                           double (&raw)[6][P]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+#pragma unroll
+    for (int k = 0; k < P; ++k) raw[q][k] = fin[(int64_t)q * S + gi[k]];
+}
+
+template <int P>
+__device__ __forceinline__ void tile_transpose(int lane, double* lds,
+                                               const double (&raw)[6][P],
+                                               double (&f)[6][P]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) lds[lds_idx<P>(k * 64 + lane)] = raw[q][k];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < P; ++k) f[q][k] = lds[lds_idx<P>(lane * P + k)];
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Stores the nodes of this wavefront's segment whose tile index lies in
 // [lo, hi) and whose global index is below n.
 template <int P>

@@ -272,7 +272,7 @@ class Lattice:
         return self.get_tuning()
 
     # ------------------------------------------------------ gradients --
-    def set_adjoint_kernel(self, kernel: int = KERNEL_PLAIN):
+    def set_adjoint_kernel(self, kernel: int = KERNEL_AUTO):
         check(lib().lbm_set_adjoint_kernel(self._h, int(kernel)))
 
     def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):
@@ -475,7 +475,7 @@ class Batch:
         return self.get_tuning()
 
     # ------------------------------------------------------ gradients --
-    def set_adjoint_kernel(self, kernel: int = KERNEL_PLAIN):
+    def set_adjoint_kernel(self, kernel: int = KERNEL_AUTO):
         check(lib().lbm_batch_set_adjoint_kernel(self._h, int(kernel)))
 
     def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):

@@ -106,8 +106,9 @@ def test_init_and_workspace_and_tuning_host():
     (1 << 24, (8, 40, 4)),   # wide tiles: 9119 tiles of 1840 output nodes
     (1 << 21, (8, 40, 4)),
     (1 << 20, (4, 24, 4)),   # too few P = 8 tiles for 4 workgroups per CU
-    (8192, (2, 8, 1)),       # small lattices: the narrowest tile
-    (3, (2, 8, 1))])
+    (1 << 19, (2, 16, 4)),
+    (8192, (2, 16, 1)),      # small lattices: the narrowest tile, K = 16
+    (3, (2, 16, 1))])
 def test_default_tuning_follows_lattice_length(n, shape):
     rc, h = _init(n)
     assert rc == lbm.LBM_OK
@@ -170,9 +171,9 @@ def test_batch_groups_validation_host():
 def test_blocked_adjoint_shape_check_host(shape, ok):
     """Workspace sizes exist for every valid forward shape; the checkpointed
     forward with the blocked reverse kernel refuses, before any HIP call, a
-    shape whose halo leaves the reverse tiles (P = 4 with up to 8 wavefronts
-    for P = 8, else the forward P and wavefronts; 64 P W nodes) no interior:
-    4K >= 2048 for P = 8 with 8 wavefronts."""
+    shape whose halo leaves the reverse tiles (64 P W nodes: P = 2, else
+    P = 4 with 8 wavefronts for halos of 4K >= 128 W) no interior:
+    4K >= 2048, possible only for P = 8 with 8 wavefronts."""
     rc, h = _init(5000)
     assert rc == lbm.LBM_OK
     L = lbm.lib()

@@ -128,6 +128,9 @@ def test_blocked_adjoint_rejects_halo_beyond_reverse_tile():
     assert e.value.code == lbm().LBM_ENOTSUP
     lat.set_adjoint_kernel(lbm().KERNEL_PLAIN)
     lat.forward_ckpt(f, 10, 5, aws)
+    # the default (AUTO) falls back to the one-step kernel for this shape
+    lat.set_adjoint_kernel(lbm().KERNEL_AUTO)
+    lat.forward_ckpt(f, 10, 5, aws)
 
 
 def test_graph_adjoint_matches_direct():
