@@ -207,8 +207,13 @@ LBM_API int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
 
 /* Bytes of the workspace that lbm_forward_ckpt / lbm_adjoint / lbm_loss /
  * lbm_equilibrium_adjoint / lbm_moments_adjoint use for this nsteps and
- * ckpt_every (0 on bad arguments): ceil(nsteps/ckpt_every) checkpoints,
- * min(ckpt_every, nsteps) - 1 recomputed states, one more state and tables. */
+ * ckpt_every with the current tile shape and reverse kernel (0 on bad
+ * arguments): ceil(nsteps/ckpt_every) checkpoints, min(ckpt_every, nsteps)
+ * - 1 recomputed states, one more state and tables.  The recomputed states
+ * are held twice when the reverse sweep is pipelined: with the blocked
+ * reverse kernel on problems whose reverse launches hold fewer than 2048
+ * wavefronts (small lattices), the recompute of one checkpoint segment runs
+ * on a second stream beside the reverse steps of the next. */
 LBM_API size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
                                            int64_t ckpt_every);
 /* Advances f (device, 6*n) by nsteps steps in place like lbm_step, keeping

@@ -632,7 +632,7 @@ __global__ void k_rbar_reduce(const int64_t* __restrict__ first,
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct AdjLayout {
-  int64_t n_fwd, n_rec, n_rev, n_adj, n_ck, n_seg;
+  int64_t n_fwd, n_rec, n_rev, n_adj, n_ck, n_seg, seg_bufs;
   size_t consts, offs, fwd_tiles, rec_tiles, rev_tiles, adj_tiles, adj_first,
       rev_first,
       rslots, scratch, pp, ckpt, seg, total;
@@ -682,7 +682,33 @@ int64_t adj_tile_count(const lbm_batch* b) {
   return s;
 }
 
-AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C) {
+// Whether the reverse sweep of the batch's current settings runs one step
+// per launch (LBM_KERNEL_AUTO: the blocked kernel wherever its tiles can hold
+// the forward halo).
+bool resolve_adj_plain(const lbm_batch* b) {
+  return b->adj_kernel == LBM_KERNEL_PLAIN ||
+         (b->adj_kernel == LBM_KERNEL_AUTO && rev_out(b->tune) < 1);
+}
+
+// Whether the reverse sweep overlaps the recompute of one checkpoint segment
+// with the reverse steps of the next (two buffers of segment states): with
+// the blocked reverse kernel, when its launches leave most of the chip idle
+// (fewer wavefronts than the 2048 the 256 CUs hold at two per SIMD), as on
+// small lattices bound by launch latency.  A launch that fills the chip
+// gains nothing from a second stream (measured on the 1024-lattice
+// gradient) and the second buffer would cost (C-1) more states.
+bool adj_pipelined(const lbm_batch* b, bool plain) {
+  if (plain) return false;
+  const int64_t out = rev_out(b->tune);
+  if (out < 1) return false;
+  return tiles_of(b, out) * rev_tuning(b->tune).waves_per_group < 2048;
+}
+
+// Workspace layout; `pipelined`: two buffers of segment states (see
+// adj_pipelined).  The segment states come last: the other offsets do not
+// depend on it.
+AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C,
+                     bool pipelined) {
   AdjLayout L{};
   L.n_fwd = b->count_tiles(b->tune);
   L.n_rec = b->count_tiles(rec_tuning(b->tune));
@@ -718,7 +744,8 @@ AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C) {
   L.ckpt = o;
   o = align256(o + state * (size_t)L.n_ck);
   L.seg = o;
-  o = align256(o + state * (size_t)L.n_seg);
+  L.seg_bufs = pipelined ? 2 : 1;
+  o = align256(o + state * (size_t)L.n_seg * L.seg_bufs);
   L.total = o;
   return L;
 }
@@ -770,7 +797,7 @@ int check_adj(const lbm_batch* b, const void* ws, size_t ws_bytes,
     return set_err(LBM_EINVAL,
                    "no checkpoints for this workspace, nsteps and ckpt_every: "
                    "call lbm_batch_forward_ckpt first");
-  if (ws_bytes < adj_layout(b, nsteps, C).total)
+  if (ws_bytes < adj_layout(b, nsteps, C, adj_pipelined(b, b->adj_plain)).total)
     return set_err(LBM_EWORKSPACE, "adjoint workspace too small");
   return LBM_OK;
 }
@@ -778,7 +805,7 @@ int check_adj(const lbm_batch* b, const void* ws, size_t ws_bytes,
 // The reverse sweep: recompute each checkpoint segment, then adjoint steps.
 int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
                     double* fbar, double* rbar, hipStream_t s) {
-  const AdjLayout L = adj_layout(b, nsteps, C);
+  const AdjLayout L = adj_layout(b, nsteps, C, adj_pipelined(b, b->adj_plain));
   const Consts* cs = at<Consts>(ws, L.consts);
   const int64_t* offs = at<int64_t>(ws, L.offs);
   const size_t SD = 6 * (size_t)b->n_total;
@@ -792,48 +819,96 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
   double* oth = at<double>(ws, L.pp);
   const int Prec = b->tune.nodes_per_lane, Wrec = b->tune.waves_per_group;
   const int Krec = b->tune.steps_per_launch;
-  for (int64_t k = L.n_ck - 1; k >= 0; --k) {
-    const int64_t t0 = k * C;
-    const int64_t len = std::min(C, nsteps - t0);
-    double* ck = at<double>(ws, L.ckpt) + SD * k;
-    auto state = [&](int64_t i) {
-      return i == 0 ? ck : at<double>(ws, L.seg) + SD * (i - 1);
-    };
-    // states t0+1 .. t0+len-1, up to Krec of them per launch
+  auto seg_len = [&](int64_t k) { return std::min(C, nsteps - k * C); };
+  auto ckpt = [&](int64_t k) { return at<double>(ws, L.ckpt) + SD * k; };
+  // segment k's states t0+1 .. t0+len-1 live in segment buffer k % seg_bufs
+  auto segbuf = [&](int64_t k) {
+    return at<double>(ws, L.seg) + SD * (size_t)L.n_seg * (size_t)(k % L.seg_bufs);
+  };
+  auto state = [&](int64_t k, int64_t i) {
+    return i == 0 ? ckpt(k) : segbuf(k) + SD * (i - 1);
+  };
+  // recompute of segment k on stream st: up to Krec states per launch
+  auto recompute = [&](int64_t k, hipStream_t st) -> int {
+    const int64_t len = seg_len(k);
     for (int64_t i0 = 0; i0 + 1 < len; i0 += Krec) {
-      const int k = (int)std::min<int64_t>(Krec, len - 1 - i0);
-      rc = launch_batch_tile(cs, offs, at<TileRef>(ws, L.rec_tiles), L.n_rec,
-                             state(i0), state(i0 + 1), b->n_total, Prec,
-                             2 * Krec, k, Wrec, b->eq_class(), s,
-                             (int64_t)SD);
-      if (rc) return rc;
+      const int kk = (int)std::min<int64_t>(Krec, len - 1 - i0);
+      const int r = launch_batch_tile(cs, offs, at<TileRef>(ws, L.rec_tiles),
+                                      L.n_rec, state(k, i0), state(k, i0 + 1),
+                                      b->n_total, Prec, 2 * Krec, kk, Wrec,
+                                      b->eq_class(), st, (int64_t)SD);
+      if (r) return r;
     }
-    if (b->adj_plain) {
-      for (int64_t i = len - 1; i >= 0; --i) {
+    return LBM_OK;
+  };
+  const lbm_tuning rt = rev_tuning(b->tune);
+  const int Padj = rt.nodes_per_lane, Wadj = rt.waves_per_group;
+  // the blocked reverse steps of segment k on s, up to Krec per launch
+  auto reverse = [&](int64_t k) -> int {
+    for (int64_t hi = seg_len(k); hi > 0;) {
+      const int64_t lo = std::max<int64_t>(0, hi - Krec);
+      const int r = launch_adjoint_tile(
+          Padj, Wadj, cs, offs, at<TileRef>(ws, L.rev_tiles), L.n_rev, ckpt(k),
+          segbuf(k), (int64_t)SD, (int)lo, (int)hi, cur, oth, b->n_total,
+          2 * Krec, slots, s);
+      if (r) return r;
+      std::swap(cur, oth);
+      hi = lo;
+    }
+    return LBM_OK;
+  };
+  if (b->adj_plain) {
+    for (int64_t k = L.n_ck - 1; k >= 0; --k) {
+      if ((rc = recompute(k, s))) return rc;
+      for (int64_t i = seg_len(k) - 1; i >= 0; --i) {
         hipLaunchKernelGGL(k_adjoint_step, dim3((unsigned)L.n_adj),
                            dim3(kAdjBlock), 0, s, cs, offs,
                            at<TileRef>(ws, L.adj_tiles), L.n_adj,
-                           (const double*)state(i), (const double*)cur, oth,
+                           (const double*)state(k, i), (const double*)cur, oth,
                            b->n_total, slots);
         if ((rc = hip_check(hipGetLastError(), "k_adjoint_step"))) return rc;
         std::swap(cur, oth);
       }
-    } else {
-      // up to Krec reverse steps per launch on the reverse tile shape
-      const lbm_tuning rt = rev_tuning(b->tune);
-      const int Padj = rt.nodes_per_lane, Wadj = rt.waves_per_group;
-      for (int64_t hi = len; hi > 0;) {
-        const int64_t lo = std::max<int64_t>(0, hi - Krec);
-        rc = launch_adjoint_tile(Padj, Wadj, cs, offs,
-                                 at<TileRef>(ws, L.rev_tiles), L.n_rev, ck,
-                                 at<double>(ws, L.seg), (int64_t)SD, (int)lo,
-                                 (int)hi, cur, oth, b->n_total, 2 * Krec,
-                                 slots, s);
-        if (rc) return rc;
-        std::swap(cur, oth);
-        hi = lo;
-      }
     }
+  } else if (L.seg_bufs == 1) {
+    for (int64_t k = L.n_ck - 1; k >= 0; --k) {
+      if ((rc = recompute(k, s))) return rc;
+      if ((rc = reverse(k))) return rc;
+    }
+  } else {
+    // Pipelined: segment k-1 is recomputed on the side stream while the
+    // reverse steps of segment k run on s.  Segment buffer k % 2 is written
+    // by recompute(k) only after reverse(k+2), its previous reader, ended.
+    // Events: 0/1 recompute of an even/odd segment done, 2/3 reverse of an
+    // even/odd segment done, 4 fork, 5 join.
+    const hipStream_t s2 = b->rstream;
+    hipEvent_t* ev = b->revents;
+    rc = hip_check(hipEventRecord(ev[4], s), "hipEventRecord");
+    if (!rc) rc = hip_check(hipStreamWaitEvent(s2, ev[4], 0), "hipStreamWaitEvent");
+    if (rc) return rc;
+    const int64_t last = L.n_ck - 1;
+    rc = recompute(last, s2);
+    if (!rc) rc = hip_check(hipEventRecord(ev[last % 2], s2), "hipEventRecord");
+    for (int64_t k = last; k >= 0 && !rc; --k) {
+      if (k >= 1) {
+        // buffer (k-1) % 2 was last read by reverse(k+1)
+        if (k + 1 <= last)
+          rc = hip_check(hipStreamWaitEvent(s2, ev[2 + (k + 1) % 2], 0),
+                         "hipStreamWaitEvent");
+        if (!rc) rc = recompute(k - 1, s2);
+        if (!rc)
+          rc = hip_check(hipEventRecord(ev[(k - 1) % 2], s2), "hipEventRecord");
+        if (rc) break;
+      }
+      rc = hip_check(hipStreamWaitEvent(s, ev[k % 2], 0), "hipStreamWaitEvent");
+      if (!rc) rc = reverse(k);
+      if (!rc) rc = hip_check(hipEventRecord(ev[2 + k % 2], s), "hipEventRecord");
+    }
+    // join the side stream even after a failure, so that a capture ends
+    const int r1 = hip_check(hipEventRecord(ev[5], s2), "hipEventRecord");
+    const int r2 = hip_check(hipStreamWaitEvent(s, ev[5], 0), "hipStreamWaitEvent");
+    if (!rc) rc = r1 ? r1 : r2;
+    if (rc) return rc;
   }
   if (cur != fbar &&
       (rc = hip_check(hipMemcpyAsync(fbar, cur, sizeof(double) * SD,
@@ -855,6 +930,17 @@ lbm_batch* single_batch(lbm_handle* h) {
   return h->one;
 }
 
+// The handle's batch with the handle's current tile shape and reverse
+// kernel: the workspace size and the checkpointed forward must see the same.
+lbm_batch* synced_batch(lbm_handle* h) {
+  lbm_batch* b = single_batch(h);
+  if (!b) return nullptr;
+  if (h->tune.kernel == LBM_KERNEL_BLOCKED && !same_tuning(b->tune, h->tune))
+    lbm_batch_set_tuning(b, &h->tune);
+  b->adj_kernel = h->adj_kernel;
+  return b;
+}
+
 }  // namespace
 
 namespace lbm {
@@ -871,7 +957,8 @@ extern "C" {
 size_t lbm_batch_adjoint_workspace_bytes(const lbm_batch* b, int64_t nsteps,
                                          int64_t ckpt_every) {
   if (!b || nsteps < 0 || ckpt_every < 1) return 0;
-  return adj_layout(b, nsteps, ckpt_every).total;
+  return adj_layout(b, nsteps, ckpt_every,
+                    adj_pipelined(b, resolve_adj_plain(b))).total;
 }
 
 int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
@@ -879,7 +966,10 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   if (!b || !f || !ws) return set_err(LBM_EINVAL, "NULL argument");
   if (nsteps < 0 || ckpt_every < 1)
     return set_err(LBM_EINVAL, "need nsteps >= 0 and ckpt_every >= 1");
-  const AdjLayout L = adj_layout(b, nsteps, ckpt_every);
+  // AUTO: the blocked reverse kernel (a prefetching K-step tile) wherever
+  // its tiles can hold the forward halo, else the one-step kernel
+  b->adj_plain = resolve_adj_plain(b);
+  const AdjLayout L = adj_layout(b, nsteps, ckpt_every, adj_pipelined(b, b->adj_plain));
   if (ws_bytes < L.total)
     return set_err(LBM_EWORKSPACE, "adjoint workspace of %zu bytes, need %zu",
                    ws_bytes, L.total);
@@ -887,16 +977,29 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     return set_err(LBM_EINVAL, "f and ws overlap");
   if (((uintptr_t)f | (uintptr_t)ws) & 7)
     return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
-  // AUTO: the blocked reverse kernel (a prefetching K-step tile) wherever
-  // its tiles can hold the forward halo, else the one-step kernel
-  b->adj_plain = b->adj_kernel == LBM_KERNEL_PLAIN ||
-                 (b->adj_kernel == LBM_KERNEL_AUTO && rev_out(b->tune) < 1);
   if (!b->adj_plain && rev_out(b->tune) < 1)
     return set_err(LBM_ENOTSUP,
                    "the blocked adjoint kernel's tiles (P = 4, 8 wavefronts "
                    "for this shape) cannot hold a halo of 2K = %d nodes; use "
                    "the one-step adjoint kernel or a smaller K",
                    2 * b->tune.steps_per_launch);
+  if (L.seg_bufs == 2) {
+    // the pipelined reverse sweep's side stream (default priority) and
+    // events, created once, outside any capture
+    if (!b->rstream) {
+      const int r = hip_check(
+          hipStreamCreateWithFlags(&b->rstream, hipStreamNonBlocking),
+          "hipStreamCreate");
+      if (r) return r;
+    }
+    for (hipEvent_t& ev : b->revents)
+      if (!ev) {
+        const int r = hip_check(
+            hipEventCreateWithFlags(&ev, hipEventDisableTiming),
+            "hipEventCreate");
+        if (r) return r;
+      }
+  }
   const hipStream_t s = b->stream;
   int rc = LBM_OK;
   const bool same = b->adj_ws == ws && b->adj_nsteps == nsteps &&
@@ -1001,9 +1104,9 @@ int lbm_batch_adjoint(lbm_batch* b, void* ws, size_t ws_bytes, int64_t nsteps,
 int lbm_batch_loss(lbm_batch* b, const double* f, const double* target,
                    void* ws, size_t ws_bytes, double* loss, double* fbar) {
   if (!b || !f || !ws || !loss || !fbar) return set_err(LBM_EINVAL, "NULL argument");
-  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt).total)
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain)).total)
     return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
   hipLaunchKernelGGL(k_loss, dim3((unsigned)b->n_inst), dim3(256), 0, b->stream,
                      at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs), f, target,
                      loss, fbar, b->n_total);
@@ -1017,9 +1120,9 @@ int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
                                   size_t ws_bytes) {
   if (!b || !rho || !J || !zeta || !fbar || !rho_bar || !J_bar || !zeta_bar || !ws)
     return set_err(LBM_EINVAL, "NULL argument");
-  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt).total)
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain)).total)
     return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
   hipLaunchKernelGGL(k_equilibrium_adjoint, dim3((unsigned)b->n_inst), dim3(256),
                      0, b->stream, at<Consts>(ws, L.consts),
                      at<int64_t>(ws, L.offs), rho, J, zeta, fbar, rho_bar,
@@ -1030,9 +1133,9 @@ int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
 int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
                               void* ws, size_t ws_bytes) {
   if (!b || !mbar || !fbar || !ws) return set_err(LBM_EINVAL, "NULL argument");
-  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt).total)
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain)).total)
     return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
   hipLaunchKernelGGL(k_moments_adjoint, dim3((unsigned)b->n_inst), dim3(256), 0,
                      b->stream, at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs),
                      mbar, fbar, b->n_total);
@@ -1062,7 +1165,7 @@ int lbm_set_adjoint_kernel(lbm_handle* h, int kernel) {
 size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
                                    int64_t ckpt_every) {
   if (!h) return 0;
-  lbm_batch* b = single_batch(h);
+  lbm_batch* b = synced_batch(h);
   // rbar staging for the host copy lives in the scratch region
   return b ? lbm_batch_adjoint_workspace_bytes(b, nsteps, ckpt_every) : 0;
 }
@@ -1070,11 +1173,8 @@ size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
 int lbm_forward_ckpt(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
                      int64_t nsteps, int64_t ckpt_every) {
   if (!h) return set_err(LBM_EINVAL, "handle is NULL");
-  lbm_batch* b = single_batch(h);
+  lbm_batch* b = synced_batch(h);
   if (!b) return LBM_EINVAL;
-  if (h->tune.kernel == LBM_KERNEL_BLOCKED && !same_tuning(b->tune, h->tune))
-    lbm_batch_set_tuning(b, &h->tune);
-  b->adj_kernel = h->adj_kernel;
   return lbm_batch_forward_ckpt(b, f, ws, ws_bytes, nsteps, ckpt_every);
 }
 
@@ -1083,7 +1183,7 @@ int lbm_adjoint(lbm_handle* h, void* ws, size_t ws_bytes, int64_t nsteps,
   if (!h || !rbar) return set_err(LBM_EINVAL, "NULL argument");
   lbm_batch* b = single_batch(h);
   if (!b) return LBM_EINVAL;
-  const AdjLayout L = adj_layout(b, nsteps, ckpt_every);
+  const AdjLayout L = adj_layout(b, nsteps, ckpt_every, adj_pipelined(b, b->adj_plain));
   double* dev = at<double>(ws, L.scratch);
   int rc = lbm_batch_adjoint(b, ws, ws_bytes, nsteps, ckpt_every, fbar, dev,
                              use_graph);
@@ -1101,7 +1201,7 @@ int lbm_loss(lbm_handle* h, const double* f, const double* target, void* ws,
   lbm_batch* b = single_batch(h);
   if (!b) return LBM_EINVAL;
   if (b->adj_ws != ws) return set_err(LBM_EINVAL, "call lbm_forward_ckpt first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt);
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
   double* dev = at<double>(ws, L.scratch);
   int rc = lbm_batch_loss(b, f, target, ws, ws_bytes, dev, fbar);
   if (!rc)

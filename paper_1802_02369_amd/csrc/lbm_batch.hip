@@ -503,6 +503,9 @@ void lbm_batch_destroy(lbm_batch* b) {
   drop_graph(b);
   lbm::drop_adjoint_graph(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->rstream) (void)hipStreamDestroy(b->rstream);
+  for (hipEvent_t ev : b->revents)
+    if (ev) (void)hipEventDestroy(ev);
   for (hipStream_t st : b->gstreams) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : b->gevents) (void)hipEventDestroy(ev);
   delete b;

@@ -163,6 +163,10 @@ struct lbm_batch {
   std::vector<lbm::Consts> consts;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used only for graph capture
+  // side stream and events of the pipelined reverse sweep (the recompute
+  // of one checkpoint segment overlaps the reverse steps of the next)
+  hipStream_t rstream = nullptr;
+  hipEvent_t revents[6] = {};
   lbm_tuning tune{};
   // what lbm_batch_prepare uploaded
   const void* prep_ws = nullptr;

@@ -246,6 +246,40 @@ def test_batched_adjoint(adj):
         np.testing.assert_allclose(rbar[i], sb, rtol=1e-9, atol=1e-12 * np.abs(sb).max())
 
 
+def test_blocked_reverse_large_batch_matches_one_step_reverse():
+    """A batch large enough for the blocked reverse sweep to run on one
+    stream (its launches fill the chip: 256 lattices, 2.06M nodes): the
+    gradients equal those of the one-step reverse kernel, which the oracle
+    tests pin on smaller batches."""
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_batched_adjoint(n_inst=256, steps=40, ckpt=7,
+                                           lmin=7000, lmax=9000)
+    bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
+    ps = [gpu_params(oracle_params("paper", s_e=float(s))) for s in bt.s_e]
+    fl = bt.fields
+    out = {}
+    for adj in ("blocked", "plain"):
+        b = lbm().Batch(bt.offsets, ps)
+        b.set_tuning(4, 16, 4)
+        b.set_adjoint_kernel(lbm().KERNEL_BLOCKED if adj == "blocked"
+                             else lbm().KERNEL_PLAIN)
+        r_, J_, z_ = T(fl.rho), T(fl.J), T(fl.zeta)
+        f = b.equilibrium(r_, J_, z_)
+        aws = b.adjoint_workspace(steps, ckpt, dev())
+        b.forward_ckpt(f, steps, ckpt, aws)
+        _, fbar = b.loss(f, None, aws)
+        rbar = b.adjoint(aws, steps, ckpt, fbar).cpu().numpy()
+        g = b.equilibrium_adjoint(r_, J_, z_, fbar, aws)
+        out[adj] = (rbar, [x.cpu().numpy() for x in g])
+        del aws, b
+    rb, gb = out["blocked"]
+    rp, gp = out["plain"]
+    assert np.isfinite(rb).all()
+    np.testing.assert_allclose(rb, rp, rtol=1e-10, atol=1e-13 * np.abs(rp).max())
+    for x, y in zip(gb, gp):
+        assert np.abs(x - y).max() <= 1e-11 * np.abs(y).max()
+
+
 def test_autograd_function():
     from paper_1802_02369_amd.autograd import LBMFunction
     po = oracle_params("paper", s_e=1.7)
