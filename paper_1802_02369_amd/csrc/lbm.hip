@@ -107,6 +107,7 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->gamma = g;
   c->cp = cp;
   c->se_2 = p->s_e / 2.0;
+  c->ise2 = 1.0 / (p->s_e * p->s_e);
   c->se_3 = p->s_e / 3.0;
   c->se_6 = p->s_e / 6.0;
   c->sp_2 = p->s_psi / 2.0;

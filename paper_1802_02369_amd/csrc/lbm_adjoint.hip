@@ -16,11 +16,13 @@
 //   (v)^T, (iv)^T, (ii)^T  the local chain through the relaxation, the
 //             equilibria and the equation of state back to f(t, j);
 //   rates     d/ds_e (relaxation of e and c), d/ds_psi, d/ds_eps.
-// The step has radius 2 in both f(t) and fbar(t+1).  One thread per node,
-// 256-node tiles whose 252 interior nodes are stored; u, T and the gathered
-// terms go through LDS.  Rate partials are summed per tile into a per-tile
-// slot (same workgroup, launches in order: deterministic) and reduced per
-// lattice in tile order at the end.
+// The step has radius 2 in both f(t) and fbar(t+1).  Two kernels run it:
+// k_adjoint_step, one step per launch, one thread per node, 256-node tiles
+// whose 252 interior nodes are stored, u, T and the gathered terms through
+// LDS; and k_adjoint_tile, up to K steps per launch on a register tile (the
+// default where its tiles hold the halo; see below).  Rate partials are
+// summed per tile into a per-tile slot (same workgroup, launches in order:
+// deterministic) and reduced per lattice in tile order at the end.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,7 +52,7 @@ __device__ __forceinline__ int64_t wrap_in(int64_t x, int64_t n, bool small) {
 // Forward quantities of one node that the reverse sweep reuses.
 struct NodeFwd {
   double rho, J, zeta, e, psi, eps;
-  double u, s, X, T, w;
+  double u, s, X, T, w, ir;  // ir = 1/rho
   double e_eq, psi_eq, eps_eq;
 };
 
@@ -64,7 +66,7 @@ __device__ __forceinline__ void node_forward(const Consts& c, double f0,
   q.zeta = c.mz * (g0 + sg);
   q.psi = c.mpsi * (gp - gm);
   q.eps = c.meps * (sg - 2.0 * g0);
-  lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T);
+  lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T, q.ir);
   q.w = lbm::recip(q.T);
   if (c.eq_kind == 0) {
     const double p = q.rho * c.r * q.T;
@@ -92,7 +94,7 @@ __device__ __forceinline__ void equilibria_adjoint(const Consts& c,
                                                    double& rb, double& Jb,
                                                    double& zb) {
   double sb = 0.0, Xb = 0.0;
-  const double ir = lbm::recip(q.rho);
+  const double ir = q.ir;
   if (c.eq_kind == 0) {
     // eps_eq = eps_c rho X + e_eq s
     rb += c.eps_c * q.X * xb;
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
                 Zb * c.src_c * q.rho * q.w * q.w *
                     (du * du + 2.0 * c.cPr * dT * dT * q.w);
     double rb = Zb * c.src_c * q.w * Q;
-    if (c.src_c != 0.0) r0 -= Zb * 0.25 * q.rho * q.w * Q / (c.s_e * c.s_e);
+    if (c.src_c != 0.0) r0 -= Zb * 0.25 * q.rho * q.w * Q * c.ise2;
     // (vi)^T: adjoints of (rho, J, zeta, e*, psi*, eps*) from fbar*
     rb += c.fa * (a0 + ap + am);
     double Jb = c.fc * (ap - am);
@@ -234,9 +236,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
 
 // ------------------------------------------------ register-tile adjoint --
 //
-// K reverse steps of a tile of 64*P*WG nodes per launch (the forward tile
-// shape, halo H = 2K on each side).  fbar stays in registers; each step reads
-// the forward state f(t) of the tile (coalesced, through LDS) and does:
+// K reverse steps of a tile of 64*P*WG nodes per launch (halo H = 2K on
+// each side, K the forward's steps per launch; its own tile table).  fbar
+// stays in registers; each step takes the forward state f(t) of the tile
+// (coalesced loads issued during the previous step, through LDS) and does:
 //   A  u, T (and rho, s, X) of every node from f(t);
 //   -  streamed adjoint: fbar*_+(k) = fbar_+(k+1), fbar*_-(k) = fbar_-(k-1),
 //      with u, T of the outside neighbours (DPP, LDS between wavefronts);
@@ -264,13 +267,13 @@ __device__ __forceinline__ void adjoint_tile_step(
     Boundary* bnd, double (*bab)[4], int lane, int wave, const bool (&own)[P],
     double& r0, double& r1, double& r2) {
   // A: forward quantities of each node
-  double rho[P], u[P], s[P], X[P], T[P];
+  double rho[P], u[P], s[P], X[P], T[P], ir[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) {
     rho[k] = lbm::density(c, ft[0][k], ft[1][k], ft[2][k]);
     const double J = c.mJ * (ft[1][k] - ft[2][k]);
     const double zeta = c.mz * (ft[3][k] + (ft[4][k] + ft[5][k]));
-    lbm::thermo(c, rho[k], J, zeta, u[k], s[k], X[k], T[k]);
+    lbm::thermo(c, rho[k], J, zeta, u[k], s[k], X[k], T[k], ir[k]);
   }
   if (WG > 1) {
     if (lane == 0) {
@@ -363,6 +366,7 @@ __device__ __forceinline__ void adjoint_tile_step(
     q.s = s[k];
     q.X = X[k];
     q.T = T[k];
+    q.ir = ir[k];
     q.w = lbm::recip(T[k]);
     if (c.eq_kind == 0) {
       const double p = q.rho * c.r * q.T;
@@ -388,7 +392,7 @@ __device__ __forceinline__ void adjoint_tile_step(
                               (du * du + 2.0 * c.cPr * dT * dT * q.w);
     double rb = Zb * c.src_c * q.w * Q;
     double dr0 = 0.0;
-    if (c.src_c != 0.0) dr0 -= Zb * 0.25 * q.rho * q.w * Q / (c.s_e * c.s_e);
+    if (c.src_c != 0.0) dr0 -= Zb * 0.25 * q.rho * q.w * Q * c.ise2;
     rb += c.fa * (a0 + ap + am);
     double Jb = c.fc * (ap - am);
     const double esb = c.fb * (0.5 * (ap + am) - a0);
@@ -434,7 +438,7 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   const TileRef tr = tiles[b];
   const int64_t off = offs[tr.inst];
   const int64_t n = offs[tr.inst + 1] - off;
-  const Consts c = cs[tr.inst];
+  const Consts& c = cs[tr.inst];  // loaded where used
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* lds = stage + wave * (WW + 64);
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(256) void k_equilibrium_adjoint(
     q.rho = rho[j];
     q.J = J[j];
     q.zeta = zeta[j];
-    lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T);
+    lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T, q.ir);
     if (c.eq_kind == 0) {
       const double p = q.rho * c.r * q.T;
       q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
@@ -787,6 +791,26 @@ int fwd_steps(lbm_batch* b, const Consts* cs, const int64_t* offs,
                                     hipMemcpyDeviceToDevice, s),
                      "hipMemcpyAsync");
   return LBM_OK;
+}
+
+// The checkpointed forward on stream s: checkpoint k is the state at step
+// k * C, then the segment's launches.
+int enqueue_forward_ckpt(lbm_batch* b, void* ws, double* f, int64_t nsteps,
+                         int64_t C, const AdjLayout& L, hipStream_t s) {
+  const size_t SB = sizeof(double) * 6 * b->n_total;
+  const Consts* cs = at<Consts>(ws, L.consts);
+  const int64_t* offs = at<int64_t>(ws, L.offs);
+  int rc = LBM_OK;
+  for (int64_t k = 0; k < L.n_ck && !rc; ++k) {
+    rc = hip_check(hipMemcpyAsync(at<char>(ws, L.ckpt) + SB * k, f, SB,
+                                  hipMemcpyDeviceToDevice, s),
+                   "hipMemcpyAsync");
+    const int64_t len = std::min(C, nsteps - k * C);
+    if (!rc && len > 0)
+      rc = fwd_steps(b, cs, offs, at<TileRef>(ws, L.fwd_tiles), L.n_fwd, f,
+                     at<double>(ws, L.pp), len, s);
+  }
+  return rc;
 }
 
 int check_adj(const lbm_batch* b, const void* ws, size_t ws_bytes,
@@ -1046,19 +1070,7 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     b->adj_tune = b->tune;
     b->adj_plain_up = b->adj_plain;
   }
-  const size_t SB = sizeof(double) * 6 * b->n_total;
-  const Consts* cs = at<Consts>(ws, L.consts);
-  const int64_t* offs = at<int64_t>(ws, L.offs);
-  for (int64_t k = 0; k < L.n_ck && !rc; ++k) {
-    rc = hip_check(hipMemcpyAsync(at<char>(ws, L.ckpt) + SB * k, f, SB,
-                                  hipMemcpyDeviceToDevice, s),
-                   "hipMemcpyAsync");
-    const int64_t len = std::min(ckpt_every, nsteps - k * ckpt_every);
-    if (!rc && len > 0)
-      rc = fwd_steps(b, cs, offs, at<TileRef>(ws, L.fwd_tiles), L.n_fwd, f,
-                     at<double>(ws, L.pp), len, s);
-  }
-  return rc;
+  return enqueue_forward_ckpt(b, ws, f, nsteps, ckpt_every, L, s);
 }
 
 int lbm_batch_adjoint(lbm_batch* b, void* ws, size_t ws_bytes, int64_t nsteps,

@@ -40,6 +40,7 @@ struct Consts {
   double xs0l;         // xs0 - (gamma - 1) ln rho0
   // The time step in scaled moments (see collide_local):
   double se_2, se_3, se_6;  // s_e / 2, s_e / 3, s_e / 6
+  double ise2;              // 1 / s_e^2 (d sigma_e / d s_e = -1 / s_e^2)
   double sp_2, sx_3, sx_6;  // s_psi / 2, s_eps / 3, s_eps / 6
   double hP;                // c0^2 / (gamma lambda^2) = p0 / (rho0 lambda^2)
   double two_g;             // 2 / gamma
@@ -184,16 +185,24 @@ __device__ __forceinline__ double exp_fin(double x) {
 // these functions (one-step, any tile shape, batched), and those kernels
 // produce bitwise identical states.
 
-// Thermodynamics from conserved moments: u, s and X = ln(T/T0), T.
+// Thermodynamics from conserved moments: u, s and X = ln(T/T0), T; ir
+// returns 1/rho.
+__device__ __forceinline__ void thermo(const Consts& c, double rho, double J,
+                                       double zeta, double& u, double& s,
+                                       double& X, double& T, double& ir) {
+#pragma clang fp contract(off)
+  const double lr = ln_inv(rho, ir);
+  u = J * ir;
+  s = zeta * ir;
+  X = fma(c.gm1, lr, fma(c.gcp, s, c.xs0l));
+  T = c.T0 * exp_fin(X);
+}
+
 __device__ __forceinline__ void thermo(const Consts& c, double rho, double J,
                                        double zeta, double& u, double& s,
                                        double& X, double& T) {
-#pragma clang fp contract(off)
-  const double ir = recip(rho);
-  u = J * ir;
-  s = zeta * ir;
-  X = fma(c.gm1, ln_pos(rho), fma(c.gcp, s, c.xs0l));
-  T = c.T0 * exp_fin(X);
+  double ir;
+  thermo(c, rho, J, zeta, u, s, X, T, ir);
 }
 
 // Isentropic pressure p0 (rho/rho0)^gamma = rho r T0 (rho/rho0)^(gamma-1)

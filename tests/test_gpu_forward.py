@@ -152,7 +152,9 @@ def test_results_independent_of_tuning(pname):
     f0 = random_state(rng, n, po, amp=0.1, u=0.05, ds=0.1)
     say(f"tuning invariance {pname} n={n}")
     outs = {}
-    for name in list(TUNINGS) + ["p8k20w8", "p8k60w2"]:
+    # K not a multiple of the mirror-lane refresh period P/2 as well
+    for name in list(TUNINGS) + ["p8k20w8", "p8k60w2", "p8k9w4", "p8k13w8",
+                                 "p4k6w8"]:
         lat = lbm().Lattice(n, gpu_params(po))
         if name in TUNINGS:
             lat.set_tuning(**{"nodes_per_lane": 2, "steps_per_launch": 8,
