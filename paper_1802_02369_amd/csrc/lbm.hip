@@ -462,8 +462,19 @@ __device__ __forceinline__ void tile_run(const Consts& c,
   if (!every_step) tile_store<P>(fout, S, n, wstart, lo, hi, lane, lds, f);
 }
 
+// Wavefronts per SIMD the tile kernels are compiled for (the register
+// budget: 512 / n VGPRs each).  Section-8 kernels at P = 8 hold 168 VGPRs
+// for three (the few values that spill are touched only around the step
+// loop, which measured 297 -> 312 GLUPS at N = 2^24 against two); with 8
+// wavefronts per workgroup a CU gains no third one, so those stay at two.
+// The kernels that select the equilibria per lattice, or store every step,
+// need more registers at P >= 4 and take one.
+constexpr int tile_waves_per_simd(int P, int WG, bool sec8_plain) {
+  return P == 2 ? 4 : (!sec8_plain ? 1 : (P == 8 && WG <= 4 ? 3 : 2));
+}
+
 template <int P, int WG, int EQ>
-__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : (EQ == 0 ? 2 : 1)) void k_step_tile(
+__global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0)) void k_step_tile(
     Consts c, const double* __restrict__ fin, double* __restrict__ fout,
     int64_t n, int K, int64_t ntiles) {
   const int64_t tile = blockIdx.x;
@@ -479,7 +490,7 @@ __global__ __launch_bounds__(64 * WG, P == 2 ? 4 : (EQ == 0 ? 2 : 1)) void k_ste
 // EVERY: store the state after every step, step s into
 // fout + (s-1)*state_stride.
 template <int P, int WG, int EQ, bool EVERY>
-__global__ __launch_bounds__(64 * WG, P == 2 ? 4 : (EQ == 0 && !EVERY ? 2 : 1)) void k_batch_tile(
+__global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0 && !EVERY)) void k_batch_tile(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const lbm::TileRef* __restrict__ tiles, const double* __restrict__ fin,
     double* __restrict__ fout, int64_t S, int H, int K, int64_t ntiles,

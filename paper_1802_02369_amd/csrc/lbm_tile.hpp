@@ -96,17 +96,20 @@ __device__ __forceinline__ void tile_store(double* __restrict__ fout,
                                            int64_t S, int64_t n, int64_t start,
                                            int lo, int hi, int lane, double* lds,
                                            const double (&f)[6][P]) {
+  // one 64-bit lane base and a wavefront-uniform upper bound keep few
+  // values live around a kernel's step loop
+  const int64_t g0 = start + lane;
+  const int64_t lim = n - start;  // i < lim  <=>  start + i < n
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
 #pragma unroll
     for (int k = 0; k < P; ++k) lds[lds_idx<P>(lane * P + k)] = f[q][k];
     __builtin_amdgcn_wave_barrier();
-    double* dst = fout + (int64_t)q * S;
+    double* dst = fout + (int64_t)q * S + g0;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       const int i = k * 64 + lane;
-      const int64_t g = start + i;
-      if (i >= lo && i < hi && g < n) dst[g] = lds[lds_idx<P>(i)];
+      if (i >= lo && i < hi && i < lim) dst[k * 64] = lds[lds_idx<P>(i)];
     }
     __builtin_amdgcn_wave_barrier();
   }
