@@ -276,8 +276,9 @@ def test_large_config_sampled():
     rng = np.random.default_rng(42)
     samples = list(rng.integers(0, n, 48)) + [0, 1, 2, n - 3, n - 2, n - 1]
     out = lat.get_tuning()
-    tile = (64 * out["nodes_per_lane"] * out["waves_per_group"]
-            - 4 * out["steps_per_launch"])
+    # tile edges: a tile spans P (62 W + 2) nodes and stores all but 4K
+    tile = (out["nodes_per_lane"] * (62 * out["waves_per_group"] + 2)
+            - 4 * min(k, out["steps_per_launch"]))
     samples += [tile - 1, tile, 5 * tile + 1, (n // tile) * tile]
     fl3 = (fl.rho, fl.J, fl.zeta)
     got = f[:, torch.tensor(samples, device=f.device)].cpu().numpy()
@@ -289,6 +290,51 @@ def test_large_config_sampled():
     d1 = lat.diagnostics(f)
     assert d1[0] == pytest.approx(d0[0], rel=1e-13)
     assert abs(d1[1] - d0[1]) < 1e-13 * n
+
+
+def test_lattice_beyond_32_bit_indices():
+    """n = 2^29 + 12345 nodes (26 GB per state): array offsets q*n + j pass
+    2^31 elements.  Five steps of the default tile kernel and of the one-step
+    kernel, from a state built on the GPU; the oracle runs each sampled
+    node's 21-node dependency window of that same initial state (copied
+    back), and the window centre must match.  The two kernels must also
+    agree bitwise."""
+    po = oracle_params("paper")
+    n = (1 << 29) + 12345
+    k = 5
+    say(f"lattice beyond 32-bit indices n={n}")
+    lat = lbm().Lattice(n, gpu_params(po))
+    j = torch.arange(n, dtype=torch.float64, device=dev())
+    ph = 2 * np.pi / n
+    rho = po.rho0 * (1 + 0.1 * torch.sin(7 * ph * j) + 0.02 * torch.cos(1013 * ph * j))
+    J = rho * po.lam * 0.05 * torch.sin(3 * ph * j + 0.4)
+    zeta = rho * (po.s0 + 0.1 * po.cp * torch.cos(11 * ph * j))
+    del j
+    f0 = lat.equilibrium(rho, J, zeta)
+    del rho, J, zeta
+    out = lat.get_tuning()
+    tile = out["nodes_per_lane"] * (62 * out["waves_per_group"] + 2) - 4 * k
+    samples = [0, 1, 2, tile - 1, tile, tile + 1, 1 << 28, (1 << 29) - 1,
+               1 << 29, n // 2 + 7, (n // tile) * tile, n - 3, n - 2, n - 1]
+    wins = [(np.arange(s - 2 * k, s + 2 * k + 1)) % n for s in samples]
+    f0w = [f0[:, torch.from_numpy(w).to(dev())].cpu().numpy() for w in wins]
+    want = np.stack([oracle.run(w, k, po)[:, 2 * k] for w in f0w], axis=1)
+    scale = np.abs(want).max()
+    outs = []
+    for tuning in (None, {"kernel": lbm().KERNEL_PLAIN}):
+        if tuning:
+            lat.set_tuning(**tuning)
+        f = f0.clone()
+        lat.step(f, k)
+        got = f[:, torch.tensor(samples, device=dev())].cpu().numpy()
+        err = (np.abs(got - want).max(axis=1)
+               / np.maximum(np.abs(want).max(axis=1), 1e-3 * scale))
+        assert err.max() < TOL, (tuning, err)
+        outs.append(f)
+        del f
+    assert torch.equal(outs[0], outs[1])
+    del outs, f0
+    torch.cuda.empty_cache()
 
 
 def test_diagnostics_and_nonfinite_detection():
