@@ -207,13 +207,15 @@ LBM_API int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
 
 /* Bytes of the workspace that lbm_forward_ckpt / lbm_adjoint / lbm_loss /
  * lbm_equilibrium_adjoint / lbm_moments_adjoint use for this nsteps and
- * ckpt_every with the current tile shape and reverse kernel (0 on bad
- * arguments): ceil(nsteps/ckpt_every) checkpoints, min(ckpt_every, nsteps)
- * - 1 recomputed states, one more state and tables.  The recomputed states
- * are held twice when the reverse sweep is pipelined: with the blocked
- * reverse kernel on problems whose reverse launches hold fewer than 2048
- * wavefronts (small lattices), the recompute of one checkpoint segment runs
- * on a second stream beside the reverse steps of the next. */
+ * ckpt_every with the current tile shape, reverse kernel and recompute
+ * stride (0 on bad arguments): ceil(nsteps/ckpt_every) checkpoints, the
+ * stored recomputed states (m = min(ckpt_every, nsteps) - 1 of them, or
+ * floor(m/2) at stride 2, see lbm_set_recompute_stride), one more state and
+ * tables.  The recomputed states are held twice when the reverse sweep is
+ * pipelined: with the blocked reverse kernel on problems whose reverse
+ * launches hold fewer than 2048 wavefronts (small lattices), the recompute
+ * of one checkpoint segment runs on a second stream beside the reverse
+ * steps of the next. */
 LBM_API size_t lbm_adjoint_workspace_bytes(lbm_handle* h, int64_t nsteps,
                                            int64_t ckpt_every);
 /* Advances f (device, 6*n) by nsteps steps in place like lbm_step, keeping
@@ -255,6 +257,18 @@ LBM_API int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
  * LBM_ENOTSUP an explicit LBM_KERNEL_BLOCKED whose halo leaves even those
  * no interior (4K >= 2048).  Takes effect at the next lbm_forward_ckpt. */
 LBM_API int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
+/* Stride of the recomputed forward states that the blocked reverse sweep
+ * stores: 1 keeps every state of a checkpoint segment; 2 keeps the even ones
+ * only, and the reverse kernel recomputes each odd state from the one before
+ * (one forward step per two reverse steps, bitwise the stored value) in
+ * place of a store and a load of 48 bytes per node, with half the segment
+ * buffer and a halo of 2K + 2.  0 (the default) takes 2 where the reverse
+ * launches hold at least 2048 wavefronts (large problems, whose sweep is
+ * bound by those loads and stores) and 1 elsewhere.  Stride 2 applies only
+ * to the blocked kernel at P = 2 with K >= 2 (elsewhere the sweep keeps
+ * every state).  Results do not depend on it.  Takes effect at the next
+ * lbm_forward_ckpt; LBM_EINVAL for a stride outside 0..2. */
+LBM_API int lbm_set_recompute_stride(lbm_handle* h, int stride);
 
 /* ------------------------------------------------- batches of lattices */
 
@@ -348,6 +362,7 @@ LBM_API int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
 LBM_API int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
                                       void* ws, size_t ws_bytes);
 LBM_API int lbm_batch_set_adjoint_kernel(lbm_batch* b, int kernel);
+LBM_API int lbm_batch_set_recompute_stride(lbm_batch* b, int stride);
 
 #ifdef __cplusplus
 }

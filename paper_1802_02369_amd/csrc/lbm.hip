@@ -418,16 +418,18 @@ __device__ __forceinline__ int active_waves(int64_t n, int64_t start, int H) {
 // H >= 2K).  Only the first nw wavefronts work (span P(62 nw + 2)); the
 // others end at once, which a workgroup barrier allows (it waits for the
 // wavefronts that have not ended), and leave their SIMDs to other
-// workgroups.  With every_step, the interior is stored after each step
-// s = 1..K into the state fout + (s-1)*state_stride (the states a reverse
-// sweep needs).
+// workgroups.  With every_step (the recompute of a checkpoint segment for a
+// reverse sweep), the state after step s = 1..K is state i = first + s of
+// the segment, and the interior of those states whose i is a multiple of
+// `every` is stored, state i into fout + ((i-1)/every)*state_stride.
 template <int P, int WG, int EQ>
 __device__ __forceinline__ void tile_run(const Consts& c,
                                          const double* __restrict__ fin,
                                          double* __restrict__ fout, int64_t S,
                                          int64_t n, int64_t start, int H,
                                          int K, bool every_step = false,
-                                         int64_t state_stride = 0) {
+                                         int64_t state_stride = 0,
+                                         int first = 0, int every = 1) {
   constexpr int WW = 64 * P;       // nodes of one wavefront
   constexpr int WS = 62 * P;       // wavefront stride in the tile
   __shared__ double stage[WG * (WW + 64)];
@@ -450,9 +452,9 @@ __device__ __forceinline__ void tile_run(const Consts& c,
   int since = 0, buf = 0;
   for (int step = 0; step < K; ++step) {
     tile_step<P, EQ>(c, f);
-    if (every_step)
-      tile_store<P>(fout + step * state_stride, S, n, wstart, lo, hi, lane,
-                    lds, f);
+    if (every_step && (first + step + 1) % every == 0)
+      tile_store<P>(fout + (int64_t)((first + step) / every) * state_stride, S,
+                    n, wstart, lo, hi, lane, lds, f);
     if (WG > 1 && ++since == P / 2 && step + 1 < K) {
       mirror_refresh<P, WG>(f, edge[buf], lane, wave, nw);
       buf ^= 1;
@@ -487,14 +489,14 @@ __global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0)) void 
 // which occupies [offs[inst], offs[inst+1]) of every array of a state of
 // array stride S, with that lattice's own constants.  The tiling (halo H,
 // OUT = W - 2H) is fixed by the tile table; a launch runs K <= H/2 steps.
-// EVERY: store the state after every step, step s into
-// fout + (s-1)*state_stride.
+// EVERY: store the states of a checkpoint segment that the reverse sweep
+// loads (see tile_run: first, every).
 template <int P, int WG, int EQ, bool EVERY>
 __global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0 && !EVERY)) void k_batch_tile(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const lbm::TileRef* __restrict__ tiles, const double* __restrict__ fin,
     double* __restrict__ fout, int64_t S, int H, int K, int64_t ntiles,
-    int64_t state_stride) {
+    int64_t state_stride, int first, int every) {
   const int64_t b = blockIdx.x;
   if (b >= ntiles) return;  // uniform over the workgroup
   const lbm::TileRef tr = tiles[b];
@@ -503,7 +505,7 @@ __global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0 && !EVE
   const Consts c = cs[tr.inst];
   const int OUT = lbm::tile_nodes(P, WG) - 2 * H;
   tile_run<P, WG, EQ>(c, fin + off, fout + off, S, n, (int64_t)tr.t * OUT - H, H,
-                  K, EVERY, state_stride);
+                  K, EVERY, state_stride, first, every);
 }
 
 // One workgroup per lattice of a batch: moments m = M f (eq. M-d1q3q3).
@@ -735,33 +737,41 @@ template <int P, int WG>
 static void launch_batch_t(const Consts* cs, const int64_t* offs,
                            const TileRef* tiles, int64_t ntiles,
                            const double* fin, double* fout, int64_t S, int H,
-                           int K, int64_t state_stride, int eq, hipStream_t s) {
+                           int K, int64_t state_stride, int first, int every,
+                           int eq, hipStream_t s) {
   const dim3 grid((unsigned)ntiles), block(64 * WG);
   if (eq == 0 && state_stride == 0)
     hipLaunchKernelGGL((k_batch_tile<P, WG, 0, false>), grid, block, 0, s, cs,
-                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride, first,
+                       every);
   else if (eq == 0)
     hipLaunchKernelGGL((k_batch_tile<P, WG, 0, true>), grid, block, 0, s, cs,
-                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride, first,
+                       every);
   else if (state_stride == 0)
     hipLaunchKernelGGL((k_batch_tile<P, WG, -1, false>), grid, block, 0, s, cs,
-                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride, first,
+                       every);
   else
     hipLaunchKernelGGL((k_batch_tile<P, WG, -1, true>), grid, block, 0, s, cs,
-                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride);
+                       offs, tiles, fin, fout, S, H, K, ntiles, state_stride, first,
+                       every);
 }
 
 int launch_batch_tile(const Consts* cs, const int64_t* offs,
                       const TileRef* tiles, int64_t ntiles, const double* fin,
                       double* fout, int64_t S, int P, int H, int K, int wg,
-                      int eq, hipStream_t s, int64_t state_stride) {
+                      int eq, hipStream_t s, int64_t state_stride, int first,
+                      int every) {
   if (ntiles <= 0) return LBM_OK;
   if (K < 1 || 2 * K > H || 2 * H >= tile_nodes(P, wg))
     return set_err(LBM_EINVAL, "bad batched tile geometry H=%d K=%d", H, K);
+  if (first < 0 || every < 1)
+    return set_err(LBM_EINVAL, "bad segment state numbering");
 #define LBM_BATCH_CASE(PP, WW)                                              \
   if (P == PP && wg == WW) {                                                \
     launch_batch_t<PP, WW>(cs, offs, tiles, ntiles, fin, fout, S, H, K,    \
-                           state_stride, eq, s);                            \
+                           state_stride, first, every, eq, s);              \
     return hip_check(hipGetLastError(), "k_batch_tile");                    \
   }
   LBM_BATCH_CASE(2, 1)

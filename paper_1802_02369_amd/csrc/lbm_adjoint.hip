@@ -418,9 +418,110 @@ __device__ __forceinline__ void adjoint_tile_step(
   }
 }
 
-// Reverse steps i_hi-1 down to i_lo of a checkpoint segment; the forward
-// state of step i is ck (i = 0) or seg + (i-1)*SD.
+// One forward step of the reverse kernel's tile (wavefronts side by side,
+// without the forward kernels' mirror lanes), for the states the reverse
+// sweep recomputes from the state before: the node arithmetic of the forward
+// kernels (collide_local, source_g, streaming) in the same order, so the
+// result is bitwise the state they produce.  Neighbours inside a wavefront
+// come through DPP; the edge nodes of neighbouring wavefronts through LDS:
+// their u, T (xa) before the sources and their outgoing populations (xb)
+// before the streaming.  The tile's two outer nodes on each side are wrong
+// afterwards (they have no neighbour), which the halo absorbs.
 template <int P, int WG>
+__device__ __forceinline__ void tile_step_x(const Consts& c, double (&f)[6][P],
+                                            double (*xa)[4], double (*xb)[4],
+                                            int lane, int wave) {
+  double uA, TA, rwA, wA;  // node P-1, collided first
+  lbm::collide_local<-1>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
+                         f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
+  double um, Tm, rwm, wm;  // node k (the one whose source is next)
+  lbm::collide_local<-1>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0],
+                         f[5][0], um, Tm, rwm, wm);
+  double ul = lbm::from_left(uA), Tl = lbm::from_left(TA);
+  double uR = lbm::from_right(um), TR = lbm::from_right(Tm);
+  if (WG > 1) {
+    if (lane == 0) {
+      xa[wave][0] = um;
+      xa[wave][1] = Tm;
+    }
+    if (lane == 63) {
+      xa[wave][2] = uA;
+      xa[wave][3] = TA;
+    }
+    __syncthreads();
+    if (lane == 0 && wave > 0) {
+      ul = xa[wave - 1][2];
+      Tl = xa[wave - 1][3];
+    }
+    if (lane == 63 && wave < WG - 1) {
+      uR = xa[wave + 1][0];
+      TR = xa[wave + 1][1];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    double ur, Tr, rwr = 0.0, wr = 0.0;
+    if (k + 1 < P - 1) {
+      lbm::collide_local<-1>(c, f[0][k + 1], f[1][k + 1], f[2][k + 1],
+                             f[3][k + 1], f[4][k + 1], f[5][k + 1], ur, Tr, rwr,
+                             wr);
+    } else if (k + 1 == P - 1) {
+      ur = uA;
+      Tr = TA;
+      rwr = rwA;
+      wr = wA;
+    } else {
+      ur = uR;
+      Tr = TR;
+    }
+    const double add = lbm::source_g(c, rwm, wm, ul, ur, Tl, Tr);
+    f[3][k] += add;
+    f[4][k] += add;
+    f[5][k] += add;
+    ul = um;
+    Tl = Tm;
+    um = ur;
+    Tm = Tr;
+    rwm = rwr;
+    wm = wr;
+  }
+  // (viii) streaming
+  double fpL = lbm::from_left(f[1][P - 1]), gpL = lbm::from_left(f[4][P - 1]);
+  double fmR = lbm::from_right(f[2][0]), gmR = lbm::from_right(f[5][0]);
+  if (WG > 1) {
+    if (lane == 63) {
+      xb[wave][0] = f[1][P - 1];
+      xb[wave][1] = f[4][P - 1];
+    }
+    if (lane == 0) {
+      xb[wave][2] = f[2][0];
+      xb[wave][3] = f[5][0];
+    }
+    __syncthreads();
+    if (lane == 0 && wave > 0) {
+      fpL = xb[wave - 1][0];
+      gpL = xb[wave - 1][1];
+    }
+    if (lane == 63 && wave < WG - 1) {
+      fmR = xb[wave + 1][2];
+      gmR = xb[wave + 1][3];
+    }
+  }
+  shift_right<P>(f[1], fpL);
+  shift_right<P>(f[4], gpL);
+  shift_left<P>(f[2], fmR);
+  shift_left<P>(f[5], gmR);
+}
+
+// Reverse steps i_hi-1 down to i_lo of a checkpoint segment.  E = 1: the
+// forward state of every step i is stored, ck (i = 0) or seg + (i-1)*SD.
+// E = 2: only the even ones are (state i at seg + (i/2-1)*SD); an odd step's
+// state is recomputed from the one before, which then serves the next (even)
+// step, so each such pair of steps loads one state.  The prefetch of a pair's
+// state is issued during the previous pair.  If the launch's first step is
+// odd, its recomputed state is wrong at the two outer nodes of each side,
+// which costs the halo two more nodes (H >= 2K + 2).
+template <int P, int WG, int E>
 __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const TileRef* __restrict__ tiles, int64_t ntiles,
@@ -432,6 +533,7 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   __shared__ double stage[WG * (WW + 64)];
   __shared__ Boundary bnd[WG];
   __shared__ double bab[WG][4];
+  __shared__ double xa[E == 2 ? WG : 1][4], xb[E == 2 ? WG : 1][4];
   __shared__ double red[3][64 * WG];
   const int64_t b = blockIdx.x;
   if (b >= ntiles) return;  // uniform over the workgroup
@@ -460,16 +562,35 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   tile_fetch<P>(fbn + off, S, gi, raw);
   tile_transpose<P>(lane, lds, raw, fb);
   auto state = [&](int i) {
-    return (i == 0 ? ck : seg + (int64_t)(i - 1) * SD) + off;
+    return (i == 0 ? ck : seg + (int64_t)((i - 1) / E) * SD) + off;
   };
+  // the stored state step i starts from
+  auto base = [](int i) { return E == 2 ? (i & ~1) : i; };
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  // the forward state of the next (earlier) step is fetched while this
-  // step computes
-  tile_fetch<P>(state(i_hi - 1), S, gi, raw);
+  // the stored state of the next (earlier) step or pair is fetched while
+  // this one computes
+  tile_fetch<P>(state(base(i_hi - 1)), S, gi, raw);
+  double fa[6][P];  // E = 2: the even state an odd step was recomputed from
   for (int i = i_hi - 1; i >= i_lo; --i) {
     double ft[6][P];
-    tile_transpose<P>(lane, lds, raw, ft);
-    if (i > i_lo) tile_fetch<P>(state(i - 1), S, gi, raw);
+    if (E == 2 && (i & 1)) {
+      tile_transpose<P>(lane, lds, raw, fa);
+      if (i - 2 >= i_lo) tile_fetch<P>(state(base(i - 2)), S, gi, raw);
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int k = 0; k < P; ++k) ft[q][k] = fa[q][k];
+      tile_step_x<P, WG>(c, ft, xa, xb, lane, wave);
+    } else if (E == 2 && i < i_hi - 1) {
+      // the state the odd step i + 1 was recomputed from
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int k = 0; k < P; ++k) ft[q][k] = fa[q][k];
+    } else {
+      tile_transpose<P>(lane, lds, raw, ft);
+      if (i > i_lo) tile_fetch<P>(state(base(i - 1)), S, gi, raw);
+    }
     adjoint_tile_step<P, WG>(c, ft, fb, bnd, bab, lane, wave, own, r0, r1, r2);
   }
   tile_store<P>(fbo + off, S, n, wstart, H - wave * WW, W - H - wave * WW,
@@ -490,40 +611,49 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   if (t < 3) rslots[3 * b + t] += red[t][0];
 }
 
-template <int P, int WG>
+template <int P, int WG, int E>
 void launch_adjoint_tile_t(const Consts* cs, const int64_t* offs,
                            const TileRef* tiles, int64_t ntiles,
                            const double* ck, const double* seg, int64_t SD,
                            int i_lo, int i_hi, const double* fbn, double* fbo,
                            int64_t S, int H, double* rslots, hipStream_t s) {
-  hipLaunchKernelGGL((k_adjoint_tile<P, WG>), dim3((unsigned)ntiles),
+  hipLaunchKernelGGL((k_adjoint_tile<P, WG, E>), dim3((unsigned)ntiles),
                      dim3(64 * WG), 0, s, cs, offs, tiles, ntiles, ck, seg, SD,
                      i_lo, i_hi, fbn, fbo, S, H, rslots);
 }
 
-int launch_adjoint_tile(int P, int WG, const Consts* cs, const int64_t* offs,
-                        const TileRef* tiles, int64_t ntiles, const double* ck,
-                        const double* seg, int64_t SD, int i_lo, int i_hi,
-                        const double* fbn, double* fbo, int64_t S, int H,
-                        double* rslots, hipStream_t s) {
-  if (i_hi - i_lo < 1 || 2 * (i_hi - i_lo) > H || 2 * H >= 64 * P * WG)
+// E: stride of the stored segment states (1, or 2 at P = 2).
+int launch_adjoint_tile(int P, int WG, int E, const Consts* cs,
+                        const int64_t* offs, const TileRef* tiles,
+                        int64_t ntiles, const double* ck, const double* seg,
+                        int64_t SD, int i_lo, int i_hi, const double* fbn,
+                        double* fbo, int64_t S, int H, double* rslots,
+                        hipStream_t s) {
+  if (i_hi - i_lo < 1 || 2 * (i_hi - i_lo) + (E == 2 ? 2 : 0) > H ||
+      2 * H >= 64 * P * WG)
     return set_err(LBM_EINVAL, "bad adjoint tile geometry");
-#define LBM_ADJ_CASE(PP, WW)                                                  \
-  if (P == PP && WG == WW) {                                                  \
-    launch_adjoint_tile_t<PP, WW>(cs, offs, tiles, ntiles, ck, seg, SD, i_lo, \
-                                  i_hi, fbn, fbo, S, H, rslots, s);           \
+#define LBM_ADJ_CASE(PP, WW, EE)                                              \
+  if (P == PP && WG == WW && E == EE) {                                       \
+    launch_adjoint_tile_t<PP, WW, EE>(cs, offs, tiles, ntiles, ck, seg, SD,   \
+                                      i_lo, i_hi, fbn, fbo, S, H, rslots, s); \
     return hip_check(hipGetLastError(), "k_adjoint_tile");                    \
   }
-  LBM_ADJ_CASE(2, 1)
-  LBM_ADJ_CASE(2, 2)
-  LBM_ADJ_CASE(2, 4)
-  LBM_ADJ_CASE(2, 8)
-  LBM_ADJ_CASE(4, 1)
-  LBM_ADJ_CASE(4, 2)
-  LBM_ADJ_CASE(4, 4)
-  LBM_ADJ_CASE(4, 8)
+  LBM_ADJ_CASE(2, 1, 1)
+  LBM_ADJ_CASE(2, 2, 1)
+  LBM_ADJ_CASE(2, 4, 1)
+  LBM_ADJ_CASE(2, 8, 1)
+  LBM_ADJ_CASE(2, 1, 2)
+  LBM_ADJ_CASE(2, 2, 2)
+  LBM_ADJ_CASE(2, 4, 2)
+  LBM_ADJ_CASE(2, 8, 2)
+  LBM_ADJ_CASE(4, 1, 1)
+  LBM_ADJ_CASE(4, 2, 1)
+  LBM_ADJ_CASE(4, 4, 1)
+  LBM_ADJ_CASE(4, 8, 1)
 #undef LBM_ADJ_CASE
-  return set_err(LBM_EINVAL, "unsupported adjoint tile shape P=%d waves=%d", P, WG);
+  return set_err(LBM_EINVAL,
+                 "unsupported adjoint tile shape P=%d waves=%d stride=%d", P,
+                 WG, E);
 }
 
 // fbar of the equilibrium initialisation -> adjoints of rho, J, zeta.
@@ -642,31 +772,29 @@ struct AdjLayout {
       rslots, scratch, pp, ckpt, seg, total;
 };
 
-// The recompute runs with the forward tile shape and stores every step.
+// The recompute runs with the forward tile shape.
 lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
 
-// Tile shape of the blocked reverse kernel for a forward tuning.  Its tiles
-// span 64 P W nodes (no overlap between wavefronts) with the forward halo 2K.
-// P = 2 keeps two wavefronts per SIMD (the reverse step needs about 220
-// VGPRs at P = 2, over 256 at P = 4), with the wavefronts that give about
-// the forward tile's width (at least the forward's, at most 8); a halo too
-// wide for those tiles (4K >= 128 W) falls back to P = 4 with 8 wavefronts.
-lbm_tuning rev_tuning(const lbm_tuning& t) {
-  lbm_tuning r = t;
-  r.nodes_per_lane = 2;
-  r.waves_per_group = std::min(
-      8, std::max(t.waves_per_group, t.nodes_per_lane * t.waves_per_group / 2));
-  if (4 * t.steps_per_launch >= 64 * 2 * r.waves_per_group) {
-    r.nodes_per_lane = 4;
-    r.waves_per_group = 8;
-  }
-  return r;
-}
+// Tile shape of the blocked reverse kernel for a forward tuning and a stride
+// E of the stored segment states.  Its tiles span 64 P W nodes (no overlap
+// between wavefronts) with halo H = 2K, or 2K + 2 at E = 2 (see
+// k_adjoint_tile).  P = 2 keeps two wavefronts per SIMD (the reverse step
+// needs about 220 VGPRs at P = 2, over 256 at P = 4), with the wavefronts
+// that give about the forward tile's width (at least the forward's, at most
+// 8); a halo too wide for those tiles falls back to P = 4 with 8 wavefronts
+// and E = 1.
+struct RevShape {
+  int P, W, H, E;
+  int64_t out() const { return 64 * (int64_t)P * W - 2 * (int64_t)H; }
+};
 
-int64_t rev_out(const lbm_tuning& t) {
-  const lbm_tuning r = rev_tuning(t);
-  return 64 * (int64_t)r.nodes_per_lane * r.waves_per_group -
-         4 * (int64_t)t.steps_per_launch;
+RevShape rev_shape(const lbm_tuning& t, int E) {
+  const int K = t.steps_per_launch;
+  RevShape r{2, std::min(8, std::max(t.waves_per_group,
+                                     t.nodes_per_lane * t.waves_per_group / 2)),
+             2 * K + (E == 2 ? 2 : 0), E};
+  if (2 * r.H >= 64 * 2 * r.W) r = RevShape{4, 8, 2 * K, 1};
+  return r;
 }
 
 // Tiles of `out` output nodes covering every lattice (0 if out < 1: such a
@@ -691,35 +819,71 @@ int64_t adj_tile_count(const lbm_batch* b) {
 // the forward halo).
 bool resolve_adj_plain(const lbm_batch* b) {
   return b->adj_kernel == LBM_KERNEL_PLAIN ||
-         (b->adj_kernel == LBM_KERNEL_AUTO && rev_out(b->tune) < 1);
+         (b->adj_kernel == LBM_KERNEL_AUTO && rev_shape(b->tune, 1).out() < 1);
 }
 
-// Whether the reverse sweep overlaps the recompute of one checkpoint segment
-// with the reverse steps of the next (two buffers of segment states): with
-// the blocked reverse kernel, when its launches leave most of the chip idle
-// (fewer wavefronts than the 2048 the 256 CUs hold at two per SIMD), as on
-// small lattices bound by launch latency.  A launch that fills the chip
-// gains nothing from a second stream (measured on the 1024-lattice
-// gradient) and the second buffer would cost (C-1) more states.
-bool adj_pipelined(const lbm_batch* b, bool plain) {
-  if (plain) return false;
-  const int64_t out = rev_out(b->tune);
-  if (out < 1) return false;
-  return tiles_of(b, out) * rev_tuning(b->tune).waves_per_group < 2048;
+// Launches of the blocked reverse kernel fill the chip when they have at
+// least the 2048 wavefronts that 256 CUs hold at two per SIMD.
+bool rev_fills_chip(const lbm_batch* b, const RevShape& r) {
+  return tiles_of(b, r.out()) * r.W >= 2048;
 }
 
-// Workspace layout; `pipelined`: two buffers of segment states (see
-// adj_pipelined).  The segment states come last: the other offsets do not
-// depend on it.
+// Stride of the segment states the reverse sweep stores.  Every second one
+// (the kernel recomputes the others: one forward step per pair of reverse
+// steps in place of storing and loading 48 bytes per node, and half the
+// segment buffer) needs the blocked kernel at P = 2 with K >= 2.  Automatic
+// (0): there, where its launches fill the chip; a launch-bound sweep (small
+// lattices) keeps every state, as the recomputation would lengthen each
+// launch.
+int resolve_every(const lbm_batch* b, bool plain) {
+  if (plain || b->tune.steps_per_launch < 2) return 1;
+  const RevShape r = rev_shape(b->tune, 2);
+  if (r.E != 2 || r.out() < 1) return 1;
+  if (b->rec_stride == 1 || b->rec_stride == 2) return b->rec_stride;
+  return rev_fills_chip(b, r) ? 2 : 1;
+}
+
+// The reverse sweep's settings: one-step kernel or the blocked one with its
+// tile shape and state stride, and whether the sweep overlaps the recompute
+// of one checkpoint segment with the reverse steps of the next (two buffers
+// of segment states): with the blocked kernel when its launches leave most
+// of the chip idle, as on small lattices bound by launch latency.  A launch
+// that fills the chip gains nothing from a second stream (measured on the
+// 1024-lattice gradient) and the second buffer would cost its states again.
+struct AdjPlan {
+  bool plain, pipelined;
+  RevShape rev;
+};
+
+AdjPlan adj_plan(const lbm_batch* b, bool plain, int every) {
+  AdjPlan p{plain, false, rev_shape(b->tune, plain ? 1 : every)};
+  p.pipelined = !plain && p.rev.out() >= 1 && !rev_fills_chip(b, p.rev);
+  return p;
+}
+
+// The plan of the current settings (workspace queries) and the one that
+// lbm_batch_forward_ckpt resolved (the reverse sweep and its checks).
+AdjPlan current_plan(const lbm_batch* b) {
+  const bool plain = resolve_adj_plain(b);
+  return adj_plan(b, plain, resolve_every(b, plain));
+}
+AdjPlan resolved_plan(const lbm_batch* b) {
+  return adj_plan(b, b->adj_plain, b->adj_every);
+}
+
+// Workspace layout.  The segment states come last: the other offsets do not
+// depend on them.
 AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C,
-                     bool pipelined) {
+                     const AdjPlan& P) {
   AdjLayout L{};
   L.n_fwd = b->count_tiles(b->tune);
   L.n_rec = b->count_tiles(rec_tuning(b->tune));
-  L.n_rev = tiles_of(b, rev_out(b->tune));
+  L.n_rev = tiles_of(b, P.rev.out());
   L.n_adj = adj_tile_count(b);
   L.n_ck = nsteps > 0 ? (nsteps + C - 1) / C : 1;
-  L.n_seg = std::max<int64_t>(0, std::min(C, nsteps) - 1);
+  // states 1 .. len-1 of a segment of len steps, or the even ones
+  L.n_seg = std::max<int64_t>(0, std::min(C, nsteps) - 1) /
+            (P.plain ? 1 : P.rev.E);
   const size_t state = sizeof(double) * 6 * (size_t)b->n_total;
   size_t o = 0;
   L.consts = o;
@@ -748,7 +912,7 @@ AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C,
   L.ckpt = o;
   o = align256(o + state * (size_t)L.n_ck);
   L.seg = o;
-  L.seg_bufs = pipelined ? 2 : 1;
+  L.seg_bufs = P.pipelined ? 2 : 1;
   o = align256(o + state * (size_t)L.n_seg * L.seg_bufs);
   L.total = o;
   return L;
@@ -817,11 +981,12 @@ int check_adj(const lbm_batch* b, const void* ws, size_t ws_bytes,
               int64_t nsteps, int64_t C) {
   if (!b || !ws) return set_err(LBM_EINVAL, "NULL argument");
   if (b->adj_ws != ws || b->adj_nsteps != nsteps || b->adj_ckpt != C ||
-      !same_tuning(b->adj_tune, b->tune) || b->adj_plain_up != b->adj_plain)
+      !same_tuning(b->adj_tune, b->tune) || b->adj_plain_up != b->adj_plain ||
+      b->adj_every_up != b->adj_every)
     return set_err(LBM_EINVAL,
                    "no checkpoints for this workspace, nsteps and ckpt_every: "
                    "call lbm_batch_forward_ckpt first");
-  if (ws_bytes < adj_layout(b, nsteps, C, adj_pipelined(b, b->adj_plain)).total)
+  if (ws_bytes < adj_layout(b, nsteps, C, resolved_plan(b)).total)
     return set_err(LBM_EWORKSPACE, "adjoint workspace too small");
   return LBM_OK;
 }
@@ -829,7 +994,8 @@ int check_adj(const lbm_batch* b, const void* ws, size_t ws_bytes,
 // The reverse sweep: recompute each checkpoint segment, then adjoint steps.
 int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
                     double* fbar, double* rbar, hipStream_t s) {
-  const AdjLayout L = adj_layout(b, nsteps, C, adj_pipelined(b, b->adj_plain));
+  const AdjPlan plan = resolved_plan(b);
+  const AdjLayout L = adj_layout(b, nsteps, C, plan);
   const Consts* cs = at<Consts>(ws, L.consts);
   const int64_t* offs = at<int64_t>(ws, L.offs);
   const size_t SD = 6 * (size_t)b->n_total;
@@ -843,38 +1009,43 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
   double* oth = at<double>(ws, L.pp);
   const int Prec = b->tune.nodes_per_lane, Wrec = b->tune.waves_per_group;
   const int Krec = b->tune.steps_per_launch;
+  // stride of the stored segment states
+  const int E = plan.plain ? 1 : plan.rev.E;
   auto seg_len = [&](int64_t k) { return std::min(C, nsteps - k * C); };
   auto ckpt = [&](int64_t k) { return at<double>(ws, L.ckpt) + SD * k; };
-  // segment k's states t0+1 .. t0+len-1 live in segment buffer k % seg_bufs
+  // segment k's stored states (t0+1 .. t0+len-1, or the even ones) live in
+  // segment buffer k % seg_bufs
   auto segbuf = [&](int64_t k) {
     return at<double>(ws, L.seg) + SD * (size_t)L.n_seg * (size_t)(k % L.seg_bufs);
   };
   auto state = [&](int64_t k, int64_t i) {
-    return i == 0 ? ckpt(k) : segbuf(k) + SD * (i - 1);
+    return i == 0 ? ckpt(k) : segbuf(k) + SD * ((i - 1) / E);
   };
-  // recompute of segment k on stream st: up to Krec states per launch
+  // recompute of segment k on stream st: up to Krec states per launch, each
+  // launch starting from a stored state (an even one at E = 2)
+  const int Kst = E == 2 ? Krec & ~1 : Krec;
   auto recompute = [&](int64_t k, hipStream_t st) -> int {
     const int64_t len = seg_len(k);
-    for (int64_t i0 = 0; i0 + 1 < len; i0 += Krec) {
-      const int kk = (int)std::min<int64_t>(Krec, len - 1 - i0);
+    for (int64_t i0 = 0; i0 + 1 < len; i0 += Kst) {
+      const int kk = (int)std::min<int64_t>(Kst, len - 1 - i0);
       const int r = launch_batch_tile(cs, offs, at<TileRef>(ws, L.rec_tiles),
-                                      L.n_rec, state(k, i0), state(k, i0 + 1),
+                                      L.n_rec, state(k, i0), segbuf(k),
                                       b->n_total, Prec, 2 * Krec, kk, Wrec,
-                                      b->eq_class(), st, (int64_t)SD);
+                                      b->eq_class(), st, (int64_t)SD, (int)i0,
+                                      E);
       if (r) return r;
     }
     return LBM_OK;
   };
-  const lbm_tuning rt = rev_tuning(b->tune);
-  const int Padj = rt.nodes_per_lane, Wadj = rt.waves_per_group;
+  const RevShape rv = plan.rev;
   // the blocked reverse steps of segment k on s, up to Krec per launch
   auto reverse = [&](int64_t k) -> int {
     for (int64_t hi = seg_len(k); hi > 0;) {
       const int64_t lo = std::max<int64_t>(0, hi - Krec);
       const int r = launch_adjoint_tile(
-          Padj, Wadj, cs, offs, at<TileRef>(ws, L.rev_tiles), L.n_rev, ckpt(k),
-          segbuf(k), (int64_t)SD, (int)lo, (int)hi, cur, oth, b->n_total,
-          2 * Krec, slots, s);
+          rv.P, rv.W, rv.E, cs, offs, at<TileRef>(ws, L.rev_tiles), L.n_rev,
+          ckpt(k), segbuf(k), (int64_t)SD, (int)lo, (int)hi, cur, oth,
+          b->n_total, rv.H, slots, s);
       if (r) return r;
       std::swap(cur, oth);
       hi = lo;
@@ -962,6 +1133,7 @@ lbm_batch* synced_batch(lbm_handle* h) {
   if (h->tune.kernel == LBM_KERNEL_BLOCKED && !same_tuning(b->tune, h->tune))
     lbm_batch_set_tuning(b, &h->tune);
   b->adj_kernel = h->adj_kernel;
+  b->rec_stride = h->rec_stride;
   return b;
 }
 
@@ -982,7 +1154,7 @@ size_t lbm_batch_adjoint_workspace_bytes(const lbm_batch* b, int64_t nsteps,
                                          int64_t ckpt_every) {
   if (!b || nsteps < 0 || ckpt_every < 1) return 0;
   return adj_layout(b, nsteps, ckpt_every,
-                    adj_pipelined(b, resolve_adj_plain(b))).total;
+                    current_plan(b)).total;
 }
 
 int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
@@ -993,7 +1165,9 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   // AUTO: the blocked reverse kernel (a prefetching K-step tile) wherever
   // its tiles can hold the forward halo, else the one-step kernel
   b->adj_plain = resolve_adj_plain(b);
-  const AdjLayout L = adj_layout(b, nsteps, ckpt_every, adj_pipelined(b, b->adj_plain));
+  b->adj_every = resolve_every(b, b->adj_plain);
+  const AdjPlan plan = resolved_plan(b);
+  const AdjLayout L = adj_layout(b, nsteps, ckpt_every, plan);
   if (ws_bytes < L.total)
     return set_err(LBM_EWORKSPACE, "adjoint workspace of %zu bytes, need %zu",
                    ws_bytes, L.total);
@@ -1001,7 +1175,7 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     return set_err(LBM_EINVAL, "f and ws overlap");
   if (((uintptr_t)f | (uintptr_t)ws) & 7)
     return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
-  if (!b->adj_plain && rev_out(b->tune) < 1)
+  if (!b->adj_plain && plan.rev.out() < 1)
     return set_err(LBM_ENOTSUP,
                    "the blocked adjoint kernel's tiles (P = 4, 8 wavefronts "
                    "for this shape) cannot hold a halo of 2K = %d nodes; use "
@@ -1029,7 +1203,8 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   const bool same = b->adj_ws == ws && b->adj_nsteps == nsteps &&
                     b->adj_ckpt == ckpt_every &&
                     same_tuning(b->adj_tune, b->tune) &&
-                    b->adj_plain_up == b->adj_plain;
+                    b->adj_plain_up == b->adj_plain &&
+                    b->adj_every_up == b->adj_every;
   if (!same) {
     // tables of this workspace layout: forward and recompute tiles (the
     // forward tile shape), tiles of the blocked and of the one-step reverse
@@ -1037,7 +1212,7 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     const auto fwd = tile_table(b, tile_width(b->tune) - 4 * b->tune.steps_per_launch);
     const auto rec = tile_table(
         b, tile_width(rec_tuning(b->tune)) - 4 * b->tune.steps_per_launch);
-    const auto rev = tile_table(b, rev_out(b->tune));
+    const auto rev = tile_table(b, plan.rev.out());
     const auto adj = tile_table(b, kAdjOut);
     auto firsts = [&](const std::vector<TileRef>& tab) {
       std::vector<int64_t> first(b->n_inst + 1, 0);
@@ -1069,6 +1244,7 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     b->adj_ckpt = ckpt_every;
     b->adj_tune = b->tune;
     b->adj_plain_up = b->adj_plain;
+    b->adj_every_up = b->adj_every;
   }
   return enqueue_forward_ckpt(b, ws, f, nsteps, ckpt_every, L, s);
 }
@@ -1116,9 +1292,9 @@ int lbm_batch_adjoint(lbm_batch* b, void* ws, size_t ws_bytes, int64_t nsteps,
 int lbm_batch_loss(lbm_batch* b, const double* f, const double* target,
                    void* ws, size_t ws_bytes, double* loss, double* fbar) {
   if (!b || !f || !ws || !loss || !fbar) return set_err(LBM_EINVAL, "NULL argument");
-  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain)).total)
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, resolved_plan(b)).total)
     return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, resolved_plan(b));
   hipLaunchKernelGGL(k_loss, dim3((unsigned)b->n_inst), dim3(256), 0, b->stream,
                      at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs), f, target,
                      loss, fbar, b->n_total);
@@ -1132,9 +1308,9 @@ int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
                                   size_t ws_bytes) {
   if (!b || !rho || !J || !zeta || !fbar || !rho_bar || !J_bar || !zeta_bar || !ws)
     return set_err(LBM_EINVAL, "NULL argument");
-  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain)).total)
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, resolved_plan(b)).total)
     return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, resolved_plan(b));
   hipLaunchKernelGGL(k_equilibrium_adjoint, dim3((unsigned)b->n_inst), dim3(256),
                      0, b->stream, at<Consts>(ws, L.consts),
                      at<int64_t>(ws, L.offs), rho, J, zeta, fbar, rho_bar,
@@ -1145,9 +1321,9 @@ int lbm_batch_equilibrium_adjoint(lbm_batch* b, const double* rho,
 int lbm_batch_moments_adjoint(lbm_batch* b, const double* mbar, double* fbar,
                               void* ws, size_t ws_bytes) {
   if (!b || !mbar || !fbar || !ws) return set_err(LBM_EINVAL, "NULL argument");
-  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain)).total)
+  if (b->adj_ws != ws || ws_bytes < adj_layout(b, b->adj_nsteps, b->adj_ckpt, resolved_plan(b)).total)
     return set_err(LBM_EINVAL, "call lbm_batch_forward_ckpt with this workspace first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, resolved_plan(b));
   hipLaunchKernelGGL(k_moments_adjoint, dim3((unsigned)b->n_inst), dim3(256), 0,
                      b->stream, at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs),
                      mbar, fbar, b->n_total);
@@ -1165,6 +1341,22 @@ int lbm_batch_set_adjoint_kernel(lbm_batch* b, int kernel) {
 
 // ----------------------------------------------------- single lattice --
 
+int lbm_batch_set_recompute_stride(lbm_batch* b, int stride) {
+  if (!b) return set_err(LBM_EINVAL, "batch is NULL");
+  if (stride < 0 || stride > 2)
+    return set_err(LBM_EINVAL, "recompute stride must be 0, 1 or 2, not %d",
+                   stride);
+  b->rec_stride = stride;
+  return LBM_OK;
+}
+int lbm_set_recompute_stride(lbm_handle* h, int stride) {
+  if (!h) return set_err(LBM_EINVAL, "handle is NULL");
+  if (stride < 0 || stride > 2)
+    return set_err(LBM_EINVAL, "recompute stride must be 0, 1 or 2, not %d",
+                   stride);
+  h->rec_stride = stride;
+  return LBM_OK;
+}
 int lbm_set_adjoint_kernel(lbm_handle* h, int kernel) {
   if (!h) return set_err(LBM_EINVAL, "handle is NULL");
   if (kernel != LBM_KERNEL_AUTO && kernel != LBM_KERNEL_PLAIN &&
@@ -1195,7 +1387,7 @@ int lbm_adjoint(lbm_handle* h, void* ws, size_t ws_bytes, int64_t nsteps,
   if (!h || !rbar) return set_err(LBM_EINVAL, "NULL argument");
   lbm_batch* b = single_batch(h);
   if (!b) return LBM_EINVAL;
-  const AdjLayout L = adj_layout(b, nsteps, ckpt_every, adj_pipelined(b, b->adj_plain));
+  const AdjLayout L = adj_layout(b, nsteps, ckpt_every, resolved_plan(b));
   double* dev = at<double>(ws, L.scratch);
   int rc = lbm_batch_adjoint(b, ws, ws_bytes, nsteps, ckpt_every, fbar, dev,
                              use_graph);
@@ -1213,7 +1405,7 @@ int lbm_loss(lbm_handle* h, const double* f, const double* target, void* ws,
   lbm_batch* b = single_batch(h);
   if (!b) return LBM_EINVAL;
   if (b->adj_ws != ws) return set_err(LBM_EINVAL, "call lbm_forward_ckpt first");
-  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, adj_pipelined(b, b->adj_plain));
+  const AdjLayout L = adj_layout(b, b->adj_nsteps, b->adj_ckpt, resolved_plan(b));
   double* dev = at<double>(ws, L.scratch);
   int rc = lbm_batch_loss(b, f, target, ws, ws_bytes, dev, fbar);
   if (!rc)

@@ -31,13 +31,16 @@ int launch_diagnostics(const Consts& c, const double* f, int64_t n,
 int launch_moments(const Consts& c, const double* f, double* m, int64_t n,
                    hipStream_t s);
 
-// state_stride > 0: store the state after every one of the K steps, step s
-// (1-based) into fout + (s-1)*state_stride.  eq = 0 when every lattice of
-// the table has the equilibria of section 8 (eq_kind 0), else -1.
+// state_stride > 0: fin is state `first` of a checkpoint segment, and of
+// the states first+1 .. first+K the launch reaches, state i is stored into
+// fout + ((i-1)/every)*state_stride when i is a multiple of `every`.  eq = 0
+// when every lattice of the table has the equilibria of section 8
+// (eq_kind 0), else -1.
 int launch_batch_tile(const Consts* cs, const int64_t* offs,
                       const TileRef* tiles, int64_t ntiles, const double* fin,
                       double* fout, int64_t S, int P, int H, int K, int wg,
-                      int eq, hipStream_t s, int64_t state_stride = 0);
+                      int eq, hipStream_t s, int64_t state_stride = 0,
+                      int first = 0, int every = 1);
 int launch_batch_equilibrium(const Consts* cs, const int64_t* offs,
                              int64_t n_inst, const double* rho, const double* J,
                              const double* zeta, double* f, int64_t S,
@@ -153,6 +156,7 @@ struct lbm_handle {
   lbm_tuning tune;
   bool tune_default = true;  // tune is the default for n and the equilibria
   int32_t adj_kernel = LBM_KERNEL_AUTO;  // reverse-sweep kernel
+  int32_t rec_stride = 0;  // stride of the stored segment states (0: auto)
   lbm_batch* one = nullptr;  // batch of this one lattice, for the adjoint
 };
 
@@ -201,6 +205,11 @@ struct lbm_batch {
   // launch (else K per launch)
   bool adj_plain = false;
   bool adj_plain_up = false;  // the value the uploaded tables were built for
+  // requested stride of the segment states the reverse sweep stores (0:
+  // automatic), what lbm_batch_forward_ckpt resolved it to, and the value
+  // the uploaded tables were built for
+  int32_t rec_stride = 0;
+  int32_t adj_every = 1, adj_every_up = 1;
   // captured graph of the last lbm_batch_adjoint(use_graph = 1)
   hipGraphExec_t adj_exec = nullptr;
   const double* ag_fbar = nullptr;

@@ -119,6 +119,8 @@ def lib():
                                           ctypes.c_int),
             "lbm_set_adjoint_kernel": ([_vp, ctypes.c_int], ctypes.c_int),
             "lbm_batch_set_adjoint_kernel": ([_vp, ctypes.c_int], ctypes.c_int),
+            "lbm_set_recompute_stride": ([_vp, ctypes.c_int], ctypes.c_int),
+            "lbm_batch_set_recompute_stride": ([_vp, ctypes.c_int], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -274,6 +276,11 @@ class Lattice:
     # ------------------------------------------------------ gradients --
     def set_adjoint_kernel(self, kernel: int = KERNEL_AUTO):
         check(lib().lbm_set_adjoint_kernel(self._h, int(kernel)))
+
+    def set_recompute_stride(self, stride: int = 0):
+        """Stride of the recomputed states the reverse sweep stores (0 auto,
+        1 every state, 2 the even ones; lbm_set_recompute_stride)."""
+        check(lib().lbm_set_recompute_stride(self._h, int(stride)))
 
     def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):
         nb = int(lib().lbm_adjoint_workspace_bytes(self._h, int(nsteps),
@@ -477,6 +484,9 @@ class Batch:
     # ------------------------------------------------------ gradients --
     def set_adjoint_kernel(self, kernel: int = KERNEL_AUTO):
         check(lib().lbm_batch_set_adjoint_kernel(self._h, int(kernel)))
+
+    def set_recompute_stride(self, stride: int = 0):
+        check(lib().lbm_batch_set_recompute_stride(self._h, int(stride)))
 
     def adjoint_workspace(self, nsteps: int, ckpt_every: int, device="cuda"):
         nb = int(lib().lbm_batch_adjoint_workspace_bytes(

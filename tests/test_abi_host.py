@@ -191,6 +191,38 @@ def test_blocked_adjoint_shape_check_host(shape, ok):
     L.lbm_destroy(h)
 
 
+def test_recompute_stride_host():
+    """Stride 2 keeps floor((C-1)/2) of the C-1 recomputed states of a
+    segment (twice, on this small pipelined problem); it needs K >= 2 and
+    the blocked reverse kernel, and strides outside 0..2 are refused."""
+    n, steps, C = 5000, 100, 20
+    rc, h = _init(n)
+    assert rc == lbm.LBM_OK
+    L = lbm.lib()
+    state = 6 * n * 8
+    t = lbm.CTuning(lbm.KERNEL_BLOCKED, 2, 16, 1)
+    assert L.lbm_set_tuning(h, ctypes.byref(t)) == lbm.LBM_OK
+    auto = L.lbm_adjoint_workspace_bytes(h, steps, C)
+    assert L.lbm_set_recompute_stride(h, 1) == lbm.LBM_OK
+    assert L.lbm_adjoint_workspace_bytes(h, steps, C) == auto
+    assert L.lbm_set_recompute_stride(h, 2) == lbm.LBM_OK
+    two = L.lbm_adjoint_workspace_bytes(h, steps, C)
+    assert abs((auto - two) - 2 * (19 - 9) * state) < 256
+    assert L.lbm_set_adjoint_kernel(h, lbm.KERNEL_PLAIN) == lbm.LBM_OK
+    assert L.lbm_adjoint_workspace_bytes(h, steps, C) > two
+    assert L.lbm_set_adjoint_kernel(h, lbm.KERNEL_AUTO) == lbm.LBM_OK
+    t = lbm.CTuning(lbm.KERNEL_BLOCKED, 2, 1, 1)
+    assert L.lbm_set_tuning(h, ctypes.byref(t)) == lbm.LBM_OK
+    k1 = L.lbm_adjoint_workspace_bytes(h, steps, C)
+    assert L.lbm_set_recompute_stride(h, 1) == lbm.LBM_OK
+    assert L.lbm_adjoint_workspace_bytes(h, steps, C) == k1
+    for bad in (-1, 3):
+        assert L.lbm_set_recompute_stride(h, bad) == lbm.LBM_EINVAL
+        assert b"stride" in L.lbm_last_error()
+    assert L.lbm_batch_set_recompute_stride(None, 1) == lbm.LBM_EINVAL
+    L.lbm_destroy(h)
+
+
 @pytest.mark.parametrize("kw,shape", [
     (dict(), (8, 40, 4)),
     (dict(eq_kind=1), (4, 24, 4)),

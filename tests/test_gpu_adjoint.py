@@ -67,7 +67,8 @@ def test_one_adjoint_step(pname, n, adj):
 
 @pytest.mark.parametrize("kernel", ["plain", "blocked", "blocked_p4w2k5",
                                     "blocked_p8w2k6", "blocked_p8w8k9",
-                                    "plainfwd"])
+                                    "plainfwd", "blocked_s2", "blocked_p4w2k5_s2",
+                                    "blocked_p8w8k9_s2"])
 @pytest.mark.parametrize("pname,n,steps,ckpt", [
     ("paper", 64, 40, 7), ("odd", 300, 33, 33), ("nosource", 97, 25, 1),
     ("linear", 260, 18, 5), ("odd", 1200, 50, 8), ("fluid", 700, 37, 20),
@@ -83,6 +84,11 @@ def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
     tgt = po.rho0 * (1 + 0.03 * np.sin(2 * np.pi * j / n + 1))
     L, rb, Jb, zb, sb = oracle.gradient(rho, J, zeta, steps, tgt, po)
     lat = lbm().Lattice(n, gpu_params(po))
+    if kernel.endswith("_s2"):
+        # keep only the even recomputed states (the reverse kernel
+        # recomputes the odd ones)
+        lat.set_recompute_stride(2)
+        kernel = kernel[:-3]
     if kernel == "plainfwd":
         lat.set_tuning(kernel=lbm().KERNEL_PLAIN)
     elif kernel == "blocked":
@@ -210,7 +216,7 @@ def test_adjoint_config_gradient():
         assert abs(rbar[q] - fd) < 1e-6 * scale
 
 
-@pytest.mark.parametrize("adj", ["plain", "blocked"])
+@pytest.mark.parametrize("adj", ["plain", "blocked", "blocked_s2"])
 def test_batched_adjoint(adj):
     """Per-lattice gradients of a ragged batch against the oracle, lattice by
     lattice (loss 1/2 sum (rho(T) - rho0)^2 per lattice)."""
@@ -220,8 +226,10 @@ def test_batched_adjoint(adj):
     bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
     ps = [oracle_params("paper", s_e=float(s)) for s in bt.s_e]
     b = lbm().Batch(bt.offsets, [gpu_params(p) for p in ps])
-    if adj == "blocked":
+    if adj.startswith("blocked"):
         b.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+    if adj == "blocked_s2":
+        b.set_recompute_stride(2)
     fl = bt.fields
     r_, J_, z_ = T(fl.rho), T(fl.J), T(fl.zeta)
     f = b.equilibrium(r_, J_, z_)
@@ -278,6 +286,91 @@ def test_blocked_reverse_large_batch_matches_one_step_reverse():
     np.testing.assert_allclose(rb, rp, rtol=1e-10, atol=1e-13 * np.abs(rp).max())
     for x, y in zip(gb, gp):
         assert np.abs(x - y).max() <= 1e-11 * np.abs(y).max()
+
+
+def _stride_run(make, stride, steps, ckpt, fields):
+    m = make()
+    m.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+    m.set_recompute_stride(stride)
+    r_, J_, z_ = fields
+    f = m.equilibrium(r_, J_, z_)
+    aws = m.adjoint_workspace(steps, ckpt, dev())
+    m.forward_ckpt(f, steps, ckpt, aws)
+    _, fbar = m.loss(f, None, aws)
+    rbar = m.adjoint(aws, steps, ckpt, fbar, use_graph=False)
+    rbar = rbar.cpu().numpy() if hasattr(rbar, "cpu") else np.asarray(rbar)
+    g = [x.cpu().numpy() for x in m.equilibrium_adjoint(r_, J_, z_, fbar, aws)]
+    return fbar.cpu().numpy(), rbar, g, aws.numel()
+
+
+@pytest.mark.parametrize("pname", ["paper", "linear", "fluid", "nosource"])
+@pytest.mark.parametrize("shape,n,steps,ckpt", [
+    ((2, 16, 1), 3000, 70, 33),     # K even, segments of odd and even length
+    ((4, 5, 2), 2500, 41, 12),      # K odd: recompute launches of 4 steps
+    ((8, 9, 8), 9000, 60, 19),      # odd tops of the reverse launches
+    ((8, 40, 4), 4000, 95, 95),     # one segment, two reverse launches
+    ((4, 7, 4), 100, 30, 30),       # a lattice shorter than one tile
+    ((2, 2, 1), 1000, 9, 4)])       # the smallest K with stride 2
+def test_recompute_stride_is_bitwise(shape, n, steps, ckpt, pname):
+    """Keeping only the even recomputed states (the reverse kernel recomputes
+    each odd one from the state before) gives bitwise the same dL/df(0) and
+    initial-field adjoints as keeping every state; the rate gradients, summed
+    over a different tiling (halo 2K + 2), agree to rounding.  The workspace
+    holds half the segment states."""
+    rng = np.random.default_rng(n + steps)
+    po = oracle_params(pname)
+    j = np.arange(n)
+    fields = (T(po.rho0 * (1 + 0.05 * np.sin(2 * np.pi * j / n)
+                          + 0.01 * rng.standard_normal(n))),
+              T(po.rho0 * po.lam * 0.02 * np.cos(2 * np.pi * j / n)),
+              T(po.rho0 * (po.s0 + 0.02 * po.cp * rng.standard_normal(n))))
+    P, K, W = shape
+
+    def make():
+        lat = lbm().Lattice(n, gpu_params(po))
+        lat.set_tuning(nodes_per_lane=P, steps_per_launch=K, waves_per_group=W)
+        return lat
+
+    say(f"  stride 1 vs 2: {pname} shape {shape} n={n} steps={steps} ckpt={ckpt}")
+    fb1, r1, g1, ws1 = _stride_run(make, 1, steps, ckpt, fields)
+    fb2, r2, g2, ws2 = _stride_run(make, 2, steps, ckpt, fields)
+    assert np.isfinite(fb1).all()
+    assert np.array_equal(fb1, fb2)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+    np.testing.assert_allclose(r2, r1, rtol=1e-12, atol=1e-14 * np.abs(r1).max())
+    if min(ckpt, steps) > 2:
+        assert ws2 < ws1
+
+
+def test_recompute_stride_batch_is_bitwise():
+    """The same for a ragged batch with mixed equilibria, both strides under
+    a captured graph."""
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_batched_adjoint(n_inst=40, steps=50, ckpt=11,
+                                           lmin=60, lmax=3000)
+    bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
+    names = ["paper", "linear", "fluid", "thermal", "odd"]
+    ps = [gpu_params(oracle_params(names[i % len(names)])) for i in range(bt.n_inst)]
+    fl = bt.fields
+    fields = (T(fl.rho), T(fl.J), T(fl.zeta))
+    out = []
+    for stride in (1, 2):
+        b = lbm().Batch(bt.offsets, ps)
+        b.set_tuning(4, 6, 4)
+        b.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+        b.set_recompute_stride(stride)
+        f = b.equilibrium(*fields)
+        aws = b.adjoint_workspace(steps, ckpt, dev())
+        b.forward_ckpt(f, steps, ckpt, aws)
+        _, fbar = b.loss(f, None, aws)
+        rbar = b.adjoint(aws, steps, ckpt, fbar).cpu().numpy()
+        out.append((fbar.cpu().numpy(), rbar))
+        del aws, b
+    assert np.isfinite(out[0][0]).all()
+    assert np.array_equal(out[0][0], out[1][0])
+    np.testing.assert_allclose(out[1][1], out[0][1], rtol=1e-12,
+                               atol=1e-14 * np.abs(out[0][1]).max())
 
 
 def test_autograd_function():
