@@ -246,10 +246,10 @@ LBM_API int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
                                 void* ws, size_t ws_bytes);
 /* Kernel of the reverse sweep.  LBM_KERNEL_BLOCKED keeps dL/df in registers
  * for up to K reverse steps of a tile of 64 P W nodes (P = 2 with W the
- * forward's wavefronts, or P W / 2 for P = 4, 8, at most 8; halo 2K), reading
- * only the recomputed forward states, the next step's prefetched while the
- * current one computes (about 2.4x the arithmetic of a forward step per
- * node-step).  LBM_KERNEL_PLAIN runs one reverse step per launch, one node
+ * forward's wavefronts, or P W / 2 for P = 4, 8, at most 8; halo 2K, or
+ * 2K + 2 at recompute stride 2), reading only the stored recomputed forward
+ * states, the next one prefetched while the current step computes (about
+ * 2.4x the arithmetic of a forward step per node-step).  LBM_KERNEL_PLAIN runs one reverse step per launch, one node
  * per thread (HBM-bound, 144 B per node-step).  LBM_KERNEL_AUTO (the
  * default) takes the blocked kernel wherever its tiles can hold the halo,
  * else the one-step kernel.  A halo too wide for P = 2 tiles (4K >= 128 W)
