@@ -254,6 +254,57 @@ def test_batched_adjoint(adj):
         np.testing.assert_allclose(rbar[i], sb, rtol=1e-9, atol=1e-12 * np.abs(sb).max())
 
 
+def test_batched_adjoint_config_sampled():
+    """The batched-gradient workload in the configuration the benchmark
+    times (1024 lattices, lengths in [1024, 8192], 4000 steps, checkpoints
+    every 63, default tile shape, automatic reverse kernel and recompute
+    stride, captured graph): loss, rate gradients and dL/drho(0) of four
+    seeded lattices (among the shorter ones, for the oracle's time) against
+    the oracle's adjoint of each lattice alone."""
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_batched_adjoint()
+    bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
+    say(f"batched adjoint config: {bt.n_inst} lattices, {bt.offsets[-1]} nodes, "
+        f"{steps} steps, checkpoints every {ckpt}")
+    ps = []
+    for s_e in bt.s_e:
+        s_psi, s_eps, _ = lbm().coupled_rates(float(s_e))
+        ps.append(oracle_params("paper", s_e=float(s_e), s_psi=s_psi, s_eps=s_eps))
+    b = lbm().Batch(bt.offsets, [gpu_params(p) for p in ps])
+    fl = bt.fields
+    r_, J_, z_ = T(fl.rho), T(fl.J), T(fl.zeta)
+    f = b.equilibrium(r_, J_, z_)
+    aws = b.adjoint_workspace(steps, ckpt, dev())
+    b.forward_ckpt(f, steps, ckpt, aws)
+    loss, fbar = b.loss(f, None, aws)
+    rbar = b.adjoint(aws, steps, ckpt, fbar).cpu().numpy()
+    g_rho = b.equilibrium_adjoint(r_, J_, z_, fbar, aws)[0].cpu().numpy()
+    loss = loss.cpu().numpy()
+    del aws
+    rng = np.random.default_rng(1024)
+    short = np.flatnonzero(np.asarray(bt.lengths) <= 1300)
+    sub = np.sort(rng.choice(short, 4, replace=False))
+    say(f"  oracle adjoint of lattices {[int(i) for i in sub]} "
+        f"(lengths {[int(n) for n in bt.lengths[sub]]})")
+
+    def one(i):
+        a, c = bt.offsets[i], bt.offsets[i + 1]
+        x = bt.instance(i)
+        return oracle.gradient(x.rho, x.J, x.zeta, steps, np.full(c - a, ps[i].rho0),
+                               ps[i])
+
+    with ThreadPoolExecutor(4) as ex:
+        res = list(ex.map(one, sub))
+    for i, (L, rb, Jb, zb, sb) in zip(sub, res):
+        a, c = bt.offsets[i], bt.offsets[i + 1]
+        err = np.abs(g_rho[a:c] - rb).max() / np.abs(rb).max()
+        say(f"  lattice {i}: loss rel {rel(loss[i], L):.1e}, dL/drho(0) {err:.1e}, "
+            f"rates {np.abs(rbar[i] - sb).max() / np.abs(sb).max():.1e}")
+        assert rel(loss[i], L) < 1e-10, i
+        assert err <= 1e-10, i
+        np.testing.assert_allclose(rbar[i], sb, rtol=1e-9, atol=1e-12 * np.abs(sb).max())
+
+
 def test_blocked_reverse_large_batch_matches_one_step_reverse():
     """A batch large enough for the blocked reverse sweep to run on one
     stream (its launches fill the chip: 256 lattices, 2.06M nodes): the
