@@ -1024,6 +1024,8 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
   // recompute of segment k on stream st: up to Krec states per launch, each
   // launch starting from a stored state (an even one at E = 2)
   const int Kst = E == 2 ? Krec & ~1 : Krec;
+  if (Kst < 1)  // resolve_every gives E = 2 only for K >= 2
+    return set_err(LBM_EINVAL, "recompute stride %d with K = %d", E, Krec);
   auto recompute = [&](int64_t k, hipStream_t st) -> int {
     const int64_t len = seg_len(k);
     for (int64_t i0 = 0; i0 + 1 < len; i0 += Kst) {
