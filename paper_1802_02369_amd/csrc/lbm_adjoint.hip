@@ -646,10 +646,7 @@ int launch_adjoint_tile(int P, int WG, int E, const Consts* cs,
   LBM_ADJ_CASE(2, 2, 2)
   LBM_ADJ_CASE(2, 4, 2)
   LBM_ADJ_CASE(2, 8, 2)
-  LBM_ADJ_CASE(4, 1, 1)
-  LBM_ADJ_CASE(4, 2, 1)
-  LBM_ADJ_CASE(4, 4, 1)
-  LBM_ADJ_CASE(4, 8, 1)
+  LBM_ADJ_CASE(4, 8, 1)  // the only P = 4 shape rev_shape gives
 #undef LBM_ADJ_CASE
   return set_err(LBM_EINVAL,
                  "unsupported adjoint tile shape P=%d waves=%d stride=%d", P,
