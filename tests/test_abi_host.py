@@ -223,6 +223,28 @@ def test_recompute_stride_host():
     L.lbm_destroy(h)
 
 
+@pytest.mark.parametrize("n_inst,Ln,auto", [(256, 8000, 2), (4, 1000, 1)])
+def test_recompute_stride_automatic_host(n_inst, Ln, auto):
+    """The automatic recompute stride is 2 where the blocked reverse
+    launches fill the chip (256 lattices of 8000 nodes at P2/W8: about
+    17000 wavefronts) and 1 on a small batch (launch-bound, pipelined)."""
+    L = lbm.lib()
+    offs = (ctypes.c_int64 * (n_inst + 1))(*[i * Ln for i in range(n_inst + 1)])
+    p = lbm.Params(s_psi=1.0).c()
+    ps = (type(p) * n_inst)(*([p] * n_inst))
+    b = ctypes.c_void_p()
+    assert L.lbm_batch_init(ctypes.byref(b), n_inst, offs, ps, None) == lbm.LBM_OK
+    t = lbm.CTuning(lbm.KERNEL_BLOCKED, 4, 16, 4)
+    assert L.lbm_batch_set_tuning(b, ctypes.byref(t)) == lbm.LBM_OK
+    ws = {}
+    for stride in (1, 2, 0):
+        assert L.lbm_batch_set_recompute_stride(b, stride) == lbm.LBM_OK
+        ws[stride] = L.lbm_batch_adjoint_workspace_bytes(b, 200, 50)
+    assert ws[2] < ws[1]
+    assert ws[0] == ws[auto]
+    L.lbm_batch_destroy(b)
+
+
 @pytest.mark.parametrize("kw,shape", [
     (dict(), (8, 40, 4)),
     (dict(eq_kind=1), (4, 24, 4)),

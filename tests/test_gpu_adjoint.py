@@ -361,7 +361,10 @@ def _stride_run(make, stride, steps, ckpt, fields):
     ((8, 9, 8), 9000, 60, 19),      # odd tops of the reverse launches
     ((8, 40, 4), 4000, 95, 95),     # one segment, two reverse launches
     ((4, 7, 4), 100, 30, 30),       # a lattice shorter than one tile
-    ((2, 2, 1), 1000, 9, 4)])       # the smallest K with stride 2
+    ((2, 2, 1), 1000, 9, 4),        # the smallest K with stride 2
+    ((2, 16, 1), 500, 1, 1),        # one step: no segment states at all
+    ((4, 5, 2), 700, 2, 5),         # one segment of two steps
+    ((8, 9, 8), 3000, 3, 2)])       # segments of two steps and one
 def test_recompute_stride_is_bitwise(shape, n, steps, ckpt, pname):
     """Keeping only the even recomputed states (the reverse kernel recomputes
     each odd one from the state before) gives bitwise the same dL/df(0) and
