@@ -20,7 +20,10 @@
 // k_adjoint_step, one step per launch, one thread per node, 256-node tiles
 // whose 252 interior nodes are stored, u, T and the gathered terms through
 // LDS; and k_adjoint_tile, up to K steps per launch on a register tile (the
-// default where its tiles hold the halo; see below).  Rate partials are
+// default where its tiles hold the halo; see below), which on large problems
+// loads every second forward state and recomputes the others.  The sweep
+// recomputes each checkpoint segment's states before its reverse steps
+// (enqueue_adjoint).  Rate partials are
 // summed per tile into a per-tile slot (same workgroup, launches in order:
 // deterministic) and reduced per lattice in tile order at the end.
 #include <hip/hip_runtime.h>
@@ -237,9 +240,11 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
 // ------------------------------------------------ register-tile adjoint --
 //
 // K reverse steps of a tile of 64*P*WG nodes per launch (halo H = 2K on
-// each side, K the forward's steps per launch; its own tile table).  fbar
-// stays in registers; each step takes the forward state f(t) of the tile
-// (coalesced loads issued during the previous step, through LDS) and does:
+// each side, or 2K + 2 when only every second forward state is stored, K
+// the forward's steps per launch; its own tile table).  fbar stays in
+// registers; each step takes the forward state f(t) of the tile (coalesced
+// loads issued during the previous step, through LDS, or recomputed from
+// the stored state before: see k_adjoint_tile) and does:
 //   A  u, T (and rho, s, X) of every node from f(t);
 //   -  streamed adjoint: fbar*_+(k) = fbar_+(k+1), fbar*_-(k) = fbar_-(k-1),
 //      with u, T of the outside neighbours (DPP, LDS between wavefronts);
