@@ -234,7 +234,7 @@ def bench_adjoint(torch, lbm, workloads, stream):
     log(f"bench: adjoint {g:.3f} G node-steps/s ({ms:.1f} ms per gradient)")
     return {"value": g, "unit": "G forward node-steps/s (whole gradient)",
             "n_nodes": n, "time_steps": steps, "ckpt_every": ck,
-            "ms_per_gradient": ms}
+            "ms_per_gradient": ms, "workspace_gb": aws.numel() * 8 / 1e9}
 
 
 def bench_batched_adjoint(torch, lbm, workloads, stream):
@@ -265,10 +265,11 @@ def bench_batched_adjoint(torch, lbm, workloads, stream):
     ms = time_runs(grad, lambda: None, 1, torch, stream)
     g = b.n_total * steps / (ms * 1e-3) / 1e9
     log(f"bench: batched adjoint {g:.3f} G node-steps/s ({ms:.1f} ms)")
+    ws_gb = aws.numel() * 8 / 1e9
     del aws
     return {"value": g, "unit": "G forward node-steps/s (whole gradient)",
             "n_inst": bt.n_inst, "n_nodes": b.n_total, "time_steps": steps,
-            "ckpt_every": ck, "ms_per_gradient": ms}
+            "ckpt_every": ck, "ms_per_gradient": ms, "workspace_gb": ws_gb}
 
 
 def main():
