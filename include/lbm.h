@@ -138,17 +138,20 @@ enum {
  * handle). */
 LBM_API size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
 
-/* Kernel selection.  lbm_set_tuning validates the shape (P in {2,4,8},
- * waves_per_group W in {1,2,4,8}, 1 <= K, 4K < P (62 W + 2)).
+/* Kernel selection.  lbm_set_tuning validates the shape (P in {1,2,4,8},
+ * waves_per_group W in {1,2,4,8}, W = 1 when P = 1, 1 <= K,
+ * 4K < P (62 W + 2), i.e. K <= 15 at P = 1).
  * The blocked kernel gives each workgroup of W wavefronts a tile of
  * P (62 W + 2) nodes held in registers for K steps (64 P per wavefront,
- * neighbouring wavefronts sharing two lanes) and stores its interior of
- * P (62 W + 2) - 4K nodes.  The
+ * neighbouring wavefronts sharing two lanes; 64 nodes at P = 1) and stores
+ * its interior of P (62 W + 2) - 4K nodes.  The
  * default depends on the lattice length and the equilibria: for eq_kind 0,
  * P = 8, K = 40, 4 wavefronts for long lattices; for eq_kind 1 or 2 (kernels
  * that select the equilibria per lattice and need more registers at P = 8)
  * P = 4, K = 24, 4 wavefronts; narrower tiles for short lattices or few
- * tiles.  lbm_set_params re-derives the default unless lbm_set_tuning or
+ * tiles, down to P = 1, K = 12 for problems of at most 16384 nodes in all
+ * (bound by the latency of each step rather than by throughput).
+ * lbm_set_params re-derives the default unless lbm_set_tuning or
  * lbm_autotune chose the shape.  Every
  * kernel and tile shape rounds each node-update identically: results are
  * bitwise independent of the tuning. */
@@ -246,11 +249,12 @@ LBM_API int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
                                 void* ws, size_t ws_bytes);
 /* Kernel of the reverse sweep.  LBM_KERNEL_BLOCKED keeps dL/df in registers
  * for up to K reverse steps of a tile of 64 P W nodes (P = 2 with W the
- * forward's wavefronts, or P W / 2 for P = 4, 8, at most 8; halo 2K, or
- * 2K + 2 at recompute stride 2), reading only the stored recomputed forward
- * states, the next one prefetched while the current step computes (about
- * 2.4x the arithmetic of a forward step per node-step).  LBM_KERNEL_PLAIN runs one reverse step per launch, one node
- * per thread (HBM-bound, 144 B per node-step).  LBM_KERNEL_AUTO (the
+ * forward's wavefronts, or P W / 2 for P = 4, 8, at most 8; P = 1, W = 1
+ * after a forward at P = 1; halo 2K, or 2K + 2 at recompute stride 2),
+ * reading only the stored recomputed forward states, the next one
+ * prefetched while the current step computes (about 2.4x the arithmetic of
+ * a forward step per node-step).  LBM_KERNEL_PLAIN runs one reverse step
+ * per launch, one node per thread (HBM-bound, 144 B per node-step).  LBM_KERNEL_AUTO (the
  * default) takes the blocked kernel wherever its tiles can hold the halo,
  * else the one-step kernel.  A halo too wide for P = 2 tiles (4K >= 128 W)
  * falls back to P = 4 with 8 wavefronts; lbm_forward_ckpt rejects with

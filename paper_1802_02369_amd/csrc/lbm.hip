@@ -313,6 +313,23 @@ __global__ __launch_bounds__(kPlainBlock + 64) void k_step_plain(
 // of three nodes' (u, T) stays live besides the populations.
 template <int P, int EQ>
 __device__ __forceinline__ void tile_step(const Consts& c, double (&f)[6][P]) {
+  if constexpr (P == 1) {
+    // one node per lane: both neighbours are the adjacent lanes
+    double u, T, rw, w;
+    lbm::collide_local<EQ>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0],
+                           f[5][0], u, T, rw, w);
+    const double add =
+        lbm::source_g(c, rw, w, lbm::from_left(u), lbm::from_right(u),
+                      lbm::from_left(T), lbm::from_right(T));
+    f[3][0] += add;
+    f[4][0] += add;
+    f[5][0] += add;
+    f[1][0] = lbm::from_left(f[1][0]);
+    f[4][0] = lbm::from_left(f[4][0]);
+    f[2][0] = lbm::from_right(f[2][0]);
+    f[5][0] = lbm::from_right(f[5][0]);
+    return;
+  }
   double uA, TA, rwA, wA;  // node P-1, collided first
   lbm::collide_local<EQ>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
                      f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
@@ -430,6 +447,8 @@ __device__ __forceinline__ void tile_run(const Consts& c,
                                          int K, bool every_step = false,
                                          int64_t state_stride = 0,
                                          int first = 0, int every = 1) {
+  // one node per lane leaves no room for mirror lanes: one wavefront
+  static_assert(P > 1 || WG == 1, "P = 1 tiles have one wavefront");
   constexpr int WW = 64 * P;       // nodes of one wavefront
   constexpr int WS = 62 * P;       // wavefront stride in the tile
   __shared__ double stage[WG * (WW + 64)];
@@ -469,10 +488,11 @@ __device__ __forceinline__ void tile_run(const Consts& c,
 // for three (the few values that spill are touched only around the step
 // loop, which measured 297 -> 312 GLUPS at N = 2^24 against two); with 8
 // wavefronts per workgroup a CU gains no third one, so those stay at two.
-// The kernels that select the equilibria per lattice, or store every step,
-// need more registers at P >= 4 and take one.
+// The kernels that select the equilibria per lattice, or store the states
+// of a reverse sweep, need more registers at P >= 4 and take one.  P <= 2
+// needs few registers: four.
 constexpr int tile_waves_per_simd(int P, int WG, bool sec8_plain) {
-  return P == 2 ? 4 : (!sec8_plain ? 1 : (P == 8 && WG <= 4 ? 3 : 2));
+  return P <= 2 ? 4 : (!sec8_plain ? 1 : (P == 8 && WG <= 4 ? 3 : 2));
 }
 
 template <int P, int WG, int EQ>
@@ -703,10 +723,15 @@ int launch_step_tile(const Consts& c, const double* fin, double* fout,
                      int64_t n, int P, int K, int wpg, hipStream_t s) {
   int rc;
   switch (P) {
+    case 1:
+      if (wpg != 1) return set_err(LBM_EINVAL, "nodes_per_lane 1 needs one wavefront");
+      launch_tile_t<1, 1>(c, fin, fout, n, K, s);
+      rc = LBM_OK;
+      break;
     case 2: rc = launch_tile_p<2>(c, fin, fout, n, K, wpg, s); break;
     case 4: rc = launch_tile_p<4>(c, fin, fout, n, K, wpg, s); break;
     case 8: rc = launch_tile_p<8>(c, fin, fout, n, K, wpg, s); break;
-    default: return set_err(LBM_EINVAL, "nodes_per_lane must be 2, 4 or 8");
+    default: return set_err(LBM_EINVAL, "nodes_per_lane must be 1, 2, 4 or 8");
   }
   if (rc) return rc;
   return hip_check(hipGetLastError(), "k_step_tile");
@@ -774,6 +799,7 @@ int launch_batch_tile(const Consts* cs, const int64_t* offs,
                            state_stride, first, every, eq, s);              \
     return hip_check(hipGetLastError(), "k_batch_tile");                    \
   }
+  LBM_BATCH_CASE(1, 1)
   LBM_BATCH_CASE(2, 1)
   LBM_BATCH_CASE(2, 2)
   LBM_BATCH_CASE(2, 4)

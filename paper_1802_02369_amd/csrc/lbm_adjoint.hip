@@ -643,6 +643,7 @@ int launch_adjoint_tile(int P, int WG, int E, const Consts* cs,
                                       i_lo, i_hi, fbn, fbo, S, H, rslots, s); \
     return hip_check(hipGetLastError(), "k_adjoint_tile");                    \
   }
+  LBM_ADJ_CASE(1, 1, 1)
   LBM_ADJ_CASE(2, 1, 1)
   LBM_ADJ_CASE(2, 2, 1)
   LBM_ADJ_CASE(2, 4, 1)
@@ -792,6 +793,9 @@ struct RevShape {
 
 RevShape rev_shape(const lbm_tuning& t, int E) {
   const int K = t.steps_per_launch;
+  // one node per lane (small lattices, bound by each step's latency): the
+  // same for the reverse, whose halo the forward's K already fits
+  if (t.nodes_per_lane == 1) return RevShape{1, 1, 2 * K, 1};
   RevShape r{2, std::min(8, std::max(t.waves_per_group,
                                      t.nodes_per_lane * t.waves_per_group / 2)),
              2 * K + (E == 2 ? 2 : 0), E};

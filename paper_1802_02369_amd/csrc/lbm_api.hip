@@ -18,11 +18,13 @@ int check_tuning(const lbm_tuning* t) {
     return set_err(LBM_EINVAL, "unknown kernel %d", t->kernel);
   if (t->kernel == LBM_KERNEL_PLAIN) return LBM_OK;
   const int P = t->nodes_per_lane, K = t->steps_per_launch;
-  if (P != 2 && P != 4 && P != 8)
-    return set_err(LBM_EINVAL, "nodes_per_lane must be 2, 4 or 8 (got %d)", P);
+  if (P != 1 && P != 2 && P != 4 && P != 8)
+    return set_err(LBM_EINVAL, "nodes_per_lane must be 1, 2, 4 or 8 (got %d)", P);
   const int w = t->waves_per_group;
   if (w != 1 && w != 2 && w != 4 && w != 8)
     return set_err(LBM_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+  if (P == 1 && w != 1)
+    return set_err(LBM_EINVAL, "nodes_per_lane 1 needs waves_per_group 1");
   if (K < 1 || 4 * K >= tile_nodes(P, w))
     return set_err(LBM_EINVAL,
                    "steps_per_launch must satisfy 1 <= K < P (62 "
@@ -56,9 +58,13 @@ lbm_tuning default_tuning(int64_t len, int64_t total, int eq) {
   // each.  The kernels that select the equilibria per lattice (eq != 0)
   // need over 256 VGPRs at P = 8, i.e. one wavefront per SIMD, so they
   // start at P = 4.
-  // Small lattices are bound by launch latency, so their one-wavefront tile
-  // takes K = 16 (fewer launches) rather than the width's best; at
-  // n = 8192 to 131072 it beats every other shape.
+  // Small problems are bound by the latency of each step's chain of
+  // arithmetic, not by throughput: their one-wavefront tiles take K = 16
+  // (fewer launches) rather than the width's best, and at most 16384 nodes
+  // in all one node per lane (half the chain per step, four times the
+  // lane-nodes, on a chip that is mostly idle anyway): measured 2.5 -> 3.5
+  // GLUPS at n = 2048 and 10.0 -> 13.7 at 8192, even at 32768 and behind
+  // P = 2 above.
   static const lbm_tuning shapes[] = {
       {LBM_KERNEL_BLOCKED, 8, 40, 4}, {LBM_KERNEL_BLOCKED, 4, 24, 4},
       {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 16, 1}};
@@ -68,6 +74,7 @@ lbm_tuning default_tuning(int64_t len, int64_t total, int eq) {
     const int64_t width = tile_width(t), out = width - 4 * t.steps_per_launch;
     if (4 * width <= len && total >= 1024 * out) return t;
   }
+  if (total <= 16384) return lbm_tuning{LBM_KERNEL_BLOCKED, 1, 12, 1};
   return shapes[count - 1];
 }
 

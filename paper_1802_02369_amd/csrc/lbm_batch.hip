@@ -357,7 +357,7 @@ int apply_groups(lbm_batch* b, const std::vector<lbm_tuning>& gshape,
 
 // Generation of the tile kernels, the last component of every tuning-cache
 // key: entries measured on kernels of another generation are not reused.
-constexpr const char* kKernelGeneration = "/k5";
+constexpr const char* kKernelGeneration = "/k6";
 
 // Times `run(t)` for each candidate on the state f, restoring f from
 // `backup` before each run and at the end; returns the fastest, and every
@@ -441,6 +441,12 @@ int lbm_autotune(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
   if (!tune_cache_get(cache_path, key, &best)) {
     std::vector<lbm_tuning> cands = tuning_candidates();
     cands.push_back(lbm_tuning{LBM_KERNEL_PLAIN, 0, 1, 1});
+    // the default shape (one wavefront, or one node per lane, on small
+    // lattices) is not among the throughput candidates
+    const lbm_tuning d = default_tuning(h->n, h->n, h->p.eq_kind == 0 ? 0 : -1);
+    if (std::none_of(cands.begin(), cands.end(),
+                     [&](const lbm_tuning& c) { return same_tuning(c, d); }))
+      cands.push_back(d);
     double* backup = static_cast<double*>(ws) + 6 * h->n + diag_ws_doubles();
     const size_t step_ws = lbm_workspace_bytes(h, LBM_WS_STEP);
     const lbm_tuning prev = h->tune;

@@ -107,8 +107,9 @@ def test_init_and_workspace_and_tuning_host():
     (1 << 21, (8, 40, 4)),
     (1 << 20, (4, 24, 4)),   # too few P = 8 tiles for 4 workgroups per CU
     (1 << 19, (2, 16, 4)),
-    (8192, (2, 16, 1)),      # small lattices: the narrowest tile, K = 16
-    (3, (2, 16, 1))])
+    (40000, (2, 16, 1)),     # small lattices: the narrowest tile, K = 16
+    (8192, (1, 12, 1)),      # up to 16384 nodes: one node per lane
+    (3, (1, 12, 1))])
 def test_default_tuning_follows_lattice_length(n, shape):
     rc, h = _init(n)
     assert rc == lbm.LBM_OK
@@ -188,6 +189,18 @@ def test_blocked_adjoint_shape_check_host(shape, ok):
                                 ctypes.c_void_p(1 << 40), nb, 10, 5)
         assert rc == lbm.LBM_ENOTSUP
         assert b"halo" in L.lbm_last_error()
+    L.lbm_destroy(h)
+
+
+def test_one_node_per_lane_needs_one_wavefront_host():
+    rc, h = _init(1000)
+    assert rc == lbm.LBM_OK
+    L = lbm.lib()
+    for P, K, W, ok in [(1, 12, 1, True), (1, 15, 1, True), (1, 16, 1, False),
+                        (1, 4, 2, False), (3, 4, 1, False)]:
+        t = lbm.CTuning(lbm.KERNEL_BLOCKED, P, K, W)
+        rc = L.lbm_set_tuning(h, ctypes.byref(t))
+        assert (rc == lbm.LBM_OK) == ok, (P, K, W)
     L.lbm_destroy(h)
 
 

@@ -68,7 +68,8 @@ def test_one_adjoint_step(pname, n, adj):
 @pytest.mark.parametrize("kernel", ["plain", "blocked", "blocked_p4w2k5",
                                     "blocked_p8w2k6", "blocked_p8w8k9",
                                     "plainfwd", "blocked_s2", "blocked_p4w2k5_s2",
-                                    "blocked_p8w8k9_s2"])
+                                    "blocked_p8w8k9_s2", "blocked_p2w1k16",
+                                    "blocked_p1w1k7"])
 @pytest.mark.parametrize("pname,n,steps,ckpt", [
     ("paper", 64, 40, 7), ("odd", 300, 33, 33), ("nosource", 97, 25, 1),
     ("linear", 260, 18, 5), ("odd", 1200, 50, 8), ("fluid", 700, 37, 20),
@@ -102,6 +103,12 @@ def test_checkpointed_gradient(pname, n, steps, ckpt, kernel):
     elif kernel == "blocked_p8w8k9":
         lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
         lat.set_tuning(nodes_per_lane=8, steps_per_launch=9, waves_per_group=8)
+    elif kernel == "blocked_p2w1k16":
+        lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+        lat.set_tuning(nodes_per_lane=2, steps_per_launch=16, waves_per_group=1)
+    elif kernel == "blocked_p1w1k7":
+        lat.set_adjoint_kernel(lbm().KERNEL_BLOCKED)
+        lat.set_tuning(nodes_per_lane=1, steps_per_launch=7, waves_per_group=1)
     aws = lat.adjoint_workspace(steps, ckpt, dev())
     r_, J_, z_ = T(rho), T(J), T(zeta)
     f = lat.equilibrium(r_, J_, z_)

@@ -49,7 +49,7 @@ def oracle_runs(states, params, steps, workers=16):
 
 RAGGED = [3, 5, 64, 100, 513, 1000, 2049, 7]
 PNAMES = ["paper", "odd", "nosource", "linear", "odd", "paper", "odd", "nosource"]
-SHAPES = [(2, 8, 4), (4, 5, 2), (2, 16, 8), (2, 1, 1), (8, 12, 2), (8, 32, 4)]
+SHAPES = [(2, 8, 4), (4, 5, 2), (2, 16, 8), (2, 1, 1), (8, 12, 2), (8, 32, 4), (1, 12, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)

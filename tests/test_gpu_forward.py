@@ -43,6 +43,8 @@ TUNINGS = {
     "p4k15w4": dict(kernel=2, nodes_per_lane=4, steps_per_launch=15, waves_per_group=4),
     "p8k32w4": dict(kernel=2, nodes_per_lane=8, steps_per_launch=32, waves_per_group=4),
     "p8k7w1": dict(kernel=2, nodes_per_lane=8, steps_per_launch=7, waves_per_group=1),
+    "p1k12w1": dict(kernel=2, nodes_per_lane=1, steps_per_launch=12, waves_per_group=1),
+    "p1k5w1": dict(kernel=2, nodes_per_lane=1, steps_per_launch=5, waves_per_group=1),
 }
 
 
@@ -154,7 +156,7 @@ def test_results_independent_of_tuning(pname):
     outs = {}
     # K not a multiple of the mirror-lane refresh period P/2 as well
     for name in list(TUNINGS) + ["p8k20w8", "p8k60w2", "p8k9w4", "p8k13w8",
-                                 "p4k6w8"]:
+                                 "p4k6w8", "p1k15w1"]:
         lat = lbm().Lattice(n, gpu_params(po))
         if name in TUNINGS:
             lat.set_tuning(**{"nodes_per_lane": 2, "steps_per_launch": 8,
