@@ -292,11 +292,23 @@ namespace {
 
 int log2_class(double x) { return x > 1 ? (int)std::lround(std::log2(x)) : 0; }
 
+// The batch autotuner's shapes: the throughput candidates and the batch's
+// default shape (one wavefront, or one node per lane, on small problems).
+std::vector<lbm_tuning> batch_candidates(const lbm_batch* b) {
+  std::vector<lbm_tuning> v = tuning_candidates();
+  const lbm_tuning d =
+      default_tuning(b->n_total / b->n_inst, b->n_total, b->eq_class());
+  if (std::none_of(v.begin(), v.end(),
+                   [&](const lbm_tuning& c) { return same_tuning(c, d); }))
+    v.push_back(d);
+  return v;
+}
+
 // Tile-table size the autotuner may need: any grouping of the candidates,
 // i.e. each lattice at its largest tile count, and the current settings.
 int64_t tune_tiles(const lbm_batch* b) {
   int64_t mx = 0;
-  const std::vector<lbm_tuning> cands = tuning_candidates();
+  const std::vector<lbm_tuning> cands = batch_candidates(b);
   for (int64_t i = 0; i < b->n_inst; ++i) {
     int64_t m = 0;
     for (const lbm_tuning& t : cands) m = std::max(m, b->lattice_tiles(i, t));
@@ -769,7 +781,7 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   std::vector<lbm_tuning> gshape;
   std::vector<double> gcost;
   if (!tune_cache_get(cache_path, key, &best, &gshape, &gcost)) {
-    const std::vector<lbm_tuning> cands = tuning_candidates();
+    const std::vector<lbm_tuning> cands = batch_candidates(b);
     double* backup = at<double>(ws, layout(b, tune_tiles(b), true).backup);
     const size_t sbytes = sizeof(double) * 6 * (size_t)b->n_total;
     // a failed search leaves the tuning and the groups as they were
