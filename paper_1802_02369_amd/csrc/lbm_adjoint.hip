@@ -786,7 +786,7 @@ lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
 // that give about the forward tile's width (at least the forward's, at most
 // 8); a halo too wide for those tiles falls back to P = 4 with 8 wavefronts
 // and E = 1.  A forward of one node per lane (small problems) keeps P = 1,
-// W = 1, E = 1 (121 VGPRs).
+// W = 1, E = 1 (about 120 VGPRs).
 struct RevShape {
   int P, W, H, E;
   int64_t out() const { return 64 * (int64_t)P * W - 2 * (int64_t)H; }
