@@ -249,7 +249,7 @@ LBM_API int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
                                 void* ws, size_t ws_bytes);
 /* Kernel of the reverse sweep.  LBM_KERNEL_BLOCKED keeps dL/df in registers
  * for up to K reverse steps of a tile of 64 P W nodes (P = 2 with W the
- * forward's wavefronts, or P W / 2 for P = 4, 8, at most 8; P = 1, W = 1
+ * forward's wavefronts, or P W / 2 for P = 4, 8, at most 4; P = 1, W = 1
  * after a forward at P = 1; halo 2K, or 2K + 2 at recompute stride 2),
  * reading only the stored recomputed forward states, the next one
  * prefetched while the current step computes (about 2.4x the arithmetic of

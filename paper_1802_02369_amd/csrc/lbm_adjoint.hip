@@ -783,9 +783,11 @@ lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
 // between wavefronts) with halo H = 2K, or 2K + 2 at E = 2 (see
 // k_adjoint_tile).  P = 2 keeps two wavefronts per SIMD (the reverse step
 // needs about 220 VGPRs at P = 2, over 256 at P = 4), with the wavefronts
-// that give about the forward tile's width (at least the forward's, at most
-// 8); a halo too wide for those tiles falls back to P = 4 with 8 wavefronts
-// and E = 1.  A forward of one node per lane (small problems) keeps P = 1,
+// that give about the forward tile's width, at least the forward's and at
+// most 4: two workgroups per CU, so that one computes while the other waits
+// at the step's barriers (the 1024-lattice gradient's reverse phase took
+// 442 ms at 4 wavefronts, 472 at 8, 512 at 2); a halo too wide for those
+// tiles falls back to P = 4 with 8 wavefronts and E = 1.  A forward of one node per lane (small problems) keeps P = 1,
 // W = 1, E = 1 (about 120 VGPRs).
 struct RevShape {
   int P, W, H, E;
@@ -797,7 +799,7 @@ RevShape rev_shape(const lbm_tuning& t, int E) {
   // one node per lane (small lattices, bound by each step's latency): the
   // same for the reverse, whose halo the forward's K already fits
   if (t.nodes_per_lane == 1) return RevShape{1, 1, 2 * K, 1};
-  RevShape r{2, std::min(8, std::max(t.waves_per_group,
+  RevShape r{2, std::min(4, std::max(t.waves_per_group,
                                      t.nodes_per_lane * t.waves_per_group / 2)),
              2 * K + (E == 2 ? 2 : 0), E};
   if (2 * r.H >= 64 * 2 * r.W) r = RevShape{4, 8, 2 * K, 1};
