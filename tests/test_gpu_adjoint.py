@@ -369,6 +369,7 @@ def _stride_run(make, stride, steps, ckpt, fields):
     ((8, 40, 4), 4000, 95, 95),     # one segment, two reverse launches
     ((4, 7, 4), 100, 30, 30),       # a lattice shorter than one tile
     ((2, 2, 1), 1000, 9, 4),        # the smallest K with stride 2
+    ((2, 6, 2), 2000, 30, 11),      # two-wavefront reverse tiles
     ((2, 16, 1), 500, 1, 1),        # one step: no segment states at all
     ((4, 5, 2), 700, 2, 5),         # one segment of two steps
     ((8, 9, 8), 3000, 3, 2)])       # segments of two steps and one
