@@ -161,7 +161,9 @@ int make_consts(const lbm_params* p, Consts* c) {
 
 namespace {
 
-constexpr int kPlainBlock = 256;
+// nodes per block of the one-step kernel: 15 wavefronts and one more for the
+// halo (960 against 256 nodes per block: 60.7 -> 61.4 GLUPS at N = 2^24)
+constexpr int kPlainBlock = 960;
 constexpr int kDiagBlock = 256;
 constexpr int kDiagMaxBlocks = 1024;
 
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(256) void k_moments(Consts c,
 // One time step, one node per thread.  Block b stores nodes
 // [b*B, b*B + B) (B = kPlainBlock), each thread its own node with aligned
 // stores: the streamed values f+(j) = f+*(j-1) and f-(j) = f-*(j+1) come
-// through LDS.  A fifth wavefront handles the four halo nodes: b*B - 1 and
+// through LDS.  One more wavefront handles the four halo nodes: b*B - 1 and
 // b*B + B are collided too (their f+* and f-* stream into the block), and
 // b*B - 2, b*B + B + 1 give u, T for those two nodes' sources.  LDS slot s
 // holds node b*B - 2 + s.  NT: non-temporal loads and stores, for states far

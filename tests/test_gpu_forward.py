@@ -125,7 +125,7 @@ def test_step_broad_thermodynamic_range(pname, tuning):
 
 
 @pytest.mark.parametrize("tuning", list(TUNINGS))
-@pytest.mark.parametrize("n", [3, 4, 5, 63, 64, 65, 255, 257, 1000, 4099, 20011])
+@pytest.mark.parametrize("n", [3, 4, 5, 63, 64, 65, 255, 257, 961, 1000, 1921, 4099, 20011])
 def test_one_step(tuning, n):
     rng = np.random.default_rng(n)
     for pname in ("paper", "odd", "nosource", "linear", "fluid", "thermal",
