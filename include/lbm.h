@@ -149,7 +149,7 @@ LBM_API size_t lbm_workspace_bytes(const lbm_handle* h, int kind);
  * P = 8, K = 40, 4 wavefronts for long lattices; for eq_kind 1 or 2 (kernels
  * that select the equilibria per lattice and need more registers at P = 8)
  * P = 4, K = 24, 4 wavefronts; narrower tiles for short lattices or few
- * tiles, down to P = 1, K = 12 for problems of at most 16384 nodes in all
+ * tiles, down to P = 1, K = 13 for problems of at most 16384 nodes in all
  * (bound by the latency of each step rather than by throughput).
  * lbm_set_params re-derives the default unless lbm_set_tuning or
  * lbm_autotune chose the shape.  Every

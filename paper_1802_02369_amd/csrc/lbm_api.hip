@@ -63,8 +63,9 @@ lbm_tuning default_tuning(int64_t len, int64_t total, int eq) {
   // (fewer launches) rather than the width's best, and at most 16384 nodes
   // in all one node per lane (half the chain per step, four times the
   // lane-nodes, on a chip that is mostly idle anyway): measured 2.5 -> 3.5
-  // GLUPS at n = 2048 and 10.0 -> 13.7 at 8192, even at 32768 and behind
-  // P = 2 above.
+  // GLUPS at n = 2048 and 10.0 -> 13.7 at 8192 (K = 12), even at 32768 and
+  // behind P = 2 above.  K = 13 ran the n = 8192 forward 3 % and its
+  // gradient 5 % faster than K = 12 (K = 10, 11: slower; 14: +8 %, +3 %).
   static const lbm_tuning shapes[] = {
       {LBM_KERNEL_BLOCKED, 8, 40, 4}, {LBM_KERNEL_BLOCKED, 4, 24, 4},
       {LBM_KERNEL_BLOCKED, 2, 16, 4}, {LBM_KERNEL_BLOCKED, 2, 16, 1}};
@@ -74,7 +75,7 @@ lbm_tuning default_tuning(int64_t len, int64_t total, int eq) {
     const int64_t width = tile_width(t), out = width - 4 * t.steps_per_launch;
     if (4 * width <= len && total >= 1024 * out) return t;
   }
-  if (total <= 16384) return lbm_tuning{LBM_KERNEL_BLOCKED, 1, 12, 1};
+  if (total <= 16384) return lbm_tuning{LBM_KERNEL_BLOCKED, 1, 13, 1};
   return shapes[count - 1];
 }
 

@@ -108,8 +108,8 @@ def test_init_and_workspace_and_tuning_host():
     (1 << 20, (4, 24, 4)),   # too few P = 8 tiles for 4 workgroups per CU
     (1 << 19, (2, 16, 4)),
     (40000, (2, 16, 1)),     # small lattices: the narrowest tile, K = 16
-    (8192, (1, 12, 1)),      # up to 16384 nodes: one node per lane
-    (3, (1, 12, 1))])
+    (8192, (1, 13, 1)),      # up to 16384 nodes: one node per lane
+    (3, (1, 13, 1))])
 def test_default_tuning_follows_lattice_length(n, shape):
     rc, h = _init(n)
     assert rc == lbm.LBM_OK
