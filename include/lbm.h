@@ -44,7 +44,8 @@ enum {
   LBM_EHIP = -2,       /* a HIP runtime call failed */
   LBM_EWORKSPACE = -3, /* workspace too small */
   LBM_ENONFINITE = -4, /* state holds NaN/Inf, rho <= 0 or T <= 0 */
-  LBM_ENOTSUP = -5     /* option not supported by this build */
+  LBM_ENOTSUP = -5,    /* option not supported by this build */
+  LBM_EUNSTABLE = -6   /* lbm_linear_stability: a Fourier mode grows */
 };
 
 /* Per-lattice constants.
@@ -114,6 +115,18 @@ LBM_API const char* lbm_last_error(void);
  * derivative of s_psi with respect to s_e.  Host only. */
 LBM_API int lbm_coupled_rates(double s_e, double gamma, double prandtl, double* s_psi,
                               double* s_eps, double* ds_psi_ds_e);
+
+/* Opt-in check of the rates against linear stability (the analysis of
+ * section 7, with the coupled equilibria of section 8): the largest modulus
+ * *max_amp, over the Fourier modes k = pi j / (nk - 1), j = 0 .. nk - 1, of
+ * the eigenvalues of one time step's amplification matrix about the
+ * uniform state rho, u, s (physical units; the source is quadratic in
+ * gradients and drops out).  Returns LBM_EUNSTABLE when it exceeds
+ * 1 + 1e-10 (a mode grows: the scheme about such a state diverges),
+ * LBM_OK otherwise, LBM_EINVAL for bad constants, rho <= 0 or nk outside
+ * 2 .. 2^20.  Host only; nothing else calls it. */
+LBM_API int lbm_linear_stability(const lbm_params* p, double rho, double u,
+                                 double s, int32_t nk, double* max_amp);
 
 /* ----------------------------------------------------- single lattice */
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -88,9 +89,145 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 using namespace lbm;
 
+// ------------------------------------------------ linear stability --
+//
+// Frozen-coefficient (von Neumann) analysis of one time step about a
+// uniform state: the source of step (vii) is quadratic in gradients and
+// drops out of the linearisation, so a Fourier mode e^{ikj} of the six
+// populations is multiplied by G(k) = D(k) C', with C' the Jacobian of the
+// node collision (steps (ii)-(vi)) and D(k) the streaming (f+, g+ from
+// j - 1: e^{-ik}; f-, g- from j + 1: e^{ik}).  C' comes from complex-step
+// differentiation of the collision written here in plain host arithmetic
+// (physical moments, the library's equation of state and equilibria), so
+// its entries are exact to rounding.
+namespace {
+
+template <class T>
+void collide_host(const Consts& c, const T f[6], T out[6]) {
+  const T rho = c.rho0 * f[0] + c.rho0 * f[1] + c.rho0 * f[2];
+  const T J = c.mJ * (f[1] - f[2]);
+  const T e = c.me * (f[1] + f[2] - 2.0 * f[0]);
+  const T zeta = c.mz * (f[3] + f[4] + f[5]);
+  const T psi = c.mpsi * (f[4] - f[5]);
+  const T eps = c.meps * (f[4] + f[5] - 2.0 * f[3]);
+  const T u = J / rho, s = zeta / rho;
+  const T X = c.gm1 * std::log(rho / c.rho0) + c.gcp * s + c.xs0;
+  T e_eq, psi_eq, eps_eq;
+  if (c.eq_kind == 0) {
+    e_eq = 3.0 * (J * u + rho * c.r * c.T0 * std::exp(X)) - c.two_l2 * rho;
+    psi_eq = zeta * u;
+    eps_eq = c.eps_c * rho * X + e_eq * s;
+  } else if (c.eq_kind == 2) {
+    const T p = rho * c.r * c.T0 * std::exp(c.gm1 * std::log(rho / c.rho0));
+    e_eq = 3.0 * (J * u + p) - c.two_l2 * rho;
+    psi_eq = 0.0;
+    eps_eq = 0.0;
+  } else {
+    e_eq = c.lin[0] * rho + c.lin[1] * J + c.lin[2] * zeta;
+    psi_eq = c.lin[3] * rho + c.lin[4] * J + c.lin[5] * zeta;
+    eps_eq = c.lin[6] * rho + c.lin[7] * J + c.lin[8] * zeta;
+  }
+  const T es = e + c.s_e * (e_eq - e);
+  const T ps = psi + c.s_psi * (psi_eq - psi);
+  const T xs = eps + c.s_eps * (eps_eq - eps);
+  const T fr = c.fa * rho, fe = c.fb * es, fj = c.fc * J;
+  out[0] = fr - fe;
+  out[1] = 0.5 * fe + fr + fj;
+  out[2] = 0.5 * fe + fr - fj;
+  const T gz = c.ga * zeta, ge = c.gb * xs, gj = c.gc * ps;
+  out[3] = gz - ge;
+  out[4] = 0.5 * ge + gz + gj;
+  out[5] = 0.5 * ge + gz - gj;
+}
+
+using cplx = std::complex<double>;
+
+// Spectral radius of a 6x6 complex matrix: ||A^n||^(1/n) for n = 2^50 by
+// repeated squaring, renormalised at each squaring (the polynomial factors
+// of non-normal or repeated eigenvalues vanish at that n).
+double spectral_radius(const cplx (&A0)[6][6]) {
+  cplx A[6][6];
+  std::copy(&A0[0][0], &A0[0][0] + 36, &A[0][0]);
+  double logs = 0.0;  // log of the scale taken out, per unit exponent
+  double inv_n = 1.0;
+  for (int it = 0; it < 50; ++it) {
+    double nrm = 0.0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) nrm = std::max(nrm, std::abs(A[i][j]));
+    if (nrm == 0.0) return 0.0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) A[i][j] /= nrm;
+    logs += std::log(nrm) * inv_n;
+    cplx B[6][6] = {};
+    for (int i = 0; i < 6; ++i)
+      for (int k = 0; k < 6; ++k)
+        for (int j = 0; j < 6; ++j) B[i][j] += A[i][k] * A[k][j];
+    std::copy(&B[0][0], &B[0][0] + 36, &A[0][0]);
+    inv_n *= 0.5;
+  }
+  double nrm = 0.0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) nrm = std::max(nrm, std::abs(A[i][j]));
+  return std::exp(logs + (nrm > 0.0 ? std::log(nrm) * inv_n : -INFINITY));
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_linear_stability(const lbm_params* p, double rho, double u, double s,
+                         int32_t nk, double* max_amp) {
+  if (!p || !max_amp) return set_err(LBM_EINVAL, "NULL argument");
+  Consts c;
+  int rc = make_consts(p, &c);
+  if (rc) return rc;
+  if (!(std::isfinite(rho) && rho > 0.0) || !std::isfinite(u) ||
+      !std::isfinite(s))
+    return set_err(LBM_EINVAL, "need a finite state with rho > 0");
+  if (nk < 2 || nk > (1 << 20))
+    return set_err(LBM_EINVAL, "nk must lie in 2 .. 2^20");
+  // populations of the uniform state: the collision's fixed point
+  double feq[6];
+  {
+    Consts ce = c;
+    ce.s_e = ce.s_psi = ce.s_eps = 1.0;  // one full relaxation lands on it
+    double f0[6];
+    const double ir = 1.0 / (3.0 * c.rho0);
+    f0[0] = f0[1] = f0[2] = rho * ir;
+    f0[1] += 0.5 * rho * u / c.mJ;
+    f0[2] -= 0.5 * rho * u / c.mJ;
+    f0[3] = f0[4] = f0[5] = rho * s / (3.0 * c.mz);
+    collide_host<double>(ce, f0, feq);
+  }
+  // Jacobian of the collision by complex steps
+  const double h = 1e-30;
+  double Jc[6][6];
+  for (int q = 0; q < 6; ++q) {
+    cplx x[6], y[6];
+    for (int i = 0; i < 6; ++i) x[i] = feq[i];
+    x[q] += cplx(0.0, h);
+    collide_host<cplx>(c, x, y);
+    for (int i = 0; i < 6; ++i) Jc[i][q] = y[i].imag() / h;
+  }
+  double worst = 0.0;
+  for (int j = 0; j < nk; ++j) {
+    const double k = M_PI * j / (nk - 1);
+    const cplx dm = std::polar(1.0, -k), dp = std::polar(1.0, k);
+    const cplx d[6] = {1.0, dm, dp, 1.0, dm, dp};
+    cplx G[6][6];
+    for (int r = 0; r < 6; ++r)
+      for (int q = 0; q < 6; ++q) G[r][q] = d[r] * Jc[r][q];
+    worst = std::max(worst, spectral_radius(G));
+  }
+  *max_amp = worst;
+  if (worst > 1.0 + 1e-10)
+    return set_err(LBM_EUNSTABLE,
+                   "linearly unstable about this state: amplification %.12g",
+                   worst);
+  return LBM_OK;
+}
 
 int lbm_coupled_rates(double s_e, double gamma, double prandtl, double* s_psi,
                       double* s_eps, double* ds_psi_ds_e) {

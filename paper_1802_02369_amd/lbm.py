@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_EWORKSPACE, LBM_ENONFINITE, LBM_ENOTSUP = \
     0, -1, -2, -3, -4, -5
+LBM_EUNSTABLE = -6
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
 MAX_GROUPS = 4
 WS_STEP, WS_TUNE = 0, 1
@@ -62,6 +63,8 @@ def lib():
         sig = {
             "lbm_last_error": ([], ctypes.c_char_p),
             "lbm_coupled_rates": ([_d, _d, _d, _dp, _dp, _dp], ctypes.c_int),
+            "lbm_linear_stability": ([ctypes.POINTER(CParams), _d, _d, _d,
+                                      ctypes.c_int32, _dp], ctypes.c_int),
             "lbm_init": ([ctypes.POINTER(_vp), _i64, ctypes.POINTER(CParams), _vp],
                          ctypes.c_int),
             "lbm_destroy": ([_vp], None),
@@ -142,6 +145,21 @@ def coupled_rates(s_e: float, gamma: float = 1.4, prandtl: float = 1.0):
     check(lib().lbm_coupled_rates(s_e, gamma, prandtl, ctypes.byref(a),
                                   ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def linear_stability(p: "Params", rho: float = 1.0, u: float = 0.0,
+                     s: float | None = None, nk: int = 256):
+    """(max amplification, stable) of one step about the uniform state
+    (rho, u, s) over nk Fourier modes in [0, pi] (lbm_linear_stability;
+    s defaults to p.s0)."""
+    a = _d()
+    cp = p.c()
+    rc = lib().lbm_linear_stability(ctypes.byref(cp), float(rho), float(u),
+                                    float(p.s0 if s is None else s), int(nk),
+                                    ctypes.byref(a))
+    if rc not in (LBM_OK, LBM_EUNSTABLE):
+        check(rc)
+    return a.value, rc == LBM_OK
 
 
 @dataclass
