@@ -69,7 +69,10 @@ enum {
  *   eq_kind    0: nonlinear equilibria of section 8 (eqs. energie-equilibre,
  *              psi-equilibre, eq-energie-entropie-d1q3q3);
  *              1: linear equilibria of section 7 (eq. equilibres-NS-linearise,
- *              printed for lambda = cp = rho0 = 1; other values are rejected);
+ *              printed for lambda = cp = rho0 = 1; other values are rejected),
+ *              with the zeta coefficient of e_eq taken as 3 c0^2 / cp (the
+ *              print shows 3 u0^2 / cp; the zeta term of the J flux in eq.
+ *              NS-rho-J-zeta-linearise requires c0^2);
  *              2: fluid D1Q3 scheme of sections 2-3 (eq. energie-equilibre
  *              with the isentropic pressure p0 (rho/rho0)^gamma), the g
  *              distribution passive (psi_eq = eps_eq = 0);

@@ -270,10 +270,16 @@ void equilibria(const Ctx& c, const S& rho, const S& J, const S& zeta,
     psi_eq = p.u0_lin * zeta;
     eps_eq = p.alpha * l2 * zeta;
   } else {
-    // Eq. equilibres-NS-linearise, as printed (units lambda = cp = 1).
+    // Eq. equilibres-NS-linearise (units lambda = cp = 1), with the zeta
+    // coefficient of e_eq read as 3 c0^2 / cp where the print shows
+    // 3 u0^2 / cp: the first-order flux (2/3) lambda^2 rho + e_eq / 3 must be
+    // the flux of J in eq. NS-rho-J-zeta-linearise, whose zeta term is
+    // (c0^2 / cp) d_x zeta, and only with that term do the printed psi_eq
+    // and eps_eq give the entropy equation of that system at second order
+    // (eq. edp-ordre-2) for every u0, s0.
     const double u0 = p.u0_lin, s0 = p.s0_lin, c0 = p.c0, g = p.gamma;
     e_eq = (3.0 * (1.0 - s0 / p.cp) * c0 * c0 - 3.0 * u0 * u0 - 2.0 * l2) * rho +
-           6.0 * u0 * J + 3.0 * (u0 * u0 / p.cp) * zeta;
+           6.0 * u0 * J + 3.0 * (c0 * c0 / p.cp) * zeta;
     psi_eq = -u0 * s0 * rho + s0 * J + u0 * zeta;
     eps_eq = (-3.0 * (s0 * c0) * (s0 * c0) - 6.0 * s0 * u0 * u0 +
               3.0 * s0 * c0 * c0 + 2.0 - 2.0 * s0 - 2.0 / g) *

@@ -31,10 +31,26 @@ def sources() -> list[str]:
 
 
 def build(extra: list[str] | None = None, out: str = LIB) -> str:
+    """Compiles every source to an object (in parallel: the translation units
+    share no device code) and links them into ``out``."""
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(os.path.dirname(HERE), "_build")
+    os.makedirs(objdir, exist_ok=True)
+    cflags = [f for f in HIPFLAGS if f != "-shared"] + list(extra or [])
+
+    def compile_one(src: str) -> str:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        subprocess.run([hipcc, *cflags, "-c", src, "-o", obj], check=True)
+        return obj
+
+    srcs = sources()
+    with ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, srcs))
     tmp = out + ".tmp"
-    cmd = [hipcc, *HIPFLAGS, *(extra or []), *sources(), "-o", tmp]
-    subprocess.run(cmd, check=True)
+    subprocess.run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC",
+                    *objs, "-o", tmp], check=True)
     os.replace(tmp, out)
     return out
 

@@ -120,11 +120,15 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->xs0l = c->xs0 - c->gm1 * std::log(r0);
   c->eq_kind = p->eq_kind;
   if (p->eq_kind == 1) {
-    // Eq. equilibres-NS-linearise as printed (lambda = cp = rho0 = 1).
+    // Eq. equilibres-NS-linearise (lambda = cp = rho0 = 1).  The zeta
+    // coefficient of e_eq is 3 c0^2 (printed 3 u0^2): the flux of J in
+    // eq. NS-rho-J-zeta-linearise has the term c0^2 d_x zeta, and the
+    // printed psi_eq, eps_eq are compatible with that system's entropy
+    // equation at second order only with it.
     const double u0 = p->u0_lin, s0 = p->s0_lin, c0 = p->c0;
     c->lin[0] = 3.0 * (1.0 - s0) * c0 * c0 - 3.0 * u0 * u0 - 2.0;
     c->lin[1] = 6.0 * u0;
-    c->lin[2] = 3.0 * u0 * u0;
+    c->lin[2] = 3.0 * c0 * c0;
     c->lin[3] = -u0 * s0;
     c->lin[4] = s0;
     c->lin[5] = u0;

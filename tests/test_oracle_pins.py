@@ -503,6 +503,183 @@ def test_linear_equilibria_stable_as_section7_reports(u0, s0):
     assert np.abs(f - base).max() <= 2 * d0
 
 
+# Linear equilibria of section 7 (eq_kind = 1).  The paper obtains them
+# from the linearised Navier-Stokes system eq. NS-rho-J-zeta-linearise by
+# asking the scheme's equivalent equations (eq. edp-ordre-2) to reproduce it:
+# the first-order fluxes Lambda_WW W + Lambda_WN m_eq (eq. edp1-d1q3q3) must be
+# A W, and the entropy equation's second-order term must be its diffusion.
+# The helpers below build that second-order system from the printed Lambda
+# (eq. Lambda-d1q3q3), the defects of conservation theta (eq. thetas) and the
+# Henon coefficients (eq. henon), for any linear equilibria E (m_eq = E W).
+
+LIN_CASES = [
+    dict(u0=0.0, s0=0.0, s_e=1.9),
+    dict(u0=0.15, s0=0.2, s_e=1.9),       # section 7's second stable run
+    dict(u0=0.1, s0=0.0, s_e=1.7),
+    dict(u0=0.0, s0=0.2, s_e=1.5),
+    dict(u0=-0.12, s0=0.3, s_e=1.3, gamma=1.3, prandtl=0.71),
+]
+
+
+_NAMES = ("u0", "s0", "c0", "cp", "gamma", "Pr", "nu0", "lam", "sigma_e",
+          "sigma_psi")
+
+
+def _expr(text, **vals):
+    """A printed expression (golden file) evaluated at the given values; the
+    names are plain symbols (gamma is the ratio of specific heats)."""
+    syms = {k: sp.Symbol(k) for k in _NAMES}
+    e = sp.sympify(text, locals=syms)
+    return float(e.subs({syms[k]: v for k, v in vals.items()}))
+
+
+def linearised_ns(u0, s0, c0, cp, gamma, Pr, nu0):
+    """A and the zeta row of B of eq. NS-rho-J-zeta-linearise (golden)."""
+    g = printed()["NS_rho_J_zeta_linearise"]
+    v = dict(u0=u0, s0=s0, c0=c0, cp=cp, gamma=gamma, Pr=Pr, nu0=nu0)
+    A = np.array([[_expr(x, **v) for x in r] for r in g["A_rows"]])
+    Bz = np.array([_expr(x, **v) for x in g["B_zeta_row"]])
+    return A, Bz
+
+
+def second_order_system(E, rates, lam=1.0):
+    """F and D of d_t W + F d_x W - dt D d_xx W = 0 for m_eq = (W, E W),
+    from eq. edp-ordre-2 with theta = d_t m_eq + Lambda_N. d_x m_eq (eq.
+    thetas) and d_t W = -F d_x W at first order (dt = dx / lam = 1)."""
+    Lam = sym_matrix(printed()["Lambda_D1Q3Q3"]["rows"], lam, 1.0, 1.0)
+    Wi, Ni = [0, 1, 2], [3, 4, 5]
+    LWW, LWN = Lam[np.ix_(Wi, Wi)], Lam[np.ix_(Wi, Ni)]
+    LNW, LNN = Lam[np.ix_(Ni, Wi)], Lam[np.ix_(Ni, Ni)]
+    F = LWW + LWN @ E
+    theta = LNW + LNN @ E - E @ F     # theta_l = Theta[l] . d_x W
+    sig = np.diag([1 / s - 0.5 for s in rates])
+    return F, LWN @ sig @ theta
+
+
+def coupled(s_e, gamma, Pr):
+    """(s_e, s_psi, s_eps) with eq. lien-sigma-sigma and s_eps = 1.5."""
+    sig_psi = 1.5 * gamma / Pr * (1 / s_e - 0.5)
+    return s_e, 1 / (sig_psi + 0.5), 1.5
+
+
+def ns_equilibria(case):
+    """The linear equilibria that make the equivalent equations those of eq.
+    NS-rho-J-zeta-linearise: e_eq from the J flux, psi_eq from the zeta flux
+    (first order), and eps_eq from the zeta row of the diffusion, which is
+    affine in eps_eq's coefficients (second order, with the coupled rates)."""
+    c0, g, Pr = 0.5, case.get("gamma", 1.4), case.get("prandtl", 1.0)
+    rates = coupled(case["s_e"], g, Pr)
+    nu0 = 1 / case["s_e"] - 0.5               # sigma_e lambda dx, dx = 1
+    A, Bz = linearised_ns(case["u0"], case["s0"], c0, 1.0, g, Pr, nu0)
+    E = np.zeros((3, 3))
+    E[0] = 3 * A[1] - np.array([2.0, 0, 0])  # (2/3) rho + e_eq/3 = A_J . W
+    E[1] = A[2]                               # psi_eq = A_zeta . W
+    base = second_order_system(E, rates)[1][2]
+    Mz = np.zeros((3, 3))
+    for i in range(3):
+        Ei = E.copy()
+        Ei[2, i] = 1.0
+        Mz[:, i] = second_order_system(Ei, rates)[1][2] - base
+    # D_zeta = base + eps_row . Mz  (row vector times the 3x3 sensitivity)
+    E[2] = np.linalg.solve(Mz.T, Bz - base)
+    return E, A, Bz, rates
+
+
+def oracle_linear_equilibria(case):
+    c0, g, Pr = 0.5, case.get("gamma", 1.4), case.get("prandtl", 1.0)
+    rates = coupled(case["s_e"], g, Pr)
+    p = oracle.Params(eq_kind=1, u0_lin=case["u0"], s0_lin=case["s0"],
+                      s0=case["s0"], c0=c0, gamma=g, prandtl=Pr, s_e=rates[0],
+                      s_psi=rates[1], s_eps=rates[2], source_on=0)
+    # the equilibria are linear in W: three independent states give E
+    Wm = np.array([[1.0, 0.9, 1.2], [0.1, -0.2, 0.05], [0.3, 0.1, -0.2]])
+    eq = oracle.equilibria(Wm[0], Wm[1], Wm[2], p)[:3]
+    return eq @ np.linalg.inv(Wm), p
+
+
+@pytest.mark.parametrize("case", LIN_CASES)
+def test_linear_equilibria_first_order_fluxes_are_linearised_ns(case):
+    """First order: the oracle's flux of J, (2/3) lambda^2 rho + e_eq/3, and
+    of zeta, psi_eq, are the fluxes A W of eq. NS-rho-J-zeta-linearise:
+    rho coefficient c0^2 - u0^2 - s0 c0^2/cp, J coefficient 2 u0, zeta
+    coefficient c0^2/cp (the printed e_eq shows 3 u0^2/cp there, which would
+    leave u0^2/cp: read as 3 c0^2/cp), and psi_eq = -u0 s0 rho + s0 J + u0 zeta."""
+    E, _ = oracle_linear_equilibria(case)
+    c0, g, Pr = 0.5, case.get("gamma", 1.4), case.get("prandtl", 1.0)
+    A, _ = linearised_ns(case["u0"], case["s0"], c0, 1.0, g, Pr, 0.1)
+    F, _ = second_order_system(E, coupled(case["s_e"], g, Pr))
+    np.testing.assert_allclose(F, A, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("case", LIN_CASES)
+def test_linear_equilibria_entropy_diffusion_is_linearised_ns(case):
+    """Second order: with the coupled rates (eq. lien-sigma-sigma,
+    s_eps = 1.5), the zeta row of the scheme's diffusion (eq. edp-ordre-2)
+    is that of eq. NS-rho-J-zeta-linearise,
+    (nu0/Pr) ((gamma - 1) cp - gamma s0) d_xx rho + gamma (nu0/Pr) d_xx zeta.
+    This fixes all three coefficients of eps_eq; at s0 = 0 its zeta
+    coefficient is alpha lambda^2 of eq. compatibilite, alpha = 3 u0^2/lambda^2."""
+    E, p = oracle_linear_equilibria(case)
+    E_ns, _, Bz, rates = ns_equilibria(case)
+    _, D = second_order_system(E, rates)
+    np.testing.assert_allclose(D[2], Bz, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(E, E_ns, rtol=1e-13, atol=1e-14)
+    if case["s0"] == 0.0:
+        s_e, s_psi, _ = rates
+        alpha = _expr(printed()["compatibilite_alpha"]["alpha"],
+                      gamma=p.gamma, Pr=p.prandtl, sigma_e=1 / s_e - 0.5,
+                      sigma_psi=1 / s_psi - 0.5, u0=case["u0"], lam=1.0)
+        assert alpha == pytest.approx(3 * case["u0"] ** 2, abs=1e-13)
+        assert E[2, 2] == pytest.approx(alpha, abs=1e-13)
+
+
+@pytest.mark.parametrize("case", [c for c in LIN_CASES if c["s0"] == 0.0])
+def test_second_order_system_reproduces_printed_theta_e(case):
+    """The machinery of second_order_system, checked against the defect of
+    conservation theta_e that section 7 prints for its decoupled system
+    (s0 = 0): theta_e = 3 (lambda^2 - 3 u0^2 - c0^2) d_x J
+    - 6 u0 (c0^2 - u0^2) d_x rho, i.e. the J row of the diffusion is
+    sigma_e theta_e / 3 in its rho and J entries."""
+    E, _, _, rates = ns_equilibria(case)
+    _, D = second_order_system(E, rates)
+    g = printed()["theta_e_section7"]
+    th = [_expr(g[k], u0=case["u0"], c0=0.5, lam=1.0) for k in ("d_rho", "d_J")]
+    sig_e = 1 / case["s_e"] - 0.5
+    np.testing.assert_allclose(D[1, :2], sig_e * np.array(th) / 3, rtol=1e-13,
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("case", LIN_CASES)
+def test_linear_equilibria_modes_match_equivalent_equations(case):
+    """Dynamics: the eigenvalues z of the oracle's linearised step on a
+    Fourier mode k (tangent-linear model, N = 512, k = 2 pi / N) give the
+    speeds -arg(z)/k of the eigenvalues mu of A (eq. NS-rho-J-zeta-linearise)
+    and the damping -ln|z|/k^2 = l D r / (l r) of the second-order system
+    built from the equilibria that the linearised system fixes, with l, r
+    the left and right eigenvectors of mu; both to O(k) relative."""
+    E_ns, A, _, rates = ns_equilibria(case)
+    _, D = second_order_system(E_ns, rates)
+    mu, R = np.linalg.eig(A)
+    Li = np.linalg.inv(R)
+    order = np.argsort(mu.real)
+    speed = mu.real[order]
+    damp = np.array([(Li[i] @ D @ R[:, i]).real for i in range(3)])[order]
+    _, p = oracle_linear_equilibria(case)
+    n = 512
+    base = oracle.init(np.ones(n), np.full(n, case["u0"]), np.full(n, case["s0"]), p)
+    z = np.linalg.eigvals(_mode_eigs(p, n, 1, base))
+    kap = 2 * np.pi / n
+    hyd = sorted((w for w in z if abs(w) > 0.99), key=lambda w: -np.angle(w))
+    assert len(hyd) == 3
+    got_speed = np.array([-np.angle(w) / kap for w in hyd])
+    got_damp = np.array([-np.log(abs(w)) / kap**2 for w in hyd])
+    np.testing.assert_allclose(got_speed, speed, rtol=1e-4, atol=1e-6)
+    np.testing.assert_allclose(got_damp, damp, rtol=2e-4)
+    # the kinetic modes relax at |1 - s|
+    kin = sorted(abs(w) for w in z if abs(w) <= 0.99)
+    np.testing.assert_allclose(kin, sorted(abs(1 - s) for s in rates), atol=5e-3)
+
+
 @pytest.mark.parametrize("dx", [1 / 40, 1 / 80, 1 / 160])
 def test_source_term_energy_and_entropy_as_section9_reports(dx):
     """Section 9 (Fig. 4 text), strong wave delta rho = 0.1 rho0 on the three
