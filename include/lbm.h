@@ -48,6 +48,21 @@ enum {
   LBM_EUNSTABLE = -6   /* lbm_linear_stability: a Fourier mode grows */
 };
 
+/* Bits of lbm_params.flags. */
+enum {
+  /* Failure detection (opt-in).  lbm_step and lbm_batch_run check the state
+   * at the end of every launch: a node fails when one of its six populations
+   * is NaN or infinite, or its rho <= 0 or T <= 0 (T from the equation of
+   * state, as lbm_diagnostics computes it).  The call then synchronises its
+   * stream and returns LBM_ENONFINITE; lbm_last_error() names the number of
+   * time steps done when the first failing launch ended and the lowest
+   * failing node (single lattice) or lattice (batch) of that launch.  The
+   * state is left as the run made it.  Each launch of K steps costs one more
+   * pass over the state it wrote (48 bytes per node read); without the flag
+   * nothing is checked and nothing waits. */
+  LBM_CHECK_FINITE = 1
+};
+
 /* Per-lattice constants.
  *   lambda  lattice velocity dx/dt (section 2)
  *   rho0    scale factor of the moment matrix (eq. M-d1q3q3) and reference
@@ -80,6 +95,9 @@ enum {
  *              (psi_eq = u0 zeta, eps_eq = alpha lambda^2 zeta), the f
  *              distribution passive (e_eq = (3 c0^2 - 2 lambda^2) rho).
  *              Kinds 2 and 3 need source_on = 0.
+ *   flags      LBM_CHECK_FINITE or 0 (other bits: LBM_EINVAL); in a batch,
+ *              the lattices whose flags have it are checked
+ *   reserved   must be 0
  */
 typedef struct lbm_params {
   double lambda, rho0, cp, gamma, prandtl, c0, s0;
@@ -88,6 +106,8 @@ typedef struct lbm_params {
   double alpha;
   int32_t source_on;
   int32_t eq_kind;
+  int32_t flags;
+  int32_t reserved;
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -184,7 +204,10 @@ LBM_API int lbm_set_equilibrium(lbm_handle* h, const double* rho, const double* 
 /* Advances the state f (device, 6*n doubles) by nsteps >= 0 time steps of the
  * algorithm of section 8, steps (i)-(viii), in place.  ws: device workspace
  * of lbm_workspace_bytes(h, LBM_WS_STEP) bytes, contents overwritten.
- * f and ws must not overlap. */
+ * f and ws must not overlap.  With LBM_CHECK_FINITE in the lattice's flags
+ * the call checks the state after every launch, synchronises and returns
+ * LBM_ENONFINITE if a node failed (see LBM_CHECK_FINITE; the step count in
+ * the message saturates at 2^28 - 1). */
 LBM_API int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
                      int64_t nsteps);
 
@@ -344,7 +367,12 @@ LBM_API int lbm_batch_set_equilibrium(lbm_batch* b, const double* rho, const dou
 /* Advances every lattice of the batch state f (device, 6*n_total doubles) by
  * nsteps time steps, in place.  With use_graph = 1 the launches are captured
  * once into a hipGraph (re-captured when f, ws, nsteps or the tuning change)
- * and replayed with one hipGraphLaunch on the stream. */
+ * and replayed with one hipGraphLaunch on the stream.  Lattices with
+ * LBM_CHECK_FINITE in their flags are checked after every launch (the
+ * checks and the reset of the failure record are kernels inside the graph);
+ * if any has them, the call synchronises and returns LBM_ENONFINITE when one
+ * failed, naming the step count and the lowest lattice index (saturating at
+ * 2^32 - 1 steps). */
 LBM_API int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
                           int64_t nsteps, int use_graph);
 /* Moments m = M f of every node (device, 6*n_total doubles, moment order as

@@ -23,11 +23,26 @@ def _consts(consts: dict | None) -> dict:
     return c
 
 
+def _rate_like(value, like):
+    """A rate gradient as a tensor on the device and of the shape of the rate
+    it belongs to."""
+    return torch.as_tensor(value, dtype=torch.float64).to(like.device).reshape(like.shape)
+
+
 class LBMFunction(torch.autograd.Function):
+    """s_e and s_eps may be Python numbers (no gradient) or 0-d tensors on
+    any device (gradients on the same device)."""
+
     @staticmethod
     def forward(ctx, rho0, J0, zeta0, s_e, s_eps, nsteps: int, ckpt_every: int,
                 consts: dict | None = None):
         c = _consts(consts)
+        for name, r in (("s_e", s_e), ("s_eps", s_eps)):
+            if torch.is_tensor(r) and r.numel() != 1:
+                raise ValueError(f"LBMFunction: {name} must be a number or a "
+                                 f"one-element tensor, got shape {tuple(r.shape)}")
+        ctx.rate_like = tuple(r.detach() if torch.is_tensor(r) else None
+                              for r in (s_e, s_eps))
         se = float(s_e)
         s_psi, _, dpsi = lbm.coupled_rates(se, c["gamma"], c["prandtl"])
         p = lbm.Params(s_e=se, s_psi=s_psi, s_eps=float(s_eps), **c)
@@ -52,21 +67,30 @@ class LBMFunction(torch.autograd.Function):
         fbar = lat.moments_adjoint(mbar, aws)
         r = lat.adjoint(aws, ctx.nsteps, ctx.ckpt, fbar)
         g_rho, g_J, g_zeta = lat.equilibrium_adjoint(rho0, J0, zeta0, fbar, aws)
-        dev = rho0.device
-        g_se = torch.tensor(r[0] + r[1] * ctx.dpsi, dtype=torch.float64, device=dev)
-        g_seps = torch.tensor(r[2], dtype=torch.float64, device=dev)
+        like_se, like_seps = ctx.rate_like
+        g_se = (_rate_like(r[0] + r[1] * ctx.dpsi, like_se)
+                if ctx.needs_input_grad[3] else None)
+        g_seps = (_rate_like(r[2], like_seps)
+                  if ctx.needs_input_grad[4] else None)
         return g_rho, g_J, g_zeta, g_se, g_seps, None, None, None
 
 
 class BatchLBMFunction(torch.autograd.Function):
     """Batch form: rho0, J0, zeta0 are (n_total,) fields in the batch layout
-    of `offsets`; s_e and s_eps are (n_inst,) tensors.  Returns the
-    (n_total,) density after nsteps."""
+    of `offsets`; s_e and s_eps are (n_inst,) tensors on any device (their
+    gradients come back on the same device).  Returns the (n_total,) density
+    after nsteps."""
 
     @staticmethod
     def forward(ctx, rho0, J0, zeta0, s_e, s_eps, offsets, nsteps: int,
                 ckpt_every: int, consts: dict | None = None):
         c = _consts(consts)
+        n_inst = len(offsets) - 1
+        for name, r in (("s_e", s_e), ("s_eps", s_eps)):
+            if not torch.is_tensor(r) or r.shape != (n_inst,):
+                raise ValueError(f"BatchLBMFunction: {name} must be a tensor of "
+                                 f"shape ({n_inst},), one rate per lattice")
+        ctx.rate_like = (s_e.detach(), s_eps.detach())
         se = s_e.detach().cpu().tolist()
         seps = s_eps.detach().cpu().tolist()
         params, dpsi = [], []
@@ -96,6 +120,9 @@ class BatchLBMFunction(torch.autograd.Function):
         fbar = bt.moments_adjoint(mbar, aws)
         r = bt.adjoint(aws, ctx.nsteps, ctx.ckpt, fbar)
         g_rho, g_J, g_zeta = bt.equilibrium_adjoint(rho0, J0, zeta0, fbar, aws)
-        g_se = r[:, 0] + r[:, 1] * ctx.dpsi
-        g_seps = r[:, 2].clone()
+        like_se, like_seps = ctx.rate_like
+        g_se = (_rate_like(r[:, 0] + r[:, 1] * ctx.dpsi, like_se)
+                if ctx.needs_input_grad[3] else None)
+        g_seps = (_rate_like(r[:, 2], like_seps)
+                  if ctx.needs_input_grad[4] else None)
         return g_rho, g_J, g_zeta, g_se, g_seps, None, None, None, None

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -76,6 +77,8 @@ int make_consts(const lbm_params* p, Consts* c) {
   if (p->eq_kind == 1 && (p->lambda != 1.0 || p->cp != 1.0 || p->rho0 != 1.0))
     return set_err(LBM_EINVAL,
                    "linear equilibria are defined for lambda = cp = rho0 = 1");
+  if ((p->flags & ~LBM_CHECK_FINITE) != 0 || p->reserved != 0)
+    return set_err(LBM_EINVAL, "flags may hold LBM_CHECK_FINITE only; reserved must be 0");
   const double l = p->lambda, cp = p->cp, r0 = p->rho0, g = p->gamma;
   std::memset(c, 0, sizeof *c);
   c->rho0 = r0;
@@ -119,6 +122,7 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->hC = cp * c->T0 / (p->prandtl * l * l);
   c->xs0l = c->xs0 - c->gm1 * std::log(r0);
   c->eq_kind = p->eq_kind;
+  c->flags = p->flags;
   if (p->eq_kind == 1) {
     // Eq. equilibres-NS-linearise (lambda = cp = rho0 = 1).  The zeta
     // coefficient of e_eq is 3 c0^2 (printed 3 u0^2): the flux of J in
@@ -665,6 +669,80 @@ __global__ __launch_bounds__(kDiagBlock) void k_batch_diag(
   if (threadIdx.x < 8) out[8 * inst + threadIdx.x] = s[0][threadIdx.x];
 }
 
+// ------------------------------------------------- failure detection ---
+//
+// LBM_CHECK_FINITE: after a launch, every node the launch wrote is checked
+// as lbm_diagnostics counts it: its six populations finite, rho > 0 and
+// T > 0 (T from the equation of state).  A failing node gives the key
+// (steps << shift) | index, with steps the time steps done when the launch
+// ended and index its node (single lattice) or lattice (batch); the record
+// keeps the smallest key: each lane's minimum over its nodes, the wavefront's
+// minimum by a butterfly, then one 64-bit vector atomic min per wavefront.
+
+__device__ __forceinline__ bool node_fails(const Consts& c,
+                                           const double* __restrict__ f,
+                                           int64_t S, int64_t j) {
+  const double f0 = f[j], fp = f[S + j], fm = f[2 * S + j];
+  const double g0 = f[3 * S + j], gp = f[4 * S + j], gm = f[5 * S + j];
+  const bool finite = isfinite(f0) && isfinite(fp) && isfinite(fm) &&
+                      isfinite(g0) && isfinite(gp) && isfinite(gm);
+  const double rho = lbm::density(c, f0, fp, fm);
+  const double J = c.mJ * (fp - fm);
+  const double zeta = c.mz * (g0 + (gp + gm));
+  double u, s_, X, T;
+  lbm::thermo(c, rho, J, zeta, u, s_, X, T);
+  return !(finite && rho > 0.0 && T > 0.0);
+}
+
+// Every lane of the wavefront takes part (lanes without a failing node
+// bring ~0).
+__device__ __forceinline__ void record_min(unsigned long long* rec,
+                                           unsigned long long key) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const unsigned long long o = __shfl_xor(key, m, 64);
+    key = o < key ? o : key;
+  }
+  if ((threadIdx.x & 63) == 0 && key != ~0ull) atomicMin(rec, key);
+}
+
+__global__ __launch_bounds__(64) void k_check_reset(unsigned long long* rec) {
+  if (threadIdx.x == 0) *rec = ~0ull;
+}
+
+// Single lattice: nodes [0, n), key steps_key | j.
+__global__ __launch_bounds__(256) void k_check_state(
+    Consts c, const double* __restrict__ f, int64_t n,
+    unsigned long long steps_key, unsigned long long* rec) {
+  unsigned long long key = ~0ull;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * 256)
+    if (node_fails(c, f, n, j) && (steps_key | (unsigned long long)j) < key)
+      key = steps_key | (unsigned long long)j;
+  record_min(rec, key);
+}
+
+// Batch: workgroup b checks the nodes tile tiles[b] stored, [t OUT,
+// t OUT + OUT) of its lattice, if that lattice asks for it; key
+// steps_key | inst.
+__global__ __launch_bounds__(256) void k_batch_check(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const lbm::TileRef* __restrict__ tiles, const double* __restrict__ f,
+    int64_t S, int OUT, unsigned long long steps_key,
+    unsigned long long* rec) {
+  const lbm::TileRef tr = tiles[blockIdx.x];
+  if (!(cs[tr.inst].flags & LBM_CHECK_FINITE)) return;  // uniform
+  const Consts c = cs[tr.inst];
+  const int64_t off = offs[tr.inst];
+  const int64_t n = offs[tr.inst + 1] - off;
+  const int64_t lo = (int64_t)tr.t * OUT;
+  const int64_t hi = lo + OUT < n ? lo + OUT : n;
+  bool bad = false;
+  for (int64_t j = lo + threadIdx.x; j < hi; j += 256)
+    bad = bad || node_fails(c, f + off, S, j);
+  record_min(rec, bad ? steps_key | (unsigned long long)tr.inst : ~0ull);
+}
+
 }  // namespace
 
 // ----------------------------------------------------- launch helpers ---
@@ -743,7 +821,44 @@ int launch_step_tile(const Consts& c, const double* fin, double* fout,
   return hip_check(hipGetLastError(), "k_step_tile");
 }
 
-size_t diag_ws_doubles() { return (size_t)kDiagMaxBlocks * 8 + 8; }
+// reduction scratch of the diagnostics (8 final values, 8 per block), then
+// the failure record of LBM_CHECK_FINITE (4 doubles)
+size_t diag_ws_doubles() { return (size_t)kDiagMaxBlocks * 8 + 8 + 4; }
+size_t check_record_double() { return (size_t)kDiagMaxBlocks * 8 + 8; }
+
+int launch_check_reset(unsigned long long* rec, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_reset, dim3(1), dim3(64), 0, s, rec);
+  return hip_check(hipGetLastError(), "k_check_reset");
+}
+
+int launch_check_state(const Consts& c, const double* f, int64_t n,
+                       int64_t steps, unsigned long long* rec, hipStream_t s) {
+  const unsigned long long sk =
+      (unsigned long long)std::min<int64_t>(steps, kCheckMaxSteps1) << 36;
+  const int nb = (int)std::min<int64_t>(2048, cdiv(n, 256));
+  hipLaunchKernelGGL(k_check_state, dim3(nb), dim3(256), 0, s, c, f, n, sk, rec);
+  return hip_check(hipGetLastError(), "k_check_state");
+}
+
+int launch_batch_check(const Consts* cs, const int64_t* offs,
+                       const TileRef* tiles, int64_t ntiles, const double* f,
+                       int64_t S, int OUT, int64_t steps,
+                       unsigned long long* rec, hipStream_t s) {
+  if (ntiles <= 0) return LBM_OK;
+  const unsigned long long sk =
+      (unsigned long long)std::min<int64_t>(steps, kCheckMaxStepsB) << 31;
+  hipLaunchKernelGGL(k_batch_check, dim3((unsigned)ntiles), dim3(256), 0, s, cs,
+                     offs, tiles, f, S, OUT, sk, rec);
+  return hip_check(hipGetLastError(), "k_batch_check");
+}
+
+int read_check_record(const unsigned long long* rec, hipStream_t s,
+                      unsigned long long* out) {
+  int rc = hip_check(hipMemcpyAsync(out, rec, sizeof *out, hipMemcpyDeviceToHost, s),
+                     "hipMemcpyAsync");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return rc;
+}
 
 int launch_diagnostics(const Consts& c, const double* f, int64_t n,
                        double* scratch, hipStream_t s) {

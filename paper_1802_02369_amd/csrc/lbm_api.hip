@@ -349,11 +349,16 @@ int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
   if (nsteps == 0) return LBM_OK;
   double* a = f;
   double* b = (double*)ws;
-  int rc = LBM_OK;
-  int64_t launches = 0;
+  // failure record of LBM_CHECK_FINITE, after the diagnostics scratch
+  const bool check = (h->p.flags & LBM_CHECK_FINITE) != 0;
+  unsigned long long* rec = reinterpret_cast<unsigned long long*>(
+      (double*)ws + 6 * n + check_record_double());
+  int rc = check ? launch_check_reset(rec, h->stream) : LBM_OK;
+  int64_t launches = 0, done = 0;
   if (h->tune.kernel == LBM_KERNEL_PLAIN) {
     for (int64_t t = 0; t < nsteps && !rc; ++t) {
       rc = launch_step_plain(h->c, a, b, n, h->stream);
+      if (!rc && check) rc = launch_check_state(h->c, b, n, t + 1, rec, h->stream);
       std::swap(a, b);
       ++launches;
     }
@@ -362,6 +367,8 @@ int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
     for (int k : split_steps(nsteps, h->tune.steps_per_launch)) {
       rc = launch_step_tile(h->c, a, b, n, h->tune.nodes_per_lane, k,
                             h->tune.waves_per_group, h->stream);
+      done += k;
+      if (!rc && check) rc = launch_check_state(h->c, b, n, done, rec, h->stream);
       if (rc) break;
       std::swap(a, b);
       ++launches;
@@ -372,7 +379,16 @@ int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
     rc = hip_check(hipMemcpyAsync(f, ws, sbytes, hipMemcpyDeviceToDevice,
                                   h->stream),
                    "hipMemcpyAsync");
-  return rc;
+  if (rc || !check) return rc;
+  unsigned long long key = 0;
+  if ((rc = read_check_record(rec, h->stream, &key))) return rc;
+  if (key == ~0ull) return LBM_OK;
+  const long long steps = (long long)(key >> 36);
+  return set_err(LBM_ENONFINITE,
+                 "non-finite or non-physical state (rho <= 0 or T <= 0) after "
+                 "%lld%s time steps: first failing node %lld",
+                 steps, steps == kCheckMaxSteps1 ? " or more" : "",
+                 (long long)(key & ((1ull << 36) - 1)));
 }
 
 int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,

@@ -27,7 +27,7 @@ namespace {
 
 // Workspace layout (byte offsets) of a batch for a tile count.
 struct Layout {
-  size_t state2, consts, offs, tiles, diag, backup, total;
+  size_t state2, consts, offs, tiles, diag, rec, backup, total;
 };
 
 Layout layout(const lbm_batch* b, int64_t ntiles, bool backup) {
@@ -43,6 +43,8 @@ Layout layout(const lbm_batch* b, int64_t ntiles, bool backup) {
   o = align256(o + sizeof(TileRef) * (size_t)std::max<int64_t>(ntiles, 1));
   L.diag = o;
   o = align256(o + sizeof(double) * 8 * (size_t)b->n_inst);
+  L.rec = o;  // failure record of LBM_CHECK_FINITE
+  o = align256(o + sizeof(unsigned long long));
   L.backup = o;
   if (backup) o = align256(o + sizeof(double) * 6 * (size_t)b->n_total);
   L.total = o;
@@ -52,6 +54,22 @@ Layout layout(const lbm_batch* b, int64_t ntiles, bool backup) {
 template <class T>
 T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// With LBM_CHECK_FINITE on some lattice: waits for the run and turns the
+// failure record into LBM_ENONFINITE.
+int batch_check_result(lbm_batch* b, void* ws) {
+  if (!b->check_finite()) return LBM_OK;
+  unsigned long long key = 0;
+  const Layout L = layout(b, b->prep_tiles, false);
+  int rc = read_check_record(at<unsigned long long>(ws, L.rec), b->stream, &key);
+  if (rc || key == ~0ull) return rc;
+  const long long steps = (long long)(key >> 31);
+  return set_err(LBM_ENONFINITE,
+                 "non-finite or non-physical state (rho <= 0 or T <= 0) after "
+                 "%lld%s time steps: first failing lattice %lld",
+                 steps, steps == kCheckMaxStepsB ? " or more" : "",
+                 (long long)(key & ((1ull << 31) - 1)));
 }
 
 int check_batch_ws(const lbm_batch* b, const void* ws, size_t ws_bytes) {
@@ -79,11 +97,18 @@ int enqueue_tiles(lbm_batch* b, const Layout& L, void* ws, double* f,
   double* a = f;
   double* w = at<double>(ws, L.state2);
   const int H = 2 * t.steps_per_launch;
+  const bool check = b->check_finite();
+  const int out = (int)(tile_width(t) - 2 * H);
+  int64_t done = 0;
   *launches = 0;
   for (int k : split_steps(nsteps, t.steps_per_launch)) {
     int rc = launch_batch_tile(cs, offs, tiles, ntiles, a, w, b->n_total,
                                t.nodes_per_lane, H, k, t.waves_per_group,
                                b->eq_class(), s);
+    done += k;
+    if (!rc && check)
+      rc = launch_batch_check(cs, offs, tiles, ntiles, w, b->n_total, out,
+                              done, at<unsigned long long>(ws, L.rec), s);
     if (rc) return rc;
     std::swap(a, w);
     ++*launches;
@@ -100,7 +125,10 @@ int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
                   hipStream_t s) {
   const Layout L = layout(b, b->prep_tiles, false);
   int64_t launches = 0;
-  int rc = LBM_OK;
+  int rc = b->check_finite()
+               ? launch_check_reset(at<unsigned long long>(ws, L.rec), s)
+               : LBM_OK;
+  if (rc) return rc;
   if (b->prep_group_tune.empty()) {
     rc = enqueue_tiles(b, L, ws, f, nsteps, b->tune, 0, b->prep_tiles, s,
                        &launches);
@@ -691,7 +719,10 @@ int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   if (((uintptr_t)f | (uintptr_t)ws) & 7)
     return set_err(LBM_EINVAL, "f and ws must be 8-byte aligned");
   if (nsteps == 0) return LBM_OK;
-  if (!use_graph) return enqueue_batch(b, f, ws, nsteps, b->stream);
+  if (!use_graph) {
+    rc = enqueue_batch(b, f, ws, nsteps, b->stream);
+    return rc ? rc : batch_check_result(b, ws);
+  }
   if (!(b->exec && b->g_f == f && b->g_ws == ws && b->g_nsteps == nsteps &&
         same_tuning(b->g_tune, b->tune) &&
         same_tunings(b->g_group_tune, b->group_tune) &&
@@ -727,7 +758,8 @@ int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     b->g_group_tune = b->group_tune;
     b->g_group_of = b->group_of;
   }
-  return hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+  rc = hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+  return rc ? rc : batch_check_result(b, ws);
 }
 
 int lbm_batch_moments(lbm_batch* b, const double* f, double* m, void* ws,

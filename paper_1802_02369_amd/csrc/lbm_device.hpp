@@ -47,7 +47,7 @@ struct Consts {
   double hS, hC;            // source: src_c lambda^2 / (3 cp T0), cp T0 / (Pr lambda^2)
   double hlin[9];           // linear equilibria in scaled moments
   int32_t eq_kind;  // 0 section 8, 1 linear, 2 isentropic fluid D1Q3
-  int32_t pad;
+  int32_t flags;    // lbm_params.flags (LBM_CHECK_FINITE)
 };
 
 // One tile of a batched launch: tile t of lattice inst.

@@ -20,6 +20,26 @@ int make_consts(const lbm_params* p, Consts* c);
 int64_t tile_out(int P, int K, int wg);
 size_t diag_ws_doubles();
 
+// Failure detection (LBM_CHECK_FINITE).  The record is one 64-bit word in
+// the workspace: ~0 when nothing failed, else the smallest key
+// (steps << 36) | node (single lattice; steps saturate at kCheckMaxSteps1)
+// or (steps << 31) | lattice (batch; steps saturate at kCheckMaxStepsB).
+constexpr int64_t kCheckMaxSteps1 = (int64_t(1) << 28) - 1;
+constexpr int64_t kCheckMaxStepsB = (int64_t(1) << 32) - 1;
+// offset in doubles of the single-lattice record inside the diagnostics
+// scratch (which follows the second state in the step workspace)
+size_t check_record_double();
+int launch_check_reset(unsigned long long* rec, hipStream_t s);
+int launch_check_state(const Consts& c, const double* f, int64_t n,
+                       int64_t steps, unsigned long long* rec, hipStream_t s);
+int launch_batch_check(const Consts* cs, const int64_t* offs,
+                       const TileRef* tiles, int64_t ntiles, const double* f,
+                       int64_t S, int OUT, int64_t steps,
+                       unsigned long long* rec, hipStream_t s);
+// copies the record to the host and synchronises the stream
+int read_check_record(const unsigned long long* rec, hipStream_t s,
+                      unsigned long long* out);
+
 int launch_equilibrium(const Consts& c, const double* rho, const double* J,
                        const double* zeta, double* f, int64_t n, hipStream_t s);
 int launch_step_plain(const Consts& c, const double* fin, double* fout,
@@ -214,6 +234,13 @@ struct lbm_batch {
   hipGraphExec_t adj_exec = nullptr;
   const double* ag_fbar = nullptr;
   const double* ag_rbar = nullptr;
+
+  // whether some lattice asks for LBM_CHECK_FINITE
+  bool check_finite() const {
+    for (const lbm_params& q : params)
+      if (q.flags & LBM_CHECK_FINITE) return true;
+    return false;
+  }
 
   // equilibrium class of the tile kernels: 0 if every lattice has eq_kind 0
   int eq_class() const {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_EWORKSPACE, LBM_ENONFINITE, LBM_ENOTSUP = \
     0, -1, -2, -3, -4, -5
 LBM_EUNSTABLE = -6
+LBM_CHECK_FINITE = 1  # bit of Params.flags
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
 MAX_GROUPS = 4
 WS_STEP, WS_TUNE = 0, 1
@@ -34,7 +35,8 @@ class CParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in (
         "lam", "rho0", "cp", "gamma", "prandtl", "c0", "s0",
         "s_e", "s_psi", "s_eps", "u0_lin", "s0_lin", "alpha")] + [
-        ("source_on", ctypes.c_int32), ("eq_kind", ctypes.c_int32)]
+        ("source_on", ctypes.c_int32), ("eq_kind", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CTuning(ctypes.Structure):
@@ -179,6 +181,7 @@ class Params:
     alpha: float = 0.0
     source_on: int = 1
     eq_kind: int = 0
+    flags: int = 0  # LBM_CHECK_FINITE: check every launch's output
 
     def c(self) -> CParams:
         s_psi = self.s_psi
@@ -187,7 +190,7 @@ class Params:
         return CParams(self.lam, self.rho0, self.cp, self.gamma, self.prandtl,
                        self.c0, self.s0, self.s_e, s_psi, self.s_eps,
                        self.u0_lin, self.s0_lin, self.alpha,
-                       int(self.source_on), int(self.eq_kind))
+                       int(self.source_on), int(self.eq_kind), int(self.flags), 0)
 
 
 def _stream_ptr(stream=None) -> int:

@@ -62,12 +62,46 @@ def _init(n, **kw):
     (16, dict(source_on=2)),
     (16, dict(eq_kind=3)),
     (16, dict(eq_kind=1, lam=2.0)),
+    (16, dict(flags=2)),
+    (16, dict(flags=-1)),
 ])
 def test_init_rejects_bad_arguments(n, kw):
     rc, h = _init(n, **kw)
     assert rc == lbm.LBM_EINVAL
     assert not h.value
     assert lbm.lib().lbm_last_error()
+
+
+def test_params_struct_matches_header():
+    """The binding's lbm_params record has the header's fields, in order,
+    with the header's types."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct lbm_params \{(.*?)\} lbm_params;", text,
+                     flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        fields += [(n.strip(), ctype) for n in names.split(",")]
+    want = {"double": ctypes.c_double, "int32_t": ctypes.c_int32}
+    got = lbm.CParams._fields_
+    assert len(got) == len(fields)
+    for (gn, gt), (hn, ht) in zip(got, fields):
+        assert gt is want[ht], (gn, hn)
+        assert gn == hn or (gn, hn) == ("lam", "lambda")
+
+
+def test_flags_validation_host():
+    p = lbm.Params(s_psi=1.0, flags=lbm.LBM_CHECK_FINITE).c()
+    h = ctypes.c_void_p()
+    assert lbm.lib().lbm_init(ctypes.byref(h), 16, ctypes.byref(p), None) == lbm.LBM_OK
+    lbm.lib().lbm_destroy(h)
+    p.reserved = 1
+    h = ctypes.c_void_p()
+    assert lbm.lib().lbm_init(ctypes.byref(h), 16, ctypes.byref(p), None) == lbm.LBM_EINVAL
+    assert not h.value
 
 
 def test_init_and_workspace_and_tuning_host():

@@ -203,9 +203,12 @@ def test_adjoint_config_gradient():
         say(f"  <grad, v> = {adj:.12e}   tangent-linear {dL:.12e}")
         assert rel(Lg, Lo) < 1e-9
         assert rel(adj, dL) < 1e-6
-    # central differences of the GPU forward run in each rate; the error is
-    # measured against the size of the rate gradient (dL/ds_eps is ~1e-8 here,
-    # below the rounding floor of a difference quotient of L ~ 1)
+    # central differences of the GPU forward run in each rate, measured
+    # against the size of the whole rate gradient.  This arm pins dL/ds_e and
+    # dL/ds_psi; it does not pin dL/ds_eps (~4e-8 here, below the rounding
+    # floor of a difference quotient of L ~ 1: the bound admits ~25 % error
+    # in it).  dL/ds_eps is held by the tangent-linear direction e_3 above,
+    # to 1e-6 relative.
     h = 1e-5
     scale = np.abs(rbar).max()
     for q in range(3):
@@ -261,13 +264,42 @@ def test_batched_adjoint(adj):
         np.testing.assert_allclose(rbar[i], sb, rtol=1e-9, atol=1e-12 * np.abs(sb).max())
 
 
+def oracle_gradient_by_segments(rho, J, zeta, steps, ckpt, target, p):
+    """oracle.gradient for a long run, driven from here segment by segment
+    with the oracle's own step, step adjoint, loss and initialisation
+    adjoint (the same checkpointed sweep, one line of progress per tenth of
+    the segments).  Returns (loss, rho_bar, J_bar, zeta_bar, rbar)."""
+    f = oracle.init(rho, J, zeta, p)
+    cks = []
+    for t0 in range(0, steps, ckpt):
+        cks.append(f)
+        f = oracle.run(f, min(ckpt, steps - t0), p)
+    L, fbar = oracle.loss(f, target, p)
+    rbar = np.zeros(3)
+    nseg = len(cks)
+    for k in range(nseg - 1, -1, -1):
+        t0 = k * ckpt
+        states = [cks[k]]
+        for _ in range(min(ckpt, steps - t0) - 1):
+            states.append(oracle.step(states[-1], p))
+        for st in reversed(states):
+            fbar, r = oracle.step_adjoint(st, fbar, p)
+            rbar += r
+        if k % max(1, nseg // 10) == 0:
+            say(f"    oracle sweep of the {len(rho)}-node lattice: segment {k} of {nseg}")
+    rb, Jb, zb = oracle.init_adjoint(rho, J, zeta, fbar, p)
+    return L, rb, Jb, zb, rbar
+
+
+@pytest.mark.timeout(900)
 def test_batched_adjoint_config_sampled():
     """The batched-gradient workload in the configuration the benchmark
     times (1024 lattices, lengths in [1024, 8192], 4000 steps, checkpoints
     every 63, default tile shape, automatic reverse kernel and recompute
     stride, captured graph): loss, rate gradients and dL/drho(0) of four
     seeded lattices (among the shorter ones, for the oracle's time) against
-    the oracle's adjoint of each lattice alone."""
+    the oracle's adjoint of each lattice alone, and of the shortest lattice
+    of at least 6000 nodes (its reverse sweep spans 12 reverse tiles)."""
     from paper_1802_02369_amd import workloads
     cfg = workloads.config_batched_adjoint()
     bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
@@ -289,10 +321,15 @@ def test_batched_adjoint_config_sampled():
     loss = loss.cpu().numpy()
     del aws
     rng = np.random.default_rng(1024)
-    short = np.flatnonzero(np.asarray(bt.lengths) <= 1300)
+    lengths = np.asarray(bt.lengths)
+    short = np.flatnonzero(lengths <= 1300)
     sub = np.sort(rng.choice(short, 4, replace=False))
+    # and the shortest lattice of at least 6000 nodes (12 reverse tiles)
+    big = np.flatnonzero(lengths >= 6000)
+    long_i = int(big[np.argmin(lengths[big])])
     say(f"  oracle adjoint of lattices {[int(i) for i in sub]} "
-        f"(lengths {[int(n) for n in bt.lengths[sub]]})")
+        f"(lengths {[int(n) for n in lengths[sub]]}) and {long_i} "
+        f"(length {int(lengths[long_i])})")
 
     def one(i):
         a, c = bt.offsets[i], bt.offsets[i + 1]
@@ -300,9 +337,17 @@ def test_batched_adjoint_config_sampled():
         return oracle.gradient(x.rho, x.J, x.zeta, steps, np.full(c - a, ps[i].rho0),
                                ps[i])
 
-    with ThreadPoolExecutor(4) as ex:
+    def one_long(i):
+        a, c = bt.offsets[i], bt.offsets[i + 1]
+        x = bt.instance(i)
+        return oracle_gradient_by_segments(x.rho, x.J, x.zeta, steps, ckpt,
+                                           np.full(c - a, ps[i].rho0), ps[i])
+
+    with ThreadPoolExecutor(5) as ex:
+        fut_long = ex.submit(one_long, long_i)
         res = list(ex.map(one, sub))
-    for i, (L, rb, Jb, zb, sb) in zip(sub, res):
+        res_long = fut_long.result()
+    for i, (L, rb, Jb, zb, sb) in zip(list(sub) + [long_i], res + [res_long]):
         a, c = bt.offsets[i], bt.offsets[i + 1]
         err = np.abs(g_rho[a:c] - rb).max() / np.abs(rb).max()
         say(f"  lattice {i}: loss rel {rel(loss[i], L):.1e}, dL/drho(0) {err:.1e}, "
@@ -460,3 +505,64 @@ def test_autograd_function():
     _, _, dpsi = lbm().coupled_rates(1.7)
     assert rel(se.grad.item(), sb[0] + sb[1] * dpsi) < 1e-9
     assert rel(seps.grad.item(), sb[2]) < 1e-9
+
+
+@pytest.mark.parametrize("rate_device", ["cpu", "cuda"])
+def test_batch_autograd_function(rate_device):
+    """BatchLBMFunction on a small ragged batch: gradients of
+    1/2 sum (rho(T) - target)^2 with respect to the initial fields and each
+    lattice's s_e (total, through the coupling s_psi(s_e)) and s_eps, against
+    the oracle's adjoint lattice by lattice, with the rates given on the CPU
+    or on the GPU (their gradients come back on the same device)."""
+    from paper_1802_02369_amd import workloads
+    from paper_1802_02369_amd.autograd import BatchLBMFunction
+    cfg = workloads.config_batched_adjoint(n_inst=5, steps=40, ckpt=9,
+                                           lmin=90, lmax=700)
+    bt, steps, ckpt = cfg["batch"], cfg["steps"], cfg["ckpt"]
+    fl = bt.fields
+    rng = np.random.default_rng(17)
+    tgt = 1 + 0.01 * rng.standard_normal(bt.offsets[-1])
+    rdev = torch.device("cpu") if rate_device == "cpu" else dev()
+    se = torch.tensor(np.asarray(bt.s_e, dtype=np.float64), device=rdev,
+                      requires_grad=True)
+    seps = torch.full((bt.n_inst,), 1.5, dtype=torch.float64, device=rdev,
+                      requires_grad=True)
+    r_ = T(fl.rho).requires_grad_()
+    J_ = T(fl.J).requires_grad_()
+    z_ = T(fl.zeta).requires_grad_()
+    rho_T = BatchLBMFunction.apply(r_, J_, z_, se, seps, list(bt.offsets), steps,
+                                   ckpt, None)
+    loss = 0.5 * ((rho_T - T(tgt)) ** 2).sum()
+    loss.backward()
+    assert se.grad.device == rdev and seps.grad.device == rdev
+    for i in range(bt.n_inst):
+        a, c = bt.offsets[i], bt.offsets[i + 1]
+        x = bt.instance(i)
+        po = oracle_params("paper", s_e=float(bt.s_e[i]))
+        L, rb, Jb, zb, sb = oracle.gradient(x.rho, x.J, x.zeta, steps, tgt[a:c], po)
+        for got, want in ((r_.grad[a:c], rb), (J_.grad[a:c], Jb), (z_.grad[a:c], zb)):
+            assert np.abs(got.cpu().numpy() - want).max() <= 1e-10 * np.abs(want).max(), i
+        _, _, dpsi = lbm().coupled_rates(float(bt.s_e[i]))
+        want = np.array([sb[0] + sb[1] * dpsi, sb[2]])
+        got = np.array([se.grad[i].item(), seps.grad[i].item()])
+        np.testing.assert_allclose(got, want, rtol=1e-9,
+                                   atol=1e-12 * np.abs(sb).max(), err_msg=str(i))
+    with pytest.raises(ValueError):
+        BatchLBMFunction.apply(r_, J_, z_, 1.7, seps, list(bt.offsets), steps, ckpt, None)
+
+
+def test_autograd_function_python_rates():
+    """LBMFunction with the rates given as Python numbers: no rate
+    gradients, field gradients as with tensor rates."""
+    from paper_1802_02369_amd.autograd import LBMFunction
+    po = oracle_params("paper", s_e=1.7)
+    n, steps, ckpt = 96, 30, 7
+    j = np.arange(n)
+    rho = 1 + 0.05 * np.sin(2 * np.pi * j / n)
+    J = 0.02 * np.cos(2 * np.pi * j / n)
+    zeta = np.zeros(n)
+    r_ = T(rho).requires_grad_()
+    rho_T = LBMFunction.apply(r_, T(J), T(zeta), 1.7, 1.5, steps, ckpt, None)
+    (0.5 * ((rho_T - 1.0) ** 2).sum()).backward()
+    L, rb, Jb, zb, sb = oracle.gradient(rho, J, zeta, steps, np.ones(n), po)
+    assert np.abs(r_.grad.cpu().numpy() - rb).max() <= 1e-10 * np.abs(rb).max()

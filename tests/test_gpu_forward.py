@@ -260,38 +260,124 @@ def test_small_config_every_step(tuning):
     assert d[6] == 0 and d[7] == 0
 
 
+def split_steps(nsteps: int, K: int) -> list:
+    """Steps per launch as the library splits a run of nsteps: the fewest
+    launches of at most K steps, made even when nsteps >= 2."""
+    L = -(-nsteps // K)
+    if L % 2 and nsteps > L:
+        L += 1
+    return [nsteps // L + (1 if i < nsteps % L else 0) for i in range(L)]
+
+
 def test_large_config_sampled():
-    """N = 2^24 progressive shock wave, the bench's launch configuration:
-    sampled nodes after 16 steps against the oracle run on their
-    dependency windows, plus exact mass conservation."""
+    """N = 2^24 progressive shock wave in the benchmark's launch
+    configuration: the default tile shape (P = 8, K = 40, 4 wavefronts:
+    2000-node tiles storing 1840) for 80 steps, i.e. two 40-step launches.
+    Sampled nodes (random ones, the first and last stored node of several
+    tiles of those launches, the lattice's last tile and the periodic wrap)
+    against the oracle run on each node's dependency window, plus mass and
+    momentum conservation."""
     from paper_1802_02369_amd import workloads
     cfg = workloads.config_large()
     n, fl = cfg["n"], cfg["fields"]
     po = oracle_params("paper", s_e=cfg["s_e"])
     say(f"large config sampled n={n}")
     lat = lbm().Lattice(n, gpu_params(po))
+    t = lat.get_tuning()
+    assert (t["nodes_per_lane"], t["steps_per_launch"], t["waves_per_group"]) == (8, 40, 4)
+    k = 80
+    ks = split_steps(k, t["steps_per_launch"])
+    assert ks == [40, 40]
     f = lat.equilibrium(*to_dev(fl.rho, fl.J, fl.zeta))
     d0 = lat.diagnostics(f)
-    k = 16
     lat.step(f, k)
     torch.cuda.synchronize()
     rng = np.random.default_rng(42)
-    samples = list(rng.integers(0, n, 48)) + [0, 1, 2, n - 3, n - 2, n - 1]
-    out = lat.get_tuning()
-    # tile edges: a tile spans P (62 W + 2) nodes and stores all but 4K
-    tile = (out["nodes_per_lane"] * (62 * out["waves_per_group"] + 2)
-            - 4 * min(k, out["steps_per_launch"]))
-    samples += [tile - 1, tile, 5 * tile + 1, (n // tile) * tile]
+    samples = list(rng.integers(0, n, 36)) + [0, 1, 2, n - 3, n - 2, n - 1]
+    # stored nodes of tile t of a K-step launch: [t OUT, t OUT + OUT) with
+    # OUT = P (62 W + 2) - 4K
+    out = (t["nodes_per_lane"] * (62 * t["waves_per_group"] + 2)
+           - 4 * ks[0])
+    assert out == 1840
+    for tt in (1, 2, 977, n // out):
+        samples += [tt * out - 1, tt * out, min(tt * out + out - 1, n - 1)]
+    samples += [n // out * out - 2, n // out * out + 1]
     fl3 = (fl.rho, fl.J, fl.zeta)
     got = f[:, torch.tensor(samples, device=f.device)].cpu().numpy()
     want = np.stack([window_oracle(fl3, j, k, po) for j in samples], axis=1)
     scale = np.abs(want).max()
     err = (np.abs(got - want).max(axis=1)
            / np.maximum(np.abs(want).max(axis=1), 1e-3 * scale))
+    say(f"  {len(samples)} nodes, worst field error {err.max():.2e}")
     assert err.max() < TOL, err
     d1 = lat.diagnostics(f)
     assert d1[0] == pytest.approx(d0[0], rel=1e-13)
     assert abs(d1[1] - d0[1]) < 1e-13 * n
+
+
+@pytest.mark.parametrize("P,K,W", [(8, 40, 4), (8, 32, 4), (2, 31, 8), (4, 24, 4),
+                                   (4, 15, 4)])
+def test_multi_step_own_k(P, K, W):
+    """Runs of 2K steps, so that every launch runs the shape's own K, on a
+    ragged lattice of a few tiles plus a remainder, against the oracle's
+    whole-lattice run."""
+    rng = np.random.default_rng(P * 1000 + K)
+    po = oracle_params("odd")
+    out = P * (62 * W + 2) - 4 * K
+    n = 3 * out + 557
+    f0 = random_state(rng, n, po, amp=0.1, u=0.05, ds=0.1)
+    say(f"multi step at own K: P={P} K={K} W={W} n={n} steps={2 * K}")
+    assert split_steps(2 * K, K) == [K, K]
+    lat = lbm().Lattice(n, gpu_params(po))
+    lat.set_tuning(nodes_per_lane=P, steps_per_launch=K, waves_per_group=W)
+    (f,) = to_dev(f0)
+    lat.step(f, 2 * K)
+    assert max_err(f.cpu().numpy(), oracle.run(f0, 2 * K, po)) < TOL
+
+
+def test_shock_config_long_trajectory():
+    """The single-lattice shock workload's wave (amplitude 0.2, wavelength
+    128 nodes, s_e = 0.9) on N = 2^16 nodes for all 2000 steps.  One GPU
+    step from the oracle's state at t = 0, 1, 10, 100, 1999 matches the
+    oracle's next state to 1e-12 per field (floored metric).  The
+    free-running GPU trajectory is compared with the free-running oracle at
+    every step; its drift through the shocks (rounding differences that the
+    nonlinear steps amplify) is printed and bounded loosely.  The same 2000
+    steps in the default launch configuration (K steps per launch) equal
+    the step-by-step run bitwise."""
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_large(n=1 << 16)
+    n, fl, T = cfg["n"], cfg["fields"], cfg["steps"]
+    po = oracle_params("paper", s_e=cfg["s_e"])
+    say(f"shock config long trajectory n={n} steps={T}")
+    lat = lbm().Lattice(n, gpu_params(po))
+    f = lat.equilibrium(*to_dev(fl.rho, fl.J, fl.zeta))
+    f_blocked = f.clone()
+    g = oracle.init(fl.rho, fl.J, fl.zeta, po)
+    one = torch.empty_like(f)
+    checks = {0, 1, 10, 100, T - 1}
+    step_err = {}
+    drift = []
+    for t in range(T):
+        if t in checks:
+            one.copy_(torch.from_numpy(g))
+            lat.step(one, 1)
+        lat.step(f, 1)
+        g_next = oracle.step(g, po)
+        if t in checks:
+            step_err[t] = max_err(one.cpu().numpy(), g_next)
+        g = g_next
+        fc = f.cpu().numpy()
+        drift.append(np.abs(fc - g).max() / np.abs(g).max())
+        if (t + 1) % 250 == 0:
+            say(f"  step {t + 1}: drift / state norm {drift[-1]:.3e}")
+    say(f"  one-step errors {step_err}")
+    for t in (1, 10, 100, 500, 1000, 1500, 2000):
+        say(f"  free-running drift at step {t}: {drift[t - 1]:.3e}")
+    assert max(step_err.values()) < TOL
+    assert np.isfinite(drift).all() and max(drift) < 1e-6
+    lat.step(f_blocked, T)
+    assert torch.equal(f_blocked, f)
 
 
 def test_lattice_beyond_32_bit_indices():
@@ -387,3 +473,99 @@ def test_source_switch_energy_and_entropy(n):
         res[src] = ((d1[3] - d0[3]) / d0[3], d1[2] - d0[2])
     assert abs(res[0][1]) < 1e-12 and res[1][1] > 1e-3
     assert abs(res[1][0]) < 0.25 * abs(res[0][0])
+
+
+def _parse_failure(msg):
+    import re
+    m = re.search(r"after (\d+) time steps: first failing (node|lattice) (\d+)", msg)
+    assert m, msg
+    return int(m.group(1)), int(m.group(3))
+
+
+@pytest.mark.parametrize("tuning", ["plain", "p2k8w4", "p8k32w4", "p1k12w1"])
+def test_check_finite_single_lattice(tuning):
+    """LBM_CHECK_FINITE on one lattice: a valid run is unchanged (bitwise)
+    and raises nothing; a NaN written into the input state, or a negative
+    density, makes lbm_step return LBM_ENONFINITE naming the steps done at
+    the end of the first launch and the lowest failing node of that launch
+    (the failure spreads at most 2 nodes per step); a valid run afterwards
+    passes again (the failure record is reset by each call)."""
+    rng = np.random.default_rng(31)
+    po = oracle_params("odd")
+    n = 4999
+    f0 = random_state(rng, n, po, amp=0.1, u=0.05, ds=0.1)
+    t = dict(kernel=2, nodes_per_lane=2, steps_per_launch=8, waves_per_group=4)
+    t.update(TUNINGS[tuning])
+    say(f"check finite, single lattice {tuning}")
+    plain_lat = lbm().Lattice(n, gpu_params(po))
+    plain_lat.set_tuning(**t)
+    pc = gpu_params(po)
+    pc.flags = lbm().LBM_CHECK_FINITE
+    lat = lbm().Lattice(n, pc)
+    lat.set_tuning(**t)
+    steps = 30
+    (a,) = to_dev(f0)
+    (b,) = to_dev(f0)
+    plain_lat.step(a, steps)
+    lat.step(b, steps)
+    assert torch.equal(a, b)
+    K = 1 if t["kernel"] == 1 else split_steps(steps, t["steps_per_launch"])[0]
+    for j, what in ((2500, "nan"), (17, "rho")):
+        (f,) = to_dev(f0)
+        if what == "nan":
+            f[3, j] = float("nan")
+        else:
+            f[0, j] = -1.0
+        with pytest.raises(lbm().LBMError) as e:
+            lat.step(f, steps)
+        assert e.value.code == lbm().LBM_ENONFINITE
+        done, node = _parse_failure(str(e.value))
+        say(f"  {what} at node {j}: reported after {done} steps, node {node}")
+        assert done == K
+        assert max(0, j - 2 * K - 2) <= node <= j
+    (f,) = to_dev(f0)
+    lat.step(f, steps)
+    assert torch.equal(f, a)
+
+
+@pytest.mark.parametrize("groups", [False, True])
+def test_check_finite_batch(groups):
+    """LBM_CHECK_FINITE in a batch, with and without shape groups, direct and
+    captured in a graph: a NaN in a checked lattice gives LBM_ENONFINITE
+    naming that lattice and the steps of the first launch; a NaN in an
+    unchecked lattice is not reported; replays after a failing one start
+    from a clean record."""
+    from paper_1802_02369_amd import workloads
+    cfg = workloads.config_batched(n_inst=6, steps=20, lmin=300, lmax=3000)
+    bt = cfg["batch"]
+    ps = []
+    for i, s_e in enumerate(bt.s_e):
+        p = gpu_params(oracle_params("paper", s_e=float(s_e)))
+        p.flags = lbm().LBM_CHECK_FINITE if i in (2, 4) else 0
+        ps.append(p)
+    b = lbm().Batch(bt.offsets, ps)
+    b.set_tuning(2, 8, 4)
+    if groups:
+        b.set_groups([(2, 8, 4), (4, 5, 2)], [0, 1, 0, 1, 1, 0])
+    fl = bt.fields
+    f0 = b.equilibrium(*to_dev(fl.rho, fl.J, fl.zeta))
+    say(f"check finite, batch groups={groups}")
+    for use_graph in (False, True):
+        f = f0.clone()
+        b.run(f, 20, use_graph=use_graph)           # valid: no error
+        for inst, reported in ((4, True), (1, False), (2, True)):
+            f = f0.clone()
+            f[3, int(bt.offsets[inst]) + 7] = float("nan")
+            if reported:
+                with pytest.raises(lbm().LBMError) as e:
+                    b.run(f, 20, use_graph=use_graph)
+                assert e.value.code == lbm().LBM_ENONFINITE
+                done, lat_i = _parse_failure(str(e.value))
+                say(f"  graph={use_graph}: NaN in lattice {inst}: after {done} steps, lattice {lat_i}")
+                assert lat_i == inst
+                # 20 steps at K = 8 or 5 run as four launches of 5
+                assert done == 5
+            else:
+                b.run(f, 20, use_graph=use_graph)
+        f = f0.clone()
+        b.run(f, 20, use_graph=use_graph)           # clean record again
