@@ -545,8 +545,11 @@ def test_batch_autograd_function(rate_device):
         _, _, dpsi = lbm().coupled_rates(float(bt.s_e[i]))
         want = np.array([sb[0] + sb[1] * dpsi, sb[2]])
         got = np.array([se.grad[i].item(), seps.grad[i].item()])
+        # dL/ds_eps is ~1e-5 of dL/ds_e here: a sum of much larger terms
+        # whose rounding depends on the summation order, hence the bound
+        # relative to the whole rate gradient
         np.testing.assert_allclose(got, want, rtol=1e-9,
-                                   atol=1e-12 * np.abs(sb).max(), err_msg=str(i))
+                                   atol=1e-10 * np.abs(sb).max(), err_msg=str(i))
     with pytest.raises(ValueError):
         BatchLBMFunction.apply(r_, J_, z_, 1.7, seps, list(bt.offsets), steps, ckpt, None)
 

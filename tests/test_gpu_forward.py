@@ -342,7 +342,8 @@ def test_shock_config_long_trajectory():
     oracle's next state to 1e-12 per field (floored metric).  The
     free-running GPU trajectory is compared with the free-running oracle at
     every step; its drift through the shocks (rounding differences that the
-    nonlinear steps amplify) is printed and bounded loosely.  The same 2000
+    nonlinear steps carry) is printed and must stay within 1e-12 of the
+    state norm (measured: 6.4e-14 after 2000 steps).  The same 2000
     steps in the default launch configuration (K steps per launch) equal
     the step-by-step run bitwise."""
     from paper_1802_02369_amd import workloads
@@ -375,7 +376,7 @@ def test_shock_config_long_trajectory():
     for t in (1, 10, 100, 500, 1000, 1500, 2000):
         say(f"  free-running drift at step {t}: {drift[t - 1]:.3e}")
     assert max(step_err.values()) < TOL
-    assert np.isfinite(drift).all() and max(drift) < 1e-6
+    assert np.isfinite(drift).all() and max(drift) < TOL
     lat.step(f_blocked, T)
     assert torch.equal(f_blocked, f)
 
