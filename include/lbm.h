@@ -211,6 +211,25 @@ LBM_API int lbm_set_equilibrium(lbm_handle* h, const double* rho, const double* 
 LBM_API int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
                      int64_t nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_step
+ * without a workspace argument.  The second state and the reduction scratch
+ * live in one fixed device array of the library, of
+ * 8 (6 LBM_NOALLOC_MAX_NODES + 8256) bytes (about 48 MiB), which each device
+ * the library runs on holds until the process ends; the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).  Lattices of
+ * more than LBM_NOALLOC_MAX_NODES nodes are rejected with LBM_EINVAL.  All
+ * calls on one device share that array: calls that overlap in time on one
+ * device (other threads, other streams, or kernels still running from an
+ * earlier call on another stream) race and give wrong results; calls on one
+ * stream are ordered and safe.  The array keeps the last call's contents;
+ * nothing in it needs to start at zero (each launch writes every node of
+ * the state it produces, and the failure record of LBM_CHECK_FINITE is reset
+ * by a kernel at the start of each call).  Otherwise as lbm_step, with the
+ * same results bitwise. */
+#define LBM_NOALLOC_MAX_NODES (1 << 20)
+LBM_API int lbm_step_noalloc(lbm_handle* h, double* f, int64_t nsteps);
+
 /* Macroscopic moments of a state: m (device, 6*n doubles) = M f_d at every
  * node, in the order rho, J, zeta, e, psi, eps (eq. M-d1q3q3). */
 LBM_API int lbm_moments(lbm_handle* h, const double* f, double* m);

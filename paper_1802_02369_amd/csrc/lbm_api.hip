@@ -6,6 +6,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -169,6 +170,92 @@ double spectral_radius(const cplx (&A0)[6][6]) {
   for (int i = 0; i < 6; ++i)
     for (int j = 0; j < 6; ++j) nrm = std::max(nrm, std::abs(A[i][j]));
   return std::exp(logs + (nrm > 0.0 ? std::log(nrm) * inv_n : -INFINITY));
+}
+
+}  // namespace
+
+namespace {
+
+// The time steps of lbm_step once its arguments are checked: ws holds the
+// second state (6 n doubles), then the diagnostics scratch with the failure
+// record of LBM_CHECK_FINITE.
+int step_run(lbm_handle* h, double* f, double* ws, int64_t nsteps) {
+  const int64_t n = h->n;
+  const size_t sbytes = (size_t)(6 * n) * sizeof(double);
+  double* a = f;
+  double* b = ws;
+  // failure record of LBM_CHECK_FINITE, after the diagnostics scratch
+  const bool check = (h->p.flags & LBM_CHECK_FINITE) != 0;
+  unsigned long long* rec = reinterpret_cast<unsigned long long*>(
+      ws + 6 * n + check_record_double());
+  int rc = check ? launch_check_reset(rec, h->stream) : LBM_OK;
+  int64_t launches = 0, done = 0;
+  if (h->tune.kernel == LBM_KERNEL_PLAIN) {
+    for (int64_t t = 0; t < nsteps && !rc; ++t) {
+      rc = launch_step_plain(h->c, a, b, n, h->stream);
+      if (!rc && check) rc = launch_check_state(h->c, b, n, t + 1, rec, h->stream);
+      std::swap(a, b);
+      ++launches;
+    }
+  } else {
+    // An even number of launches leaves the result in f without a copy.
+    for (int k : split_steps(nsteps, h->tune.steps_per_launch)) {
+      rc = launch_step_tile(h->c, a, b, n, h->tune.nodes_per_lane, k,
+                            h->tune.waves_per_group, h->stream);
+      done += k;
+      if (!rc && check) rc = launch_check_state(h->c, b, n, done, rec, h->stream);
+      if (rc) break;
+      std::swap(a, b);
+      ++launches;
+    }
+  }
+  if (rc) return rc;
+  if (launches & 1)
+    rc = hip_check(hipMemcpyAsync(f, ws, sbytes, hipMemcpyDeviceToDevice,
+                                  h->stream),
+                   "hipMemcpyAsync");
+  if (rc || !check) return rc;
+  unsigned long long key = 0;
+  if ((rc = read_check_record(rec, h->stream, &key))) return rc;
+  if (key == ~0ull) return LBM_OK;
+  const long long steps = (long long)(key >> 36);
+  return set_err(LBM_ENONFINITE,
+                 "non-finite or non-physical state (rho <= 0 or T <= 0) after "
+                 "%lld%s time steps: first failing node %lld",
+                 steps, steps == kCheckMaxSteps1 ? " or more" : "",
+                 (long long)(key & ((1ull << 36) - 1)));
+}
+
+// Scratch of lbm_step_noalloc: the second state and the diagnostics scratch
+// of a lattice of up to LBM_NOALLOC_MAX_NODES nodes, as one device array
+// that every device the library runs on holds until the process ends.  Host
+// code never uses its name as an address (on the host it names a stand-in):
+// noalloc_scratch takes each device's own address from hipGetSymbolAddress
+// once, with that device current.
+constexpr size_t kNoAllocDoubles = (size_t)6 * LBM_NOALLOC_MAX_NODES + 8192 + 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(double** out) {
+  int dev = 0;
+  int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_err(LBM_ENOTSUP, "device %d beyond the %d the library tracks", dev,
+                   kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                   "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
 }
 
 }  // namespace
@@ -347,48 +434,26 @@ int lbm_step(lbm_handle* h, double* f, void* ws, size_t ws_bytes,
   if (overlaps(f, sbytes, ws, ws_bytes))
     return set_err(LBM_EINVAL, "f and ws overlap");
   if (nsteps == 0) return LBM_OK;
-  double* a = f;
-  double* b = (double*)ws;
-  // failure record of LBM_CHECK_FINITE, after the diagnostics scratch
-  const bool check = (h->p.flags & LBM_CHECK_FINITE) != 0;
-  unsigned long long* rec = reinterpret_cast<unsigned long long*>(
-      (double*)ws + 6 * n + check_record_double());
-  int rc = check ? launch_check_reset(rec, h->stream) : LBM_OK;
-  int64_t launches = 0, done = 0;
-  if (h->tune.kernel == LBM_KERNEL_PLAIN) {
-    for (int64_t t = 0; t < nsteps && !rc; ++t) {
-      rc = launch_step_plain(h->c, a, b, n, h->stream);
-      if (!rc && check) rc = launch_check_state(h->c, b, n, t + 1, rec, h->stream);
-      std::swap(a, b);
-      ++launches;
-    }
-  } else {
-    // An even number of launches leaves the result in f without a copy.
-    for (int k : split_steps(nsteps, h->tune.steps_per_launch)) {
-      rc = launch_step_tile(h->c, a, b, n, h->tune.nodes_per_lane, k,
-                            h->tune.waves_per_group, h->stream);
-      done += k;
-      if (!rc && check) rc = launch_check_state(h->c, b, n, done, rec, h->stream);
-      if (rc) break;
-      std::swap(a, b);
-      ++launches;
-    }
-  }
+  return step_run(h, f, (double*)ws, nsteps);
+}
+
+int lbm_step_noalloc(lbm_handle* h, double* f, int64_t nsteps) {
+  if (!h || !f) return set_err(LBM_EINVAL, "NULL argument");
+  if (nsteps < 0) return set_err(LBM_EINVAL, "nsteps must be >= 0");
+  if (h->n > LBM_NOALLOC_MAX_NODES)
+    return set_err(LBM_EINVAL,
+                   "lbm_step_noalloc: n = %lld exceeds LBM_NOALLOC_MAX_NODES = %d "
+                   "(its scratch is a fixed device array); use lbm_step with a "
+                   "workspace", (long long)h->n, (int)LBM_NOALLOC_MAX_NODES);
+  if ((uintptr_t)f & 7) return set_err(LBM_EINVAL, "f must be 8-byte aligned");
+  double* ws = nullptr;
+  int rc = noalloc_scratch(&ws);
   if (rc) return rc;
-  if (launches & 1)
-    rc = hip_check(hipMemcpyAsync(f, ws, sbytes, hipMemcpyDeviceToDevice,
-                                  h->stream),
-                   "hipMemcpyAsync");
-  if (rc || !check) return rc;
-  unsigned long long key = 0;
-  if ((rc = read_check_record(rec, h->stream, &key))) return rc;
-  if (key == ~0ull) return LBM_OK;
-  const long long steps = (long long)(key >> 36);
-  return set_err(LBM_ENONFINITE,
-                 "non-finite or non-physical state (rho <= 0 or T <= 0) after "
-                 "%lld%s time steps: first failing node %lld",
-                 steps, steps == kCheckMaxSteps1 ? " or more" : "",
-                 (long long)(key & ((1ull << 36) - 1)));
+  if (overlaps(f, (size_t)(6 * h->n) * sizeof(double), ws,
+               kNoAllocDoubles * sizeof(double)))
+    return set_err(LBM_EINVAL, "f overlaps the library's scratch");
+  if (nsteps == 0) return LBM_OK;
+  return step_run(h, f, ws, nsteps);
 }
 
 int lbm_diagnostics(lbm_handle* h, const double* f, void* ws, size_t ws_bytes,

@@ -22,6 +22,7 @@ LBM_EUNSTABLE = -6
 LBM_CHECK_FINITE = 1  # bit of Params.flags
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
 MAX_GROUPS = 4
+NOALLOC_MAX_NODES = 1 << 20
 WS_STEP, WS_TUNE = 0, 1
 
 
@@ -77,6 +78,7 @@ def lib():
             "lbm_get_tuning": ([_vp, ctypes.POINTER(CTuning)], ctypes.c_int),
             "lbm_set_equilibrium": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
             "lbm_step": ([_vp, _vp, _vp, _sz, _i64], ctypes.c_int),
+            "lbm_step_noalloc": ([_vp, _vp, _i64], ctypes.c_int),
             "lbm_moments": ([_vp, _vp, _vp], ctypes.c_int),
             "lbm_diagnostics": ([_vp, _vp, _vp, _sz, _dp], ctypes.c_int),
             "lbm_autotune": ([_vp, _vp, _vp, _sz, _i64, ctypes.c_char_p,
@@ -273,6 +275,13 @@ class Lattice:
         check(lib().lbm_step(self._h, _dev_ptr(f, 6 * self.n, "f"),
                              _dev_ptr(ws, None, "ws"), ws.numel() * 8,
                              int(nsteps)))
+        return f
+
+    def step_noalloc(self, f: torch.Tensor, nsteps: int):
+        """Advances f in place by nsteps time steps without a workspace
+        (lbm_step_noalloc: the library's fixed scratch, n <= NOALLOC_MAX_NODES)."""
+        check(lib().lbm_step_noalloc(self._h, _dev_ptr(f, 6 * self.n, "f"),
+                                     int(nsteps)))
         return f
 
     def moments(self, f: torch.Tensor) -> torch.Tensor:
