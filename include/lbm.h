@@ -306,18 +306,21 @@ LBM_API int lbm_equilibrium_adjoint(lbm_handle* h, const double* rho, const doub
 LBM_API int lbm_moments_adjoint(lbm_handle* h, const double* mbar, double* fbar,
                                 void* ws, size_t ws_bytes);
 /* Kernel of the reverse sweep.  LBM_KERNEL_BLOCKED keeps dL/df in registers
- * for up to K reverse steps of a tile of 64 P W nodes (P = 2 with W the
- * forward's wavefronts, or P W / 2 for P = 4, 8, at most 4; P = 1, W = 1
- * after a forward at P = 1; halo 2K, or 2K + 2 at recompute stride 2),
- * reading only the stored recomputed forward states, the next one
- * prefetched while the current step computes (about 2.4x the arithmetic of
- * a forward step per node-step).  LBM_KERNEL_PLAIN runs one reverse step
- * per launch, one node per thread (HBM-bound, 144 B per node-step).  LBM_KERNEL_AUTO (the
+ * for up to K reverse steps of a tile of P (62 W + 2) nodes, neighbouring
+ * wavefronts sharing two lanes that are refreshed through LDS before each
+ * step (one workgroup barrier per step; P = 2 with W the forward's
+ * wavefronts, or P W / 2 for P = 4, 8, at most 4; P = 1, W = 1 after a
+ * forward at P = 1; halo 2K, or 2K + 2 at recompute stride 2), reading only
+ * the stored recomputed forward states, the next one prefetched while the
+ * current step computes (about 2.4x the arithmetic of a forward step per
+ * node-step).  LBM_KERNEL_PLAIN runs one reverse step per launch, one node
+ * per thread (HBM-bound, 144 B per node-step).  LBM_KERNEL_AUTO (the
  * default) takes the blocked kernel wherever its tiles can hold the halo,
- * else the one-step kernel.  A halo too wide for P = 2 tiles (4K >= 128 W)
- * falls back to P = 4 with 8 wavefronts; lbm_forward_ckpt rejects with
- * LBM_ENOTSUP an explicit LBM_KERNEL_BLOCKED whose halo leaves even those
- * no interior (4K >= 2048).  Takes effect at the next lbm_forward_ckpt. */
+ * else the one-step kernel.  A halo too wide for P = 2 tiles
+ * (4K >= 2 (62 W + 2)) falls back to P = 4 with 8 wavefronts; lbm_forward_ckpt
+ * rejects with LBM_ENOTSUP an explicit LBM_KERNEL_BLOCKED whose halo leaves
+ * even those no interior (4K >= 1992).  Takes effect at the next
+ * lbm_forward_ckpt. */
 LBM_API int lbm_set_adjoint_kernel(lbm_handle* h, int kernel);
 /* Stride of the recomputed forward states that the blocked reverse sweep
  * stores: 1 keeps every state of a checkpoint segment; 2 keeps the even ones

@@ -59,6 +59,7 @@ struct NodeFwd {
   double e_eq, psi_eq, eps_eq;
 };
 
+template <int EQ>
 __device__ __forceinline__ void node_forward(const Consts& c, double f0,
                                              double fp, double fm, double g0,
                                              double gp, double gm, NodeFwd& q) {
@@ -71,7 +72,7 @@ __device__ __forceinline__ void node_forward(const Consts& c, double f0,
   q.eps = c.meps * (sg - 2.0 * g0);
   lbm::thermo(c, q.rho, q.J, q.zeta, q.u, q.s, q.X, q.T, q.ir);
   q.w = lbm::recip(q.T);
-  if (c.eq_kind == 0) {
+  if (EQ == 0 || c.eq_kind == 0) {
     const double p = q.rho * c.r * q.T;
     q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
     q.psi_eq = q.zeta * q.u;
@@ -89,7 +90,9 @@ __device__ __forceinline__ void node_forward(const Consts& c, double f0,
 
 // Reverse of the equilibria (iv) and of the equation of state, given the
 // adjoints of e_eq, psi_eq, eps_eq and extra adjoints of u and T (from the
-// source); adds to the adjoints of rho, J, zeta.
+// source); adds to the adjoints of rho, J, zeta.  EQ = 0 compiles the
+// equilibria of section 8 only; EQ = -1 selects them from c.eq_kind.
+template <int EQ>
 __device__ __forceinline__ void equilibria_adjoint(const Consts& c,
                                                    const NodeFwd& q, double eb,
                                                    double pb, double xb,
@@ -98,7 +101,7 @@ __device__ __forceinline__ void equilibria_adjoint(const Consts& c,
                                                    double& zb) {
   double sb = 0.0, Xb = 0.0;
   const double ir = q.ir;
-  if (c.eq_kind == 0) {
+  if (EQ == 0 || c.eq_kind == 0) {
     // eps_eq = eps_c rho X + e_eq s
     rb += c.eps_c * q.X * xb;
     Xb += c.eps_c * q.rho * xb;
@@ -166,8 +169,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
   const double* B = fbn + off;
   // Phase A: forward recomputation at the node, streamed adjoint.
   NodeFwd q;
-  node_forward(c, F[j], F[S + j], F[2 * S + j], F[3 * S + j], F[4 * S + j],
-               F[5 * S + j], q);
+  node_forward<-1>(c, F[j], F[S + j], F[2 * S + j], F[3 * S + j], F[4 * S + j],
+                   F[5 * S + j], q);
   su[t] = q.u;
   sT[t] = q.T;
   const double a0 = B[j], ap = B[S + jr], am = B[2 * S + jm];
@@ -208,8 +211,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
     r1 += (q.psi_eq - q.psi) * psisb;
     r2 += (q.eps_eq - q.eps) * epssb;
     // (iv)^T and the equation of state
-    equilibria_adjoint(c, q, c.s_e * esb, c.s_psi * psisb, c.s_eps * epssb,
-                       ub, Tb, rb, Jb, zb);
+    equilibria_adjoint<-1>(c, q, c.s_e * esb, c.s_psi * psisb, c.s_eps * epssb,
+                           ub, Tb, rb, Jb, zb);
     // (ii)^T: fbar(t) = M^T mbar
     double* O = fbo + off;
     O[j] = c.rho0 * rb - 2.0 * c.me * eb;
@@ -239,20 +242,29 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_step(
 
 // ------------------------------------------------ register-tile adjoint --
 //
-// K reverse steps of a tile of 64*P*WG nodes per launch (halo H = 2K on
-// each side, or 2K + 2 when only every second forward state is stored, K
-// the forward's steps per launch; its own tile table).  fbar stays in
+// K reverse steps of a tile per launch, on its own tile table (halo H = 2K
+// on each side, or 2K + 2 when only every second forward state is stored, K
+// the forward's steps per launch).  The tile has the forward kernels'
+// layout: WG wavefronts, lane l of wavefront w holding the P consecutive
+// nodes from tile index 62 P w + P l, so that neighbouring wavefronts share
+// two lanes (lane 0 of w mirrors lane 62 of w - 1, lane 63 of w mirrors
+// lane 1 of w + 1) and a tile spans P (62 WG + 2) nodes.  fbar stays in
 // registers; each step takes the forward state f(t) of the tile (coalesced
-// loads issued during the previous step, through LDS, or recomputed from
-// the stored state before: see k_adjoint_tile) and does:
+// loads issued during the previous step, through LDS, or recomputed from the
+// stored state before: see k_adjoint_tile) and does, with neighbours inside
+// the wavefront through DPP only:
 //   A  u, T (and rho, s, X) of every node from f(t);
-//   -  streamed adjoint: fbar*_+(k) = fbar_+(k+1), fbar*_-(k) = fbar_-(k-1),
-//      with u, T of the outside neighbours (DPP, LDS between wavefronts);
+//   -  streamed adjoint: fbar*_+(k) = fbar_+(k+1), fbar*_-(k) = fbar_-(k-1);
 //   B  each node's source adjoint zbar and the terms it sends its neighbours,
 //      A_k = 2 c rho w du zbar and B_k = 2 c (cp/Pr) rho w^2 dT zbar;
 //   C  the gather of A, B from both neighbours and the node-local chain.
-// Rate partials are summed over the tile's output nodes [H, W - H) only (the
-// output regions of the tiles partition each lattice).
+// One step has radius 2 in fbar(t+1) and f(t), so the wrong values the
+// outermost lanes get from their missing neighbours reach two nodes into
+// the wavefront: the mirror lanes (P >= 2 nodes) absorb them, and before
+// every step the mirror lanes take fbar (and a recomputed f(t)) from the
+// lanes they mirror, through LDS with one workgroup barrier.  Rate partials
+// are summed over the tile's output nodes [H, W - H) that the wavefront owns
+// (the output regions of the tiles partition each lattice).
 template <int P>
 __device__ __forceinline__ void shift_left(double (&a)[P], double in_right) {
 #pragma unroll
@@ -266,11 +278,10 @@ __device__ __forceinline__ void shift_right(double (&a)[P], double in_left) {
   a[0] = in_left;
 }
 
-template <int P, int WG>
-__device__ __forceinline__ void adjoint_tile_step(
+template <int P, int EQ>
+__device__ __forceinline__ void adjoint_step_local(
     const Consts& c, const double (&ft)[6][P], double (&fb)[6][P],
-    Boundary* bnd, double (*bab)[4], int lane, int wave, const bool (&own)[P],
-    double& r0, double& r1, double& r2) {
+    const bool (&own)[P], double& r0, double& r1, double& r2) {
   // A: forward quantities of each node
   double rho[P], u[P], s[P], X[P], T[P], ir[P];
 #pragma unroll
@@ -280,78 +291,28 @@ __device__ __forceinline__ void adjoint_tile_step(
     const double zeta = c.mz * (ft[3][k] + (ft[4][k] + ft[5][k]));
     lbm::thermo(c, rho[k], J, zeta, u[k], s[k], X[k], T[k], ir[k]);
   }
-  if (WG > 1) {
-    if (lane == 0) {
-      bnd[wave].v[0] = fb[1][0];
-      bnd[wave].v[1] = fb[4][0];
-      bnd[wave].v[2] = u[0];
-      bnd[wave].v[3] = T[0];
-    }
-    if (lane == 63) {
-      bnd[wave].v[4] = fb[2][P - 1];
-      bnd[wave].v[5] = fb[5][P - 1];
-      bnd[wave].v[6] = u[P - 1];
-      bnd[wave].v[7] = T[P - 1];
-    }
-    __syncthreads();
-  }
-  double fpR = lbm::from_right(fb[1][0]), gpR = lbm::from_right(fb[4][0]);
-  double fmL = lbm::from_left(fb[2][P - 1]), gmL = lbm::from_left(fb[5][P - 1]);
-  double uL = lbm::from_left(u[P - 1]), TL = lbm::from_left(T[P - 1]);
-  double uR = lbm::from_right(u[0]), TR = lbm::from_right(T[0]);
-  if (WG > 1) {
-    if (lane == 63 && wave < WG - 1) {
-      fpR = bnd[wave + 1].v[0];
-      gpR = bnd[wave + 1].v[1];
-      uR = bnd[wave + 1].v[2];
-      TR = bnd[wave + 1].v[3];
-    }
-    if (lane == 0 && wave > 0) {
-      fmL = bnd[wave - 1].v[4];
-      gmL = bnd[wave - 1].v[5];
-      uL = bnd[wave - 1].v[6];
-      TL = bnd[wave - 1].v[7];
-    }
-  }
+  const double fpR = lbm::from_right(fb[1][0]), gpR = lbm::from_right(fb[4][0]);
+  const double fmL = lbm::from_left(fb[2][P - 1]), gmL = lbm::from_left(fb[5][P - 1]);
+  const double uL = lbm::from_left(u[P - 1]), TL = lbm::from_left(T[P - 1]);
+  const double uR = lbm::from_right(u[0]), TR = lbm::from_right(T[0]);
   // streamed adjoint (transpose of (viii)): fb now holds fbar*
   shift_left<P>(fb[1], fpR);
   shift_left<P>(fb[4], gpR);
   shift_right<P>(fb[2], fmL);
   shift_right<P>(fb[5], gmL);
   // B: source adjoint and what each node sends to its neighbours
-  double A[P], B[P];
+  double A[P], B[P], w[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) {
     const double ul = k == 0 ? uL : u[k - 1], ur = k == P - 1 ? uR : u[k + 1];
     const double tl = k == 0 ? TL : T[k - 1], tr = k == P - 1 ? TR : T[k + 1];
-    const double w = lbm::recip(T[k]);
+    w[k] = lbm::recip(T[k]);
     const double Zb = c.ga * (fb[3][k] + fb[4][k] + fb[5][k]);
-    A[k] = 2.0 * c.src_c * rho[k] * w * (ur - ul) * Zb;
-    B[k] = 2.0 * c.src_c * c.cPr * rho[k] * w * w * (tr - tl) * Zb;
+    A[k] = 2.0 * c.src_c * rho[k] * w[k] * (ur - ul) * Zb;
+    B[k] = 2.0 * c.src_c * c.cPr * rho[k] * w[k] * w[k] * (tr - tl) * Zb;
   }
-  if (WG > 1) {
-    if (lane == 0) {
-      bab[wave][0] = A[0];
-      bab[wave][1] = B[0];
-    }
-    if (lane == 63) {
-      bab[wave][2] = A[P - 1];
-      bab[wave][3] = B[P - 1];
-    }
-    __syncthreads();
-  }
-  double AL = lbm::from_left(A[P - 1]), BL = lbm::from_left(B[P - 1]);
-  double AR = lbm::from_right(A[0]), BR = lbm::from_right(B[0]);
-  if (WG > 1) {
-    if (lane == 0 && wave > 0) {
-      AL = bab[wave - 1][2];
-      BL = bab[wave - 1][3];
-    }
-    if (lane == 63 && wave < WG - 1) {
-      AR = bab[wave + 1][0];
-      BR = bab[wave + 1][1];
-    }
-  }
+  const double AL = lbm::from_left(A[P - 1]), BL = lbm::from_left(B[P - 1]);
+  const double AR = lbm::from_right(A[0]), BR = lbm::from_right(B[0]);
   // C: gather and node-local reverse chain
 #pragma unroll
   for (int k = 0; k < P; ++k) {
@@ -372,8 +333,8 @@ __device__ __forceinline__ void adjoint_tile_step(
     q.X = X[k];
     q.T = T[k];
     q.ir = ir[k];
-    q.w = lbm::recip(T[k]);
-    if (c.eq_kind == 0) {
+    q.w = w[k];
+    if (EQ == 0 || c.eq_kind == 0) {
       const double p = q.rho * c.r * q.T;
       q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
       q.psi_eq = q.zeta * q.u;
@@ -412,8 +373,8 @@ __device__ __forceinline__ void adjoint_tile_step(
       r1 += (q.psi_eq - q.psi) * psisb;
       r2 += (q.eps_eq - q.eps) * epssb;
     }
-    equilibria_adjoint(c, q, c.s_e * esb, c.s_psi * psisb, c.s_eps * epssb,
-                       ub, Tb, rb, Jb, zb);
+    equilibria_adjoint<EQ>(c, q, c.s_e * esb, c.s_psi * psisb, c.s_eps * epssb,
+                           ub, Tb, rb, Jb, zb);
     fb[0][k] = c.rho0 * rb - 2.0 * c.me * eb;
     fb[1][k] = c.rho0 * rb + c.mJ * Jb + c.me * eb;
     fb[2][k] = c.rho0 * rb - c.mJ * Jb + c.me * eb;
@@ -423,122 +384,69 @@ __device__ __forceinline__ void adjoint_tile_step(
   }
 }
 
-// One forward step of the reverse kernel's tile (wavefronts side by side,
-// without the forward kernels' mirror lanes), for the states the reverse
-// sweep recomputes from the state before: the node arithmetic of the forward
-// kernels (collide_local, source_g, streaming) in the same order, so the
-// result is bitwise the state they produce.  Neighbours inside a wavefront
-// come through DPP; the edge nodes of neighbouring wavefronts through LDS:
-// their u, T (xa) before the sources and their outgoing populations (xb)
-// before the streaming.  The tile's two outer nodes on each side are wrong
-// afterwards (they have no neighbour), which the halo absorbs.
+// Mirror lanes of the reverse tile before a step: lanes 1 and 62 publish
+// fbar (and, after a recomputation, f(t)) in `edge` (one buffer of a
+// double-buffered pair, as in the forward kernels), then lane 0 takes lane
+// 62 of the wavefront to its left and lane 63 lane 1 of the one to its
+// right.  with_ft is the same for every wavefront of the workgroup.
 template <int P, int WG>
-__device__ __forceinline__ void tile_step_x(const Consts& c, double (&f)[6][P],
-                                            double (*xa)[4], double (*xb)[4],
-                                            int lane, int wave) {
-  double uA, TA, rwA, wA;  // node P-1, collided first
-  lbm::collide_local<-1>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
-                         f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
-  double um, Tm, rwm, wm;  // node k (the one whose source is next)
-  lbm::collide_local<-1>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0],
-                         f[5][0], um, Tm, rwm, wm);
-  double ul = lbm::from_left(uA), Tl = lbm::from_left(TA);
-  double uR = lbm::from_right(um), TR = lbm::from_right(Tm);
-  if (WG > 1) {
-    if (lane == 0) {
-      xa[wave][0] = um;
-      xa[wave][1] = Tm;
-    }
-    if (lane == 63) {
-      xa[wave][2] = uA;
-      xa[wave][3] = TA;
-    }
-    __syncthreads();
-    if (lane == 0 && wave > 0) {
-      ul = xa[wave - 1][2];
-      Tl = xa[wave - 1][3];
-    }
-    if (lane == 63 && wave < WG - 1) {
-      uR = xa[wave + 1][0];
-      TR = xa[wave + 1][1];
-    }
-  }
+__device__ __forceinline__ void adjoint_mirror_refresh(
+    double (&fb)[6][P], double (&ft)[6][P], bool with_ft,
+    double (*edge)[2][12 * P], int lane, int wave) {
+  if (lane == 1 || lane == 62) {
+    double* d = edge[wave][lane == 62];
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    double ur, Tr, rwr = 0.0, wr = 0.0;
-    if (k + 1 < P - 1) {
-      lbm::collide_local<-1>(c, f[0][k + 1], f[1][k + 1], f[2][k + 1],
-                             f[3][k + 1], f[4][k + 1], f[5][k + 1], ur, Tr, rwr,
-                             wr);
-    } else if (k + 1 == P - 1) {
-      ur = uA;
-      Tr = TA;
-      rwr = rwA;
-      wr = wA;
-    } else {
-      ur = uR;
-      Tr = TR;
-    }
-    const double add = lbm::source_g(c, rwm, wm, ul, ur, Tl, Tr);
-    f[3][k] += add;
-    f[4][k] += add;
-    f[5][k] += add;
-    ul = um;
-    Tl = Tm;
-    um = ur;
-    Tm = Tr;
-    rwm = rwr;
-    wm = wr;
-  }
-  // (viii) streaming
-  double fpL = lbm::from_left(f[1][P - 1]), gpL = lbm::from_left(f[4][P - 1]);
-  double fmR = lbm::from_right(f[2][0]), gmR = lbm::from_right(f[5][0]);
-  if (WG > 1) {
-    if (lane == 63) {
-      xb[wave][0] = f[1][P - 1];
-      xb[wave][1] = f[4][P - 1];
-    }
-    if (lane == 0) {
-      xb[wave][2] = f[2][0];
-      xb[wave][3] = f[5][0];
-    }
-    __syncthreads();
-    if (lane == 0 && wave > 0) {
-      fpL = xb[wave - 1][0];
-      gpL = xb[wave - 1][1];
-    }
-    if (lane == 63 && wave < WG - 1) {
-      fmR = xb[wave + 1][2];
-      gmR = xb[wave + 1][3];
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) d[q * P + k] = fb[q][k];
+    if (with_ft) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int k = 0; k < P; ++k) d[6 * P + q * P + k] = ft[q][k];
     }
   }
-  shift_right<P>(f[1], fpL);
-  shift_right<P>(f[4], gpL);
-  shift_left<P>(f[2], fmR);
-  shift_left<P>(f[5], gmR);
+  __syncthreads();
+  const bool left = lane == 0 && wave > 0, right = lane == 63 && wave < WG - 1;
+  if (left || right) {
+    const double* e = left ? edge[wave - 1][1] : edge[wave + 1][0];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) fb[q][k] = e[q * P + k];
+    if (with_ft) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int k = 0; k < P; ++k) ft[q][k] = e[6 * P + q * P + k];
+    }
+  }
 }
 
 // Reverse steps i_hi-1 down to i_lo of a checkpoint segment.  E = 1: the
 // forward state of every step i is stored, ck (i = 0) or seg + (i-1)*SD.
 // E = 2: only the even ones are (state i at seg + (i/2-1)*SD); an odd step's
-// state is recomputed from the one before, which then serves the next (even)
-// step, so each such pair of steps loads one state.  The prefetch of a pair's
-// state is issued during the previous pair.  If the launch's first step is
-// odd, its recomputed state is wrong at the two outer nodes of each side,
-// which costs the halo two more nodes (H >= 2K + 2).
-template <int P, int WG, int E>
+// state is recomputed from the one before (tile_step, the forward kernels'
+// node arithmetic in the same order: bitwise the state they store), which
+// then serves the next (even) step, so each such pair of steps loads one
+// state.  The prefetch of a pair's state is issued during the previous
+// pair.  If the launch's first step is odd, its recomputed state is wrong at
+// the two outer nodes of each side, which costs the halo two more nodes
+// (H >= 2K + 2).  EQ = 0: every lattice of the table has the equilibria of
+// section 8.
+template <int P, int WG, int E, int EQ>
 __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const TileRef* __restrict__ tiles, int64_t ntiles,
     const double* __restrict__ ck, const double* __restrict__ seg, int64_t SD,
     int i_lo, int i_hi, const double* __restrict__ fbn,
     double* __restrict__ fbo, int64_t S, int H, double* __restrict__ rslots) {
-  constexpr int WW = 64 * P;
-  constexpr int W = WG * WW;
+  static_assert(P > 1 || WG == 1, "P = 1 tiles have one wavefront");
+  constexpr int WW = 64 * P;   // nodes of one wavefront
+  constexpr int WS = 62 * P;   // wavefront stride in the tile
+  constexpr int W = lbm::tile_nodes(P, WG);
   __shared__ double stage[WG * (WW + 64)];
-  __shared__ Boundary bnd[WG];
-  __shared__ double bab[WG][4];
-  __shared__ double xa[E == 2 ? WG : 1][4], xb[E == 2 ? WG : 1][4];
+  __shared__ double edge[2][WG][2][12 * P];
   __shared__ double red[3][64 * WG];
   const int64_t b = blockIdx.x;
   if (b >= ntiles) return;  // uniform over the workgroup
@@ -551,14 +459,17 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   double* lds = stage + wave * (WW + 64);
   const int OUT = W - 2 * H;
   const int64_t start = (int64_t)tr.t * OUT - H;
-  const int64_t wstart = start + wave * WW;
+  const int64_t wstart = start + wave * WS;
   const bool inside = start >= 0 && start + W <= n;
   const bool small = n < W;
+  // output nodes of the tile that this wavefront owns (the mirror lanes
+  // belong to the neighbours)
+  const bool mirror = (lane == 0 && wave > 0) || (lane == 63 && wave < WG - 1);
   bool own[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) {
-    const int it = wave * WW + lane * P + k;
-    own[k] = it >= H && it < W - H && start + it < n;
+    const int it = wave * WS + lane * P + k;
+    own[k] = !mirror && it >= H && it < W - H && start + it < n;
   }
   // the segment's global indices are the same in every state
   int64_t gi[P];
@@ -576,8 +487,10 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   // this one computes
   tile_fetch<P>(state(base(i_hi - 1)), S, gi, raw);
   double fa[6][P];  // E = 2: the even state an odd step was recomputed from
+  int buf = 0;
   for (int i = i_hi - 1; i >= i_lo; --i) {
     double ft[6][P];
+    bool recomputed = false;
     if (E == 2 && (i & 1)) {
       tile_transpose<P>(lane, lds, raw, fa);
       if (i - 2 >= i_lo) tile_fetch<P>(state(base(i - 2)), S, gi, raw);
@@ -585,7 +498,8 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
       for (int q = 0; q < 6; ++q)
 #pragma unroll
         for (int k = 0; k < P; ++k) ft[q][k] = fa[q][k];
-      tile_step_x<P, WG>(c, ft, xa, xb, lane, wave);
+      tile_step<P, EQ>(c, ft);
+      recomputed = true;
     } else if (E == 2 && i < i_hi - 1) {
       // the state the odd step i + 1 was recomputed from
 #pragma unroll
@@ -596,52 +510,64 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
       tile_transpose<P>(lane, lds, raw, ft);
       if (i > i_lo) tile_fetch<P>(state(base(i - 1)), S, gi, raw);
     }
-    adjoint_tile_step<P, WG>(c, ft, fb, bnd, bab, lane, wave, own, r0, r1, r2);
+    if (WG > 1) {
+      adjoint_mirror_refresh<P, WG>(fb, ft, recomputed, edge[buf], lane, wave);
+      buf ^= 1;
+    }
+    adjoint_step_local<P, EQ>(c, ft, fb, own, r0, r1, r2);
   }
-  tile_store<P>(fbo + off, S, n, wstart, H - wave * WW, W - H - wave * WW,
-                lane, lds, fb);
+  const int lo = max(H - wave * WS, wave > 0 ? P : 0);
+  const int hi = min(W - H - wave * WS, wave < WG - 1 ? WW - P : WW);
+  tile_store<P>(fbo + off, S, n, wstart, lo, hi, lane, lds, fb);
   const int t = threadIdx.x;
   red[0][t] = r0;
   red[1][t] = r1;
   red[2][t] = r2;
   __syncthreads();
-  for (int w = 32 * WG; w > 0; w >>= 1) {
-    if (t < w) {
-      red[0][t] += red[0][t + w];
-      red[1][t] += red[1][t + w];
-      red[2][t] += red[2][t + w];
+  for (int m = 32 * WG; m > 0; m >>= 1) {
+    if (t < m) {
+      red[0][t] += red[0][t + m];
+      red[1][t] += red[1][t + m];
+      red[2][t] += red[2][t + m];
     }
     __syncthreads();
   }
   if (t < 3) rslots[3 * b + t] += red[t][0];
 }
 
-template <int P, int WG, int E>
+template <int P, int WG, int E, int EQ>
 void launch_adjoint_tile_t(const Consts* cs, const int64_t* offs,
                            const TileRef* tiles, int64_t ntiles,
                            const double* ck, const double* seg, int64_t SD,
                            int i_lo, int i_hi, const double* fbn, double* fbo,
                            int64_t S, int H, double* rslots, hipStream_t s) {
-  hipLaunchKernelGGL((k_adjoint_tile<P, WG, E>), dim3((unsigned)ntiles),
+  hipLaunchKernelGGL((k_adjoint_tile<P, WG, E, EQ>), dim3((unsigned)ntiles),
                      dim3(64 * WG), 0, s, cs, offs, tiles, ntiles, ck, seg, SD,
                      i_lo, i_hi, fbn, fbo, S, H, rslots);
 }
 
-// E: stride of the stored segment states (1, or 2 at P = 2).
-int launch_adjoint_tile(int P, int WG, int E, const Consts* cs,
+// E: stride of the stored segment states (1, or 2 at P = 2); eq: 0 when
+// every lattice has the equilibria of section 8, else -1.
+int launch_adjoint_tile(int P, int WG, int E, int eq, const Consts* cs,
                         const int64_t* offs, const TileRef* tiles,
                         int64_t ntiles, const double* ck, const double* seg,
                         int64_t SD, int i_lo, int i_hi, const double* fbn,
                         double* fbo, int64_t S, int H, double* rslots,
                         hipStream_t s) {
   if (i_hi - i_lo < 1 || 2 * (i_hi - i_lo) + (E == 2 ? 2 : 0) > H ||
-      2 * H >= 64 * P * WG)
+      2 * H >= lbm::tile_nodes(P, WG))
     return set_err(LBM_EINVAL, "bad adjoint tile geometry");
-#define LBM_ADJ_CASE(PP, WW, EE)                                              \
-  if (P == PP && WG == WW && E == EE) {                                       \
-    launch_adjoint_tile_t<PP, WW, EE>(cs, offs, tiles, ntiles, ck, seg, SD,   \
-                                      i_lo, i_hi, fbn, fbo, S, H, rslots, s); \
-    return hip_check(hipGetLastError(), "k_adjoint_tile");                    \
+#define LBM_ADJ_CASE(PP, WW, EE)                                               \
+  if (P == PP && WG == WW && E == EE) {                                        \
+    if (eq == 0)                                                               \
+      launch_adjoint_tile_t<PP, WW, EE, 0>(cs, offs, tiles, ntiles, ck, seg,   \
+                                           SD, i_lo, i_hi, fbn, fbo, S, H,     \
+                                           rslots, s);                         \
+    else                                                                       \
+      launch_adjoint_tile_t<PP, WW, EE, -1>(cs, offs, tiles, ntiles, ck, seg,  \
+                                            SD, i_lo, i_hi, fbn, fbo, S, H,    \
+                                            rslots, s);                        \
+    return hip_check(hipGetLastError(), "k_adjoint_tile");                     \
   }
   LBM_ADJ_CASE(1, 1, 1)
   LBM_ADJ_CASE(2, 1, 1)
@@ -686,7 +612,7 @@ __global__ __launch_bounds__(256) void k_equilibrium_adjoint(
     const double eb = c.fb * (0.5 * (ap + am) - a0);
     const double pb = c.gc * (bp - bm);
     const double xb = c.gb * (0.5 * (bp + bm) - b0);
-    equilibria_adjoint(c, q, eb, pb, xb, 0.0, 0.0, rb, Jb, zb);
+    equilibria_adjoint<-1>(c, q, eb, pb, xb, 0.0, 0.0, rb, Jb, zb);
     rho_b[j] = rb;
     J_b[j] = Jb;
     zeta_b[j] = zb;
@@ -779,19 +705,20 @@ struct AdjLayout {
 lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
 
 // Tile shape of the blocked reverse kernel for a forward tuning and a stride
-// E of the stored segment states.  Its tiles span 64 P W nodes (no overlap
-// between wavefronts) with halo H = 2K, or 2K + 2 at E = 2 (see
-// k_adjoint_tile).  P = 2 keeps two wavefronts per SIMD (the reverse step
-// needs about 220 VGPRs at P = 2, over 256 at P = 4), with the wavefronts
-// that give about the forward tile's width, at least the forward's and at
-// most 4: two workgroups per CU, so that one computes while the other waits
-// at the step's barriers (the 1024-lattice gradient's reverse phase took
-// 442 ms at 4 wavefronts, 472 at 8, 512 at 2); a halo too wide for those
-// tiles falls back to P = 4 with 8 wavefronts and E = 1.  A forward of one node per lane (small problems) keeps P = 1,
-// W = 1, E = 1 (about 120 VGPRs).
+// E of the stored segment states.  Its tiles span P (62 W + 2) nodes
+// (neighbouring wavefronts share two lanes) with halo H = 2K, or 2K + 2 at
+// E = 2 (see k_adjoint_tile).  P = 2 keeps two wavefronts per SIMD (the
+// reverse step needs 190-225 VGPRs at P = 2, over 256 at P = 4), with the
+// wavefronts that give about the forward tile's width, at least the
+// forward's and at most 4: two workgroups per CU, so that one computes while
+// the other waits at a step's barrier (measured with the earlier two
+// barriers per step: the 1024-lattice gradient's reverse phase took 442 ms
+// at 4 wavefronts, 472 at 8, 512 at 2); a halo too wide for those tiles
+// falls back to P = 4 with 8 wavefronts and E = 1.  A forward of one node
+// per lane (small problems) keeps P = 1, W = 1, E = 1 (about 120 VGPRs).
 struct RevShape {
   int P, W, H, E;
-  int64_t out() const { return 64 * (int64_t)P * W - 2 * (int64_t)H; }
+  int64_t out() const { return (int64_t)tile_nodes(P, W) - 2 * (int64_t)H; }
 };
 
 RevShape rev_shape(const lbm_tuning& t, int E) {
@@ -802,7 +729,7 @@ RevShape rev_shape(const lbm_tuning& t, int E) {
   RevShape r{2, std::min(4, std::max(t.waves_per_group,
                                      t.nodes_per_lane * t.waves_per_group / 2)),
              2 * K + (E == 2 ? 2 : 0), E};
-  if (2 * r.H >= 64 * 2 * r.W) r = RevShape{4, 8, 2 * K, 1};
+  if (2 * r.H >= tile_nodes(2, r.W)) r = RevShape{4, 8, 2 * K, 1};
   return r;
 }
 
@@ -1054,7 +981,8 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
     for (int64_t hi = seg_len(k); hi > 0;) {
       const int64_t lo = std::max<int64_t>(0, hi - Krec);
       const int r = launch_adjoint_tile(
-          rv.P, rv.W, rv.E, cs, offs, at<TileRef>(ws, L.rev_tiles), L.n_rev,
+          rv.P, rv.W, rv.E, b->eq_class(), cs, offs,
+          at<TileRef>(ws, L.rev_tiles), L.n_rev,
           ckpt(k), segbuf(k), (int64_t)SD, (int)lo, (int)hi, cur, oth,
           b->n_total, rv.H, slots, s);
       if (r) return r;

@@ -115,6 +115,88 @@ __device__ __forceinline__ void tile_store(double* __restrict__ fout,
   }
 }
 
+// One time step of a wavefront's nodes.  The source of node k needs u, T of
+// k-1 and k+1, so the collisions run in the order P-1, 0, 1, ..., P-2 and
+// each source is applied as soon as its right neighbour exists; only a window
+// of three nodes' (u, T) stays live besides the populations.
+template <int P, int EQ>
+__device__ __forceinline__ void tile_step(const lbm::Consts& c, double (&f)[6][P]) {
+  if constexpr (P == 1) {
+    // one node per lane: both neighbours are the adjacent lanes
+    double u, T, rw, w;
+    lbm::collide_local<EQ>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0],
+                           f[5][0], u, T, rw, w);
+    const double add =
+        lbm::source_g(c, rw, w, lbm::from_left(u), lbm::from_right(u),
+                      lbm::from_left(T), lbm::from_right(T));
+    f[3][0] += add;
+    f[4][0] += add;
+    f[5][0] += add;
+    f[1][0] = lbm::from_left(f[1][0]);
+    f[4][0] = lbm::from_left(f[4][0]);
+    f[2][0] = lbm::from_right(f[2][0]);
+    f[5][0] = lbm::from_right(f[5][0]);
+    return;
+  }
+  double uA, TA, rwA, wA;  // node P-1, collided first
+  lbm::collide_local<EQ>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
+                     f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
+  double um, Tm, rwm, wm;  // node k (the one whose source is next)
+  __builtin_amdgcn_sched_barrier(0);
+  lbm::collide_local<EQ>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0], f[5][0],
+                     um, Tm, rwm, wm);
+  double ul = lbm::from_left(uA), Tl = lbm::from_left(TA);
+  const double uR = lbm::from_right(um), TR = lbm::from_right(Tm);
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    double ur, Tr, rwr = 0.0, wr = 0.0;
+    // Keep the scheduler from interleaving the collisions of different
+    // nodes: that would hold several nodes' temporaries live at once.
+    __builtin_amdgcn_sched_barrier(0);
+    if (k + 1 < P - 1) {
+      lbm::collide_local<EQ>(c, f[0][k + 1], f[1][k + 1], f[2][k + 1], f[3][k + 1],
+                         f[4][k + 1], f[5][k + 1], ur, Tr, rwr, wr);
+    } else if (k + 1 == P - 1) {
+      ur = uA;
+      Tr = TA;
+      rwr = rwA;
+      wr = wA;
+    } else {
+      ur = uR;
+      Tr = TR;
+    }
+    const double add = lbm::source_g(c, rwm, wm, ul, ur, Tl, Tr);
+    f[3][k] += add;
+    f[4][k] += add;
+    f[5][k] += add;
+    ul = um;
+    Tl = Tm;
+    um = ur;
+    Tm = Tr;
+    rwm = rwr;
+    wm = wr;
+  }
+  // (viii) streaming: + populations move one node right, - one node left.
+  const double fpL = lbm::from_left(f[1][P - 1]);
+  const double gpL = lbm::from_left(f[4][P - 1]);
+  const double fmR = lbm::from_right(f[2][0]);
+  const double gmR = lbm::from_right(f[5][0]);
+#pragma unroll
+  for (int k = P - 1; k > 0; --k) {
+    f[1][k] = f[1][k - 1];
+    f[4][k] = f[4][k - 1];
+  }
+  f[1][0] = fpL;
+  f[4][0] = gpL;
+#pragma unroll
+  for (int k = 0; k < P - 1; ++k) {
+    f[2][k] = f[2][k + 1];
+    f[5][k] = f[5][k + 1];
+  }
+  f[2][P - 1] = fmR;
+  f[5][P - 1] = gmR;
+}
+
 // Values exchanged between neighbouring wavefronts of a workgroup each step.
 struct Boundary {
   double v[8];
