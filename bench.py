@@ -457,6 +457,8 @@ def bench_batched(torch, lbm, workloads, stream, single_glups, tuning=None,
         f"finite: {ok}")
     roof = leg_roofline("batched", g * 1e9, 0.0, "node-update",
                         None if shapes else tune)
+    if not shapes and not roof["counters_current"]:
+        roof.update(batched_roofline_from_arithmetic(bt, tune, steps, ms, g))
     # algorithmic HBM bytes: 96 per node per launch (each launch reads and
     # writes the whole state once)
     if launches:
@@ -469,6 +471,46 @@ def bench_batched(torch, lbm, workloads, stream, single_glups, tuning=None,
             "n_nodes": b.n_total, "time_steps": steps, "ms": ms,
             "tuning": tune, "groups": groups, "graph": True, "valid": ok,
             "vs_single_lattice": g / single_glups, "roofline": roof}
+
+
+def batched_roofline_from_arithmetic(bt, tune, steps, ms, glups):
+    """ALU roofline of a batched run whose tile shape has no counter run of
+    its own: the FP64 (and VALU) instructions per computed node-update of a
+    counted batched run (the same node arithmetic, whatever the tile shape)
+    times the node-updates this shape computes (its tiles, halos included)."""
+    import glob  # noqa: F401
+    import numpy as np
+    if not os.path.exists(LEG_COUNTERS):
+        return {}
+    with open(LEG_COUNTERS) as fh:
+        legs = json.load(fh).get("legs", {})
+    ref = None
+    for key, e in sorted(legs.items()):
+        if key.startswith("batched@") and e.get("computed_units") and \
+                e.get("source_hash") == source_hash(e.get("source_files", [])):
+            ref = (key, e)
+            break
+    if ref is None:
+        return {}
+    key, e = ref
+    P, K, W = (tune[k] for k in ("nodes_per_lane", "steps_per_launch",
+                                 "waves_per_group"))
+    lens = np.diff(np.asarray(bt.offsets))
+    computed = sum(lattice_lane_nodes(int(x), P, K, W) for x in lens) * steps
+    fi = e["fp64_instr"] / e["computed_units"]
+    fv = e["valu_instr"] / e["computed_units"]
+    ff = e["flops"] / e["computed_units"]
+    t = ms * 1e-3
+    ach = fi * glups * 1e9 / 1e12
+    return {"achieved": ach, "frac": ach / LANE_INSTR_PEAK_T,
+            "fp64_instr_per_unit": fi,
+            "fp64_instr_per_unit_basis": "computed node-update",
+            "arithmetic_from": key,
+            "flops": {"per_unit": ff, "achieved": ff * glups * 1e9 / 1e12,
+                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ff * glups * 1e9 / 1e12 / FP64_PEAK_TFLOPS},
+            "valu_issue_frac": fv * computed / t / (LANE_INSTR_PEAK_T * 1e12),
+            "computed_per_useful": computed / (bt.offsets[-1] * steps)}
 
 
 def bench_adjoint(torch, lbm, workloads, stream, counter_run=False):
