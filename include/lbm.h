@@ -374,6 +374,26 @@ LBM_API int lbm_batch_set_groups(lbm_batch* b, int32_t n_groups,
  * group_of (capacity n_inst) receive the assignment unless NULL. */
 LBM_API int lbm_batch_get_groups(const lbm_batch* b, int32_t* n_groups,
                                  lbm_tuning* shapes, int32_t* group_of);
+/* Resident lattices of lbm_batch_run.  With mode 1 (the default) every
+ * lattice of LBM_RESIDENT_MIN..LBM_RESIDENT_MAX nodes runs all nsteps steps
+ * inside one launch: its state is loaded once into registers (8 nodes per
+ * lane, one wavefront per 496 nodes, lattices packed into workgroups of 12
+ * wavefronts), advanced step after step with the periodic wrap and the
+ * neighbouring wavefronts' edge nodes exchanged through LDS every 4 steps,
+ * and stored once (96 bytes of HBM per node for the whole run).  That launch
+ * runs on a side stream of the batch, forked from its stream and joined back
+ * to it (also inside the graph of use_graph = 1), beside the tiled launches
+ * of the other lattices; shape groups apply to those only.  Mode 0 runs
+ * every lattice in tiles.  Results are bitwise the same in both modes.
+ * lbm_batch_autotune, called in mode 1, also times mode 0 and keeps the
+ * faster (a batch of short lattices only can fill the chip better with
+ * tiles).  Only batches whose lattices all have eq_kind 0 run lattices
+ * resident.  Takes effect at the next lbm_batch_prepare; the adjoint calls
+ * always use tiles.  LBM_EINVAL for another mode. */
+enum { LBM_RESIDENT_MIN = 16, LBM_RESIDENT_MAX = 5952 };
+LBM_API int lbm_batch_set_resident(lbm_batch* b, int mode);
+/* Number of lattices that run resident with the current mode. */
+LBM_API int64_t lbm_batch_resident_lattices(const lbm_batch* b);
 /* Total nodes n_total of the batch (0 on a bad handle). */
 LBM_API int64_t lbm_batch_total_nodes(const lbm_batch* b);
 LBM_API size_t lbm_batch_workspace_bytes(const lbm_batch* b, int kind);
@@ -406,7 +426,8 @@ LBM_API int lbm_batch_moments(lbm_batch* b, const double* f, double* m, void* ws
  * LBM_ENONFINITE if any lattice has a non-finite or non-physical node. */
 LBM_API int lbm_batch_diagnostics(lbm_batch* b, const double* f, void* ws,
                                   size_t ws_bytes, double* out);
-/* Autotuner of the batch (as lbm_autotune; calls lbm_batch_prepare). */
+/* Autotuner of the batch (as lbm_autotune; calls lbm_batch_prepare): the
+ * tile shape, shape groups, and in resident mode 1 the mode itself. */
 LBM_API int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
                                int64_t probe_steps, const char* cache_path,
                                lbm_tuning* out);

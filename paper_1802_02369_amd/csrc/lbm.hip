@@ -456,6 +456,138 @@ __global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0 && !EVE
                   K, EVERY, state_stride, first, every);
 }
 
+// Resident lattices of a batch: a periodic lattice of L nodes short enough
+// for the registers of one workgroup runs every time step of the call in one
+// launch, with no halo and no global memory traffic between the first load
+// and the last store.  The lattice is laid out as a tile that starts at
+// position -P: lane l of its wavefront w (w = 0 .. nw-1, nw = ceil(L / 62P))
+// holds positions 62 P w + P (l - 1) + k, neighbouring wavefronts sharing
+// two lanes as in the tile kernels.  Positions outside [0, L) stand for the
+// nodes their periodic image names: lane 0 of wavefront 0 holds nodes
+// L-P .. L-1 and positions L .. L+P-1 hold nodes 0 .. P-1; every P/2 steps
+// those copies and the mirror lanes are refreshed from the lanes that own
+// the nodes, through LDS with one workgroup barrier (every lattice of a
+// workgroup runs the same steps, so all its wavefronts meet at each).  A
+// step has radius 2,
+// so the wrong values that come in from beyond a copy (or from the unused
+// positions past L+P) move two nodes per step and stay inside the copy
+// until the refresh, as for the mirror lanes.  Several lattices share a
+// workgroup of kResWaves wavefronts (items[wg_first[b] .. wg_first[b+1]),
+// each on its own wavefronts); wavefronts without a lattice end at once.
+// Every node-update rounds as in the other kernels: results are bitwise
+// those of the tiled path.
+constexpr int kResWaves = lbm::kResidentWaves;
+
+template <int P>
+__device__ __forceinline__ void resident_refresh(
+    double (&f)[6][P], double (*edge)[2][6 * P], double (*wrap)[2][6 * P],
+    int lane, int wave, int lw, int nw, int w0, int L) {
+  // positions of this lane's nodes: p0 .. p0 + P - 1
+  const int p0 = 62 * P * lw + P * (lane - 1);
+  const bool owner = (lane >= 1 && lane <= 62) || (lane == 63 && lw == nw - 1);
+  if (lane == 1 || lane == 62) {
+    double* d = edge[wave][lane == 62];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) d[q * P + k] = f[q][k];
+  }
+  if (lw == 0 && lane == 1) {  // nodes 0 .. P-1
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) wrap[w0][0][q * P + k] = f[q][k];
+  }
+  if (owner && p0 + P > L - P && p0 < L) {  // nodes L-P .. L-1
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int p = p0 + k;
+      if (p >= L - P && p < L) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) wrap[w0][1][q * P + (p - (L - P))] = f[q][k];
+      }
+    }
+  }
+  __syncthreads();
+  if (lane == 0 && lw > 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[q][k] = edge[wave - 1][1][q * P + k];
+  } else if (lane == 63 && lw < nw - 1) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[q][k] = edge[wave + 1][0][q * P + k];
+  } else if (lane == 0) {  // lw == 0: nodes L-P .. L-1
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[q][k] = wrap[w0][1][q * P + k];
+  }
+  // nodes 0 .. P-1 again, after the mirror reads: positions L .. L+P-1 lie
+  // in the last wavefront, or partly in the right mirror lane of the one
+  // before it when the last holds fewer than P nodes
+  if (p0 + P > L && p0 < L + P) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int p = p0 + k;
+      if (p >= L && p < L + P) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) f[q][k] = wrap[w0][0][q * P + (p - L)];
+      }
+    }
+  }
+}
+
+// three wavefronts per SIMD: one workgroup of twelve per CU
+template <int P, int EQ>
+__global__ __launch_bounds__(64 * kResWaves, 3) void k_batch_resident(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const lbm::ResidentItem* __restrict__ items,
+    const int32_t* __restrict__ wg_first, const double* __restrict__ fin,
+    double* __restrict__ fout, int64_t S, int64_t T) {
+  constexpr int WG = kResWaves;
+  constexpr int WW = 64 * P;
+  constexpr int WS = 62 * P;
+  __shared__ double stage[WG * (WW + 64)];
+  __shared__ double edge[2][WG][2][6 * P];
+  __shared__ double wrap[2][WG][2][6 * P];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // this wavefront's lattice (uniform over the wavefront)
+  int item = -1;
+  for (int i = wg_first[blockIdx.x]; i < wg_first[blockIdx.x + 1]; ++i) {
+    const int w0 = items[i].wave0;
+    if (wave >= w0 && wave < w0 + items[i].nw) item = i;
+  }
+  if (item < 0) return;
+  const lbm::ResidentItem it = items[item];
+  const int lw = wave - it.wave0;
+  const int64_t off = offs[it.inst];
+  const int L = (int)(offs[it.inst + 1] - off);
+  const Consts c = cs[it.inst];
+  double* lds = stage + wave * (WW + 64);
+  const int64_t wstart = -P + (int64_t)lw * WS;
+  double f[6][P];
+  tile_load<P>(fin + off, S, L, wstart, false, true, lane, lds, f);
+  // every wavefront has loaded before any stores (fout may be fin)
+  __syncthreads();
+  int since = 0, buf = 0;
+  for (int64_t step = 0; step < T; ++step) {
+    tile_step<P, EQ>(c, f);
+    if (++since == P / 2 && step + 1 < T) {
+      resident_refresh<P>(f, edge[buf], wrap[buf], lane, wave, lw, it.nw,
+                          it.wave0, L);
+      buf ^= 1;
+      since = 0;
+    }
+  }
+  // owned positions 0 .. L-1: lanes 1 .. 62, and 63 in the last wavefront
+  tile_store<P>(fout + off, S, L, wstart, P, lw < it.nw - 1 ? WW - P : WW, lane,
+                lds, f);
+}
+
 // One workgroup per lattice of a batch: moments m = M f (eq. M-d1q3q3).
 __global__ __launch_bounds__(256) void k_batch_moments(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
@@ -661,6 +793,39 @@ __global__ __launch_bounds__(256) void k_batch_check(
   record_min(rec, bad ? steps_key | (unsigned long long)tr.inst : ~0ull);
 }
 
+// Checks (LBM_CHECK_FINITE) of the resident lattices, one workgroup per
+// item, those whose flags ask for it; key steps_key | inst.
+__global__ __launch_bounds__(256) void k_batch_check_lattices(
+    const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
+    const lbm::ResidentItem* __restrict__ items, const double* __restrict__ f,
+    int64_t S, unsigned long long steps_key, unsigned long long* rec) {
+  const int inst = items[blockIdx.x].inst;
+  if (!(cs[inst].flags & LBM_CHECK_FINITE)) return;  // uniform
+  const Consts c = cs[inst];
+  const int64_t off = offs[inst];
+  const int64_t n = offs[inst + 1] - off;
+  bool bad = false;
+  for (int64_t j = threadIdx.x; j < n; j += 256) bad = bad || node_fails(c, f + off, S, j);
+  record_min(rec, bad ? steps_key | (unsigned long long)inst : ~0ull);
+}
+
+// Copy of the nodes [t OUT, t OUT + OUT) of tile b's lattice from src to
+// dst, one workgroup per tile: brings back into the caller's state the
+// lattices of a launch sequence that ended in the workspace state.
+__global__ __launch_bounds__(256) void k_batch_copy_tiles(
+    const int64_t* __restrict__ offs, const lbm::TileRef* __restrict__ tiles,
+    int OUT, const double* __restrict__ src, double* __restrict__ dst,
+    int64_t S) {
+  const lbm::TileRef tr = tiles[blockIdx.x];
+  const int64_t off = offs[tr.inst];
+  const int64_t n = offs[tr.inst + 1] - off;
+  const int64_t lo = off + (int64_t)tr.t * OUT;
+  const int64_t hi = off + ((int64_t)tr.t * OUT + OUT < n ? (int64_t)tr.t * OUT + OUT : n);
+  for (int64_t j = lo + threadIdx.x; j < hi; j += 256)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dst[q * S + j] = src[q * S + j];
+}
+
 }  // namespace
 
 // ----------------------------------------------------- launch helpers ---
@@ -768,6 +933,40 @@ int launch_batch_check(const Consts* cs, const int64_t* offs,
   hipLaunchKernelGGL(k_batch_check, dim3((unsigned)ntiles), dim3(256), 0, s, cs,
                      offs, tiles, f, S, OUT, sk, rec);
   return hip_check(hipGetLastError(), "k_batch_check");
+}
+
+int launch_batch_copy_tiles(const int64_t* offs, const TileRef* tiles,
+                            int64_t ntiles, int OUT, const double* src,
+                            double* dst, int64_t S, hipStream_t s) {
+  if (ntiles <= 0) return LBM_OK;
+  hipLaunchKernelGGL(k_batch_copy_tiles, dim3((unsigned)ntiles), dim3(256), 0, s,
+                     offs, tiles, OUT, src, dst, S);
+  return hip_check(hipGetLastError(), "k_batch_copy_tiles");
+}
+
+int launch_batch_resident(const Consts* cs, const int64_t* offs,
+                          const ResidentItem* items, const int32_t* wg_first,
+                          int64_t nwg, const double* fin, double* fout,
+                          int64_t S, int64_t T, int eq, hipStream_t s) {
+  if (nwg <= 0 || T <= 0) return LBM_OK;
+  if (eq != 0)
+    return set_err(LBM_EINVAL, "resident lattices need the section-8 equilibria");
+  hipLaunchKernelGGL((k_batch_resident<kResP, 0>), dim3((unsigned)nwg),
+                     dim3(64 * kResWaves), 0, s, cs, offs, items, wg_first, fin,
+                     fout, S, T);
+  return hip_check(hipGetLastError(), "k_batch_resident");
+}
+
+int launch_batch_check_lattices(const Consts* cs, const int64_t* offs,
+                                const ResidentItem* items, int64_t nitems,
+                                const double* f, int64_t S, int64_t steps,
+                                unsigned long long* rec, hipStream_t s) {
+  if (nitems <= 0) return LBM_OK;
+  const unsigned long long sk =
+      (unsigned long long)std::min<int64_t>(steps, kCheckMaxStepsB) << 31;
+  hipLaunchKernelGGL(k_batch_check_lattices, dim3((unsigned)nitems), dim3(256), 0,
+                     s, cs, offs, items, f, S, sk, rec);
+  return hip_check(hipGetLastError(), "k_batch_check_lattices");
 }
 
 int read_check_record(const unsigned long long* rec, hipStream_t s,

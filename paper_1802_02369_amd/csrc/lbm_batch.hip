@@ -17,6 +17,9 @@
 
 using namespace lbm;
 
+static_assert(kResidentMin == LBM_RESIDENT_MIN && kResidentMax == LBM_RESIDENT_MAX,
+              "resident lattice bounds of the header");
+
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -27,7 +30,8 @@ namespace {
 
 // Workspace layout (byte offsets) of a batch for a tile count.
 struct Layout {
-  size_t state2, consts, offs, tiles, diag, rec, backup, total;
+  size_t state2, consts, offs, tiles, res_items, res_first, diag, rec, backup,
+      total;
 };
 
 Layout layout(const lbm_batch* b, int64_t ntiles, bool backup) {
@@ -41,6 +45,10 @@ Layout layout(const lbm_batch* b, int64_t ntiles, bool backup) {
   o = align256(o + sizeof(int64_t) * (size_t)(b->n_inst + 1));
   L.tiles = o;
   o = align256(o + sizeof(TileRef) * (size_t)std::max<int64_t>(ntiles, 1));
+  L.res_items = o;  // resident lattices and their workgroups
+  o = align256(o + sizeof(ResidentItem) * (size_t)b->n_inst);
+  L.res_first = o;
+  o = align256(o + sizeof(int32_t) * (size_t)(b->n_inst + 1));
   L.diag = o;
   o = align256(o + sizeof(double) * 8 * (size_t)b->n_inst);
   L.rec = o;  // failure record of LBM_CHECK_FINITE
@@ -61,7 +69,7 @@ T* at(void* ws, size_t off) {
 int batch_check_result(lbm_batch* b, void* ws) {
   if (!b->check_finite()) return LBM_OK;
   unsigned long long key = 0;
-  const Layout L = layout(b, b->prep_tiles, false);
+  const Layout L = layout(b, b->run_tiles(), false);
   int rc = read_check_record(at<unsigned long long>(ws, L.rec), b->stream, &key);
   if (rc || key == ~0ull) return rc;
   const long long steps = (long long)(key >> 31);
@@ -76,21 +84,24 @@ int check_batch_ws(const lbm_batch* b, const void* ws, size_t ws_bytes) {
   if (!b || !ws) return set_err(LBM_EINVAL, "NULL argument");
   if (b->prep_ws != ws || !same_tuning(b->prep_tune, b->tune) ||
       !same_tunings(b->prep_group_tune, b->group_tune) ||
-      b->prep_group_of != b->group_of)
+      b->prep_group_of != b->group_of ||
+      b->prep_resident_mode != b->resident_mode)
     return set_err(LBM_EINVAL,
                    "workspace not prepared for this tuning: call "
                    "lbm_batch_prepare");
-  if (ws_bytes < layout(b, b->prep_tiles, false).total)
+  if (ws_bytes < layout(b, b->run_tiles(), false).total)
     return set_err(LBM_EWORKSPACE, "workspace too small");
   return LBM_OK;
 }
 
 // Launches of nsteps steps of the tiles [first, first + ntiles) of the table
-// with tuning t on stream s (ping-pong between f and the workspace state);
-// returns the number of launches in *launches.
+// with tuning t on stream s (ping-pong between f and the workspace state).
+// An odd number of launches (nsteps = 1, or K = 1 and nsteps odd) leaves
+// the result in the workspace state: a copy of those tiles' nodes brings it
+// into f.
 int enqueue_tiles(lbm_batch* b, const Layout& L, void* ws, double* f,
                   int64_t nsteps, const lbm_tuning& t, int64_t first,
-                  int64_t ntiles, hipStream_t s, int64_t* launches) {
+                  int64_t ntiles, hipStream_t s) {
   const Consts* cs = at<Consts>(ws, L.consts);
   const int64_t* offs = at<int64_t>(ws, L.offs);
   const TileRef* tiles = at<TileRef>(ws, L.tiles) + first;
@@ -99,8 +110,7 @@ int enqueue_tiles(lbm_batch* b, const Layout& L, void* ws, double* f,
   const int H = 2 * t.steps_per_launch;
   const bool check = b->check_finite();
   const int out = (int)(tile_width(t) - 2 * H);
-  int64_t done = 0;
-  *launches = 0;
+  int64_t done = 0, launches = 0;
   for (int k : split_steps(nsteps, t.steps_per_launch)) {
     int rc = launch_batch_tile(cs, offs, tiles, ntiles, a, w, b->n_total,
                                t.nodes_per_lane, H, k, t.waves_per_group,
@@ -111,27 +121,58 @@ int enqueue_tiles(lbm_batch* b, const Layout& L, void* ws, double* f,
                               done, at<unsigned long long>(ws, L.rec), s);
     if (rc) return rc;
     std::swap(a, w);
-    ++*launches;
+    ++launches;
   }
+  if (launches & 1)
+    return launch_batch_copy_tiles(offs, tiles, ntiles, out, a, f, b->n_total, s);
   return LBM_OK;
 }
 
 // Launch sequence of a batched run on stream s.  With shape groups, group 0
 // runs on s and group g > 0 on its own stream, forked from s and joined back
 // to it (inside a graph capture the side streams join the capture).  Every
-// group makes an even number of launches when nsteps >= 2 and one when
-// nsteps = 1, so the state ends in f, or entirely in the workspace state.
+// sequence leaves its lattices' result in f.
 int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
                   hipStream_t s) {
-  const Layout L = layout(b, b->prep_tiles, false);
-  int64_t launches = 0;
+  const Layout L = layout(b, b->run_tiles(), false);
   int rc = b->check_finite()
                ? launch_check_reset(at<unsigned long long>(ws, L.rec), s)
                : LBM_OK;
   if (rc) return rc;
-  if (b->prep_group_tune.empty()) {
-    rc = enqueue_tiles(b, L, ws, f, nsteps, b->tune, 0, b->prep_tiles, s,
-                       &launches);
+  // Resident lattices: one launch for all the steps, in place in f, on a
+  // side stream forked from s and joined back before the end (also inside a
+  // graph); no tile reads or writes their nodes.
+  const int64_t nres = (int64_t)b->prep_res_items.size();
+  const int64_t nwg = nres ? (int64_t)b->prep_res_first.size() - 1 : 0;
+  if (nres) {
+    rc = hip_check(hipEventRecord(b->res_events[0], s), "hipEventRecord");
+    if (!rc)
+      rc = hip_check(hipStreamWaitEvent(b->res_stream, b->res_events[0], 0),
+                     "hipStreamWaitEvent");
+    if (rc) return rc;
+    const Consts* cs = at<Consts>(ws, L.consts);
+    const int64_t* offs = at<int64_t>(ws, L.offs);
+    const ResidentItem* items = at<ResidentItem>(ws, L.res_items);
+    rc = launch_batch_resident(cs, offs, items, at<int32_t>(ws, L.res_first), nwg,
+                               f, f, b->n_total, nsteps, b->eq_class(),
+                               b->res_stream);
+    if (!rc && b->check_finite())
+      rc = launch_batch_check_lattices(cs, offs, items, nres, f, b->n_total,
+                                       nsteps, at<unsigned long long>(ws, L.rec),
+                                       b->res_stream);
+    // join even after a failure, so that a capture ends
+    const int r1 = hip_check(hipEventRecord(b->res_events[1], b->res_stream),
+                             "hipEventRecord");
+    if (!rc) rc = r1;
+    if (rc) {
+      (void)hipStreamWaitEvent(s, b->res_events[1], 0);
+      return rc;
+    }
+  }
+  if (b->prep_tiles == 0) {
+    // every lattice is resident
+  } else if (b->prep_group_tune.empty()) {
+    rc = enqueue_tiles(b, L, ws, f, nsteps, b->tune, 0, b->prep_tiles, s);
   } else {
     const size_t ng = b->prep_group_tune.size();
     rc = hip_check(hipEventRecord(b->gevents[0], s), "hipEventRecord");
@@ -142,7 +183,7 @@ int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
       const hipStream_t sg = g == 0 ? s : b->gstreams[g - 1];
       const int64_t first = b->prep_group_first[g];
       rc = enqueue_tiles(b, L, ws, f, nsteps, b->prep_group_tune[g], first,
-                         b->prep_group_first[g + 1] - first, sg, &launches);
+                         b->prep_group_first[g + 1] - first, sg);
     }
     // join every side stream even after a failure, so that a capture ends
     for (size_t g = 1; g < ng; ++g) {
@@ -153,13 +194,12 @@ int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
       if (!rc) rc = r1 ? r1 : r2;
     }
   }
-  if (rc) return rc;
-  if (launches & 1)
-    return hip_check(hipMemcpyAsync(f, at<double>(ws, L.state2),
-                                    sizeof(double) * 6 * b->n_total,
-                                    hipMemcpyDeviceToDevice, s),
-                     "hipMemcpyAsync");
-  return LBM_OK;
+  if (nres) {
+    const int r = hip_check(hipStreamWaitEvent(s, b->res_events[1], 0),
+                            "hipStreamWaitEvent");
+    if (!rc) rc = r;
+  }
+  return rc;
 }
 
 }  // namespace
@@ -188,6 +228,7 @@ struct CacheEntry {
   lbm_tuning t{};
   std::vector<lbm_tuning> gshape;
   std::vector<double> gcost;
+  int resident = -1;  // batch entries: the resident mode the search kept
 };
 
 std::map<std::string, CacheEntry> read_cache(const char* path) {
@@ -244,6 +285,13 @@ std::map<std::string, CacheEntry> read_cache(const char* path) {
           e.gcost.clear();
         }
       }
+      // optional "resident": 0 or 1
+      const size_t rp = body.find("\"resident\"");
+      int r = -1;
+      if (rp != std::string::npos &&
+          std::sscanf(body.c_str() + rp, "\"resident\" : %d", &r) == 1 &&
+          (r == 0 || r == 1))
+        e.resident = r;
       m[key] = e;
     }
     pos = close + 1;
@@ -256,19 +304,21 @@ std::map<std::string, CacheEntry> read_cache(const char* path) {
 namespace lbm {
 
 bool tune_cache_get(const char* path, const std::string& key, lbm_tuning* t,
-                    std::vector<lbm_tuning>* gshape, std::vector<double>* gcost) {
+                    std::vector<lbm_tuning>* gshape, std::vector<double>* gcost,
+                    int* resident) {
   auto m = read_cache(path);
   auto it = m.find(key);
   if (it == m.end()) return false;
   *t = it->second.t;
   if (gshape) *gshape = it->second.gshape;
   if (gcost) *gcost = it->second.gcost;
+  if (resident && it->second.resident >= 0) *resident = it->second.resident;
   return true;
 }
 
 void tune_cache_put(const char* path, const std::string& key,
                     const lbm_tuning& t, const std::vector<lbm_tuning>* gshape,
-                    const std::vector<double>* gcost) {
+                    const std::vector<double>* gcost, int resident) {
   if (!path) return;
   auto m = read_cache(path);
   CacheEntry e;
@@ -277,6 +327,7 @@ void tune_cache_put(const char* path, const std::string& key,
     e.gshape = *gshape;
     e.gcost = *gcost;
   }
+  e.resident = resident;
   m[key] = e;
   const std::string tmp = std::string(path) + ".tmp";
   FILE* fp = std::fopen(tmp.c_str(), "w");
@@ -296,6 +347,7 @@ void tune_cache_put(const char* path, const std::string& key,
                      x.gshape[g].waves_per_group, x.gcost[g]);
       std::fprintf(fp, "]");
     }
+    if (x.resident >= 0) std::fprintf(fp, ", \"resident\": %d", x.resident);
     std::fprintf(fp, "}%s\n", ++i < m.size() ? "," : "");
   }
   std::fprintf(fp, "}\n");
@@ -354,6 +406,7 @@ double assign_groups(const lbm_batch* b, const std::vector<lbm_tuning>& shapes,
   double total = 0;
   if (of) of->assign(b->n_inst, 0);
   for (int64_t i = 0; i < b->n_inst; ++i) {
+    if (b->resident(i)) continue;  // runs in the resident launch
     double best = INFINITY;
     for (size_t g = 0; g < shapes.size(); ++g) {
       const double c = (double)b->lattice_work(i, shapes[g]) * cost[g];
@@ -530,6 +583,10 @@ int lbm_batch_init(lbm_batch** b, int64_t n_inst, const int64_t* offsets,
   x->n_total = offsets[n_inst];
   x->offsets.assign(offsets, offsets + n_inst + 1);
   x->params.assign(params, params + n_inst);
+  x->eq_cls = std::all_of(params, params + n_inst,
+                          [](const lbm_params& q) { return q.eq_kind == 0; })
+                  ? 0
+                  : -1;
   x->consts.resize(n_inst);
   for (int64_t i = 0; i < n_inst; ++i) {
     int rc = make_consts(&params[i], &x->consts[i]);
@@ -554,6 +611,9 @@ void lbm_batch_destroy(lbm_batch* b) {
     if (ev) (void)hipEventDestroy(ev);
   for (hipStream_t st : b->gstreams) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : b->gevents) (void)hipEventDestroy(ev);
+  if (b->res_stream) (void)hipStreamDestroy(b->res_stream);
+  for (hipEvent_t ev : b->res_events)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
 }
 
@@ -639,6 +699,21 @@ int lbm_batch_get_groups(const lbm_batch* b, int32_t* n_groups,
 
 int64_t lbm_batch_total_nodes(const lbm_batch* b) { return b ? b->n_total : 0; }
 
+int lbm_batch_set_resident(lbm_batch* b, int mode) {
+  if (!b) return set_err(LBM_EINVAL, "batch is NULL");
+  if (mode != 0 && mode != 1)
+    return set_err(LBM_EINVAL, "resident mode must be 0 or 1, not %d", mode);
+  b->resident_mode = mode;
+  return LBM_OK;
+}
+
+int64_t lbm_batch_resident_lattices(const lbm_batch* b) {
+  if (!b) return 0;
+  int64_t c = 0;
+  for (int64_t i = 0; i < b->n_inst; ++i) c += b->resident(i) ? 1 : 0;
+  return c;
+}
+
 size_t lbm_batch_workspace_bytes(const lbm_batch* b, int kind) {
   if (!b) return 0;
   if (kind == LBM_WS_STEP) return layout(b, b->run_tiles(), false).total;
@@ -664,13 +739,63 @@ int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes) {
     const lbm_tuning& t = grouped ? b->group_tune[g] : b->tune;
     const int64_t out = tile_width(t) - 4 * (int64_t)t.steps_per_launch;
     for (int64_t i = 0; i < b->n_inst; ++i) {
-      if (grouped && b->group_of[i] != (int32_t)g) continue;
+      if ((grouped && b->group_of[i] != (int32_t)g) || b->resident(i)) continue;
       const int64_t n = b->offsets[i + 1] - b->offsets[i];
       for (int64_t k = 0; k * out < n; ++k)
         tiles.push_back(TileRef{(int32_t)i, (int32_t)k});
     }
   }
   first[ng] = (int64_t)tiles.size();
+  // Resident lattices packed into workgroups of kResidentWaves wavefronts,
+  // longest first, each into the first workgroup with room for its
+  // ceil(L / 62P) wavefronts.
+  std::vector<ResidentItem> items;
+  std::vector<int32_t> res_first;
+  {
+    std::vector<int64_t> order;
+    for (int64_t i = 0; i < b->n_inst; ++i)
+      if (b->resident(i)) order.push_back(i);
+    auto waves = [&](int64_t i) {
+      const int64_t L = b->offsets[i + 1] - b->offsets[i];
+      return (int32_t)((L + 62 * kResP - 1) / (62 * kResP));
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t x, int64_t y) { return waves(x) > waves(y); });
+    std::vector<int32_t> used;                     // wavefronts used per workgroup
+    std::vector<std::vector<ResidentItem>> bins;
+    for (int64_t i : order) {
+      const int32_t w = waves(i);
+      size_t g = 0;
+      while (g < used.size() && used[g] + w > kResidentWaves) ++g;
+      if (g == used.size()) {
+        used.push_back(0);
+        bins.emplace_back();
+      }
+      bins[g].push_back(ResidentItem{(int32_t)i, used[g], w, 0});
+      used[g] += w;
+    }
+    for (const auto& bin : bins) {
+      res_first.push_back((int32_t)items.size());
+      items.insert(items.end(), bin.begin(), bin.end());
+    }
+    res_first.push_back((int32_t)items.size());
+  }
+  if (!items.empty()) {
+    // the resident launch's side stream (default priority) and events,
+    // created once, outside any capture
+    if (!b->res_stream) {
+      const int r = hip_check(hipStreamCreateWithFlags(&b->res_stream,
+                                                       hipStreamNonBlocking),
+                              "hipStreamCreate");
+      if (r) return r;
+    }
+    for (hipEvent_t& ev : b->res_events)
+      if (!ev) {
+        const int r = hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming),
+                                "hipEventCreate");
+        if (r) return r;
+      }
+  }
   int rc = hip_check(hipMemcpyAsync(at<char>(ws, L.consts), b->consts.data(),
                                     sizeof(Consts) * b->n_inst,
                                     hipMemcpyHostToDevice, b->stream),
@@ -680,9 +805,19 @@ int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes) {
                                   sizeof(int64_t) * (b->n_inst + 1),
                                   hipMemcpyHostToDevice, b->stream),
                    "hipMemcpyAsync");
-  if (!rc)
+  if (!rc && !tiles.empty())
     rc = hip_check(hipMemcpyAsync(at<char>(ws, L.tiles), tiles.data(),
                                   sizeof(TileRef) * tiles.size(),
+                                  hipMemcpyHostToDevice, b->stream),
+                   "hipMemcpyAsync");
+  if (!rc && !items.empty())
+    rc = hip_check(hipMemcpyAsync(at<char>(ws, L.res_items), items.data(),
+                                  sizeof(ResidentItem) * items.size(),
+                                  hipMemcpyHostToDevice, b->stream),
+                   "hipMemcpyAsync");
+  if (!rc && !items.empty())
+    rc = hip_check(hipMemcpyAsync(at<char>(ws, L.res_first), res_first.data(),
+                                  sizeof(int32_t) * res_first.size(),
                                   hipMemcpyHostToDevice, b->stream),
                    "hipMemcpyAsync");
   if (!rc) rc = hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -693,6 +828,9 @@ int lbm_batch_prepare(lbm_batch* b, void* ws, size_t ws_bytes) {
   b->prep_group_tune = b->group_tune;
   b->prep_group_of = b->group_of;
   b->prep_group_first = grouped ? first : std::vector<int64_t>();
+  b->prep_resident_mode = b->resident_mode;
+  b->prep_res_items = items;
+  b->prep_res_first = items.empty() ? std::vector<int32_t>() : res_first;
   return LBM_OK;
 }
 
@@ -702,7 +840,7 @@ int lbm_batch_set_equilibrium(lbm_batch* b, const double* rho, const double* J,
   if (!rho || !J || !zeta || !f) return set_err(LBM_EINVAL, "NULL argument");
   int rc = check_batch_ws(b, ws, ws_bytes);
   if (rc) return rc;
-  const Layout L = layout(b, b->prep_tiles, false);
+  const Layout L = layout(b, b->run_tiles(), false);
   return launch_batch_equilibrium(at<Consts>(ws, L.consts),
                                   at<int64_t>(ws, L.offs), b->n_inst, rho, J,
                                   zeta, f, b->n_total, b->stream);
@@ -726,7 +864,7 @@ int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
   if (!(b->exec && b->g_f == f && b->g_ws == ws && b->g_nsteps == nsteps &&
         same_tuning(b->g_tune, b->tune) &&
         same_tunings(b->g_group_tune, b->group_tune) &&
-        b->g_group_of == b->group_of)) {
+        b->g_group_of == b->group_of && b->g_resident_mode == b->resident_mode)) {
     drop_graph(b);
     if (!b->cap &&
         (rc = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking),
@@ -757,6 +895,7 @@ int lbm_batch_run(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     b->g_tune = b->tune;
     b->g_group_tune = b->group_tune;
     b->g_group_of = b->group_of;
+    b->g_resident_mode = b->resident_mode;
   }
   rc = hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
   return rc ? rc : batch_check_result(b, ws);
@@ -769,7 +908,7 @@ int lbm_batch_moments(lbm_batch* b, const double* f, double* m, void* ws,
   if (!f || !m) return set_err(LBM_EINVAL, "NULL argument");
   if (overlaps(f, sizeof(double) * 6 * b->n_total, m, sizeof(double) * 6 * b->n_total))
     return set_err(LBM_EINVAL, "f and m overlap");
-  const Layout L = layout(b, b->prep_tiles, false);
+  const Layout L = layout(b, b->run_tiles(), false);
   return launch_batch_moments(at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs),
                               b->n_inst, f, m, b->n_total, b->stream);
 }
@@ -779,7 +918,7 @@ int lbm_batch_diagnostics(lbm_batch* b, const double* f, void* ws,
   int rc = check_batch_ws(b, ws, ws_bytes);
   if (rc) return rc;
   if (!f || !out) return set_err(LBM_EINVAL, "NULL argument");
-  const Layout L = layout(b, b->prep_tiles, false);
+  const Layout L = layout(b, b->run_tiles(), false);
   double* d = at<double>(ws, L.diag);
   rc = launch_batch_diag(at<Consts>(ws, L.consts), at<int64_t>(ws, L.offs),
                          b->n_inst, f, b->n_total, d, b->stream);
@@ -808,102 +947,173 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
                           std::to_string(log2_class((double)b->n_total)) + "/L" +
                           std::to_string(log2_class(mean_len)) +
                           (b->eq_class() == 0 ? "/eq8" : "/eqsel") +
-                          kKernelGeneration;
+                          (b->resident_mode ? "/res" : "") + kKernelGeneration;
   lbm_tuning best = b->tune;
   std::vector<lbm_tuning> gshape;
   std::vector<double> gcost;
-  if (!tune_cache_get(cache_path, key, &best, &gshape, &gcost)) {
-    const std::vector<lbm_tuning> cands = batch_candidates(b);
+  int resident = b->resident_mode;
+  if (!tune_cache_get(cache_path, key, &best, &gshape, &gcost, &resident)) {
     double* backup = at<double>(ws, layout(b, tune_tiles(b), true).backup);
     const size_t sbytes = sizeof(double) * 6 * (size_t)b->n_total;
-    // a failed search leaves the tuning and the groups as they were
+    // a failed search leaves the tuning, the groups and the mode as they were
     const lbm_tuning prev = b->tune;
     const std::vector<lbm_tuning> prev_gt = b->group_tune;
     const std::vector<int32_t> prev_go = b->group_of;
+    const int32_t prev_mode = b->resident_mode;
     auto fail = [&](int code) {
       b->tune = prev;
       b->group_tune = prev_gt;
       b->group_of = prev_go;
+      b->resident_mode = prev_mode;
       return code;
     };
-    b->group_tune.clear();
-    b->group_of.clear();
-    std::vector<float> times;
-    int rc = autotune_impl(
-        b->stream, f, backup, sbytes, probe_steps, cands,
-        [&](const lbm_tuning& t) {
-          b->tune = t;
-          return lbm_batch_prepare(b, ws, ws_bytes);
-        },
-        [&](const lbm_tuning&, int64_t k) {
-          return lbm_batch_run(b, f, ws, ws_bytes, k, 0);
-        },
-        &best, &times);
-    if (rc) return fail(rc);
-    // Shape groups: the measured time per computed node-update of each shape
-    // models a grouping; the best set of two or three among the eight
-    // fastest shapes is timed and kept if it beats the best single shape.
-    std::vector<double> cost(cands.size());
-    std::vector<size_t> order(cands.size());
-    size_t ib = 0;
-    for (size_t c = 0; c < cands.size(); ++c) {
-      cost[c] = (double)times[c] * 1e-3 /
-                ((double)b->count_work(cands[c]) * (double)probe_steps);
-      order[c] = c;
-      if (same_tuning(cands[c], best)) ib = c;
-    }
-    std::sort(order.begin(), order.end(),
-              [&](size_t x, size_t y) { return times[x] < times[y]; });
-    const size_t top = std::min<size_t>(8, order.size());
-    const double single = assign_groups(b, {cands[ib]}, {cost[ib]}, nullptr);
-    double best_model = single;
-    std::vector<size_t> pick;
-    auto consider = [&](const std::vector<size_t>& set) {
-      std::vector<lbm_tuning> sh;
-      std::vector<double> co;
-      for (size_t c : set) {
-        sh.push_back(cands[c]);
-        co.push_back(cost[c]);
-      }
-      const double m = assign_groups(b, sh, co, nullptr);
-      if (m < best_model) {
-        best_model = m;
-        pick = set;
-      }
+    auto run = [&](const lbm_tuning&, int64_t k) {
+      return lbm_batch_run(b, f, ws, ws_bytes, k, 0);
     };
-    for (size_t x = 0; x < top; ++x)
-      for (size_t y = x + 1; y < top; ++y) {
-        consider({order[x], order[y]});
-        for (size_t z = y + 1; z < top; ++z) consider({order[x], order[y], order[z]});
+    // One search for the current resident mode: the tile shape of the tiled
+    // lattices, then shape groups (*ms: the kept setting's time for
+    // probe_steps steps).  With every lattice resident there are no tiles
+    // to tune, and the run is timed as it is.
+    auto search = [&](lbm_tuning* best_out, std::vector<lbm_tuning>* gs,
+                      std::vector<double>* gc, float* ms) -> int {
+      b->tune = prev;
+      b->group_tune.clear();
+      b->group_of.clear();
+      gs->clear();
+      gc->clear();
+      std::vector<float> times;
+      if (b->count_work(b->tune) == 0) {
+        *best_out = b->tune;
+        lbm_tuning unused = b->tune;
+        const int r = autotune_impl(
+            b->stream, f, backup, sbytes, probe_steps, {b->tune},
+            [&](const lbm_tuning&) { return lbm_batch_prepare(b, ws, ws_bytes); },
+            run, &unused, &times);
+        *ms = r ? INFINITY : times[0];
+        return r;
       }
-    if (!pick.empty() && best_model < 0.97 * single) {
-      std::vector<lbm_tuning> sh;
-      std::vector<double> co;
-      for (size_t c : pick) {
-        sh.push_back(cands[c]);
-        co.push_back(cost[c]);
+      const std::vector<lbm_tuning> cands = batch_candidates(b);
+      int rc = autotune_impl(
+          b->stream, f, backup, sbytes, probe_steps, cands,
+          [&](const lbm_tuning& t) {
+            b->tune = t;
+            return lbm_batch_prepare(b, ws, ws_bytes);
+          },
+          run, best_out, &times);
+      if (rc) return rc;
+      // Shape groups: the measured time per computed node-update of each
+      // shape models a grouping; the best set of two or three among the
+      // eight fastest shapes is timed and kept if it beats the best single
+      // shape.
+      std::vector<double> cost(cands.size());
+      std::vector<size_t> order(cands.size());
+      size_t ib = 0;
+      for (size_t c = 0; c < cands.size(); ++c) {
+        cost[c] = (double)times[c] * 1e-3 /
+                  ((double)b->count_work(cands[c]) * (double)probe_steps);
+        order[c] = c;
+        if (same_tuning(cands[c], *best_out)) ib = c;
       }
-      b->tune = best;
-      std::vector<float> gt;
-      lbm_tuning unused = best;
-      rc = autotune_impl(
-          b->stream, f, backup, sbytes, probe_steps, {best},
-          [&](const lbm_tuning&) {
-            const int r = apply_groups(b, sh, co);
-            return r ? r : lbm_batch_prepare(b, ws, ws_bytes);
-          },
-          [&](const lbm_tuning&, int64_t k) {
-            return lbm_batch_run(b, f, ws, ws_bytes, k, 0);
-          },
-          &unused, &gt);
+      *ms = times[ib];
+      std::sort(order.begin(), order.end(),
+                [&](size_t x, size_t y) { return times[x] < times[y]; });
+      const size_t top = std::min<size_t>(8, order.size());
+      const double single = assign_groups(b, {cands[ib]}, {cost[ib]}, nullptr);
+      double best_model = single;
+      std::vector<size_t> pick;
+      auto consider = [&](const std::vector<size_t>& set) {
+        std::vector<lbm_tuning> sh;
+        std::vector<double> co;
+        for (size_t c : set) {
+          sh.push_back(cands[c]);
+          co.push_back(cost[c]);
+        }
+        const double m = assign_groups(b, sh, co, nullptr);
+        if (m < best_model) {
+          best_model = m;
+          pick = set;
+        }
+      };
+      for (size_t x = 0; x < top; ++x)
+        for (size_t y = x + 1; y < top; ++y) {
+          consider({order[x], order[y]});
+          for (size_t z = y + 1; z < top; ++z) consider({order[x], order[y], order[z]});
+        }
+      if (!pick.empty() && best_model < 0.97 * single) {
+        std::vector<lbm_tuning> sh;
+        std::vector<double> co;
+        for (size_t c : pick) {
+          sh.push_back(cands[c]);
+          co.push_back(cost[c]);
+        }
+        b->tune = *best_out;
+        std::vector<float> gt;
+        lbm_tuning unused = *best_out;
+        rc = autotune_impl(
+            b->stream, f, backup, sbytes, probe_steps, {*best_out},
+            [&](const lbm_tuning&) {
+              const int r = apply_groups(b, sh, co);
+              return r ? r : lbm_batch_prepare(b, ws, ws_bytes);
+            },
+            run, &unused, &gt);
+        if (rc) return rc;
+        if (gt[0] < times[ib]) {
+          *gs = sh;
+          *gc = co;
+          *ms = gt[0];
+        }
+      }
+      return LBM_OK;
+    };
+    float ms = INFINITY;
+    int rc = search(&best, &gshape, &gcost, &ms);
+    if (rc) return fail(rc);
+    // Resident lattices on: the search is repeated with every lattice on
+    // tiles, and the faster of the two modes is kept.
+    if (prev_mode == 1 && lbm_batch_resident_lattices(b) > 0) {
+      b->resident_mode = 0;
+      lbm_tuning best0 = prev;
+      std::vector<lbm_tuning> gshape0;
+      std::vector<double> gcost0;
+      float ms0 = INFINITY;
+      rc = search(&best0, &gshape0, &gcost0, &ms0);
       if (rc) return fail(rc);
-      if (gt[0] < times[ib]) {
-        gshape = sh;
-        gcost = co;
+      // the two settings compared over a longer run: a short probe
+      // under-weighs the resident launch, which loads and stores its
+      // lattices once per run
+      auto time_setting = [&](int mode, const lbm_tuning& t,
+                              const std::vector<lbm_tuning>& gs,
+                              const std::vector<double>& gc, float* out_ms) {
+        b->resident_mode = mode;
+        b->tune = t;
+        std::vector<float> tm;
+        lbm_tuning unused = t;
+        const int r = autotune_impl(
+            b->stream, f, backup, sbytes, std::max<int64_t>(8 * probe_steps, 256),
+            {t},
+            [&](const lbm_tuning&) {
+              const int r2 = gs.empty() ? lbm_batch_set_groups(b, 0, nullptr, nullptr)
+                                        : apply_groups(b, gs, gc);
+              return r2 ? r2 : lbm_batch_prepare(b, ws, ws_bytes);
+            },
+            run, &unused, &tm);
+        *out_ms = r ? INFINITY : tm[0];
+        return r;
+      };
+      if ((rc = time_setting(1, best, gshape, gcost, &ms))) return fail(rc);
+      if ((rc = time_setting(0, best0, gshape0, gcost0, &ms0))) return fail(rc);
+      if (ms0 < ms) {
+        best = best0;
+        gshape = gshape0;
+        gcost = gcost0;
+        resident = 0;
+      } else {
+        resident = 1;
       }
     }
-    tune_cache_put(cache_path, key, best, &gshape, &gcost);
+    tune_cache_put(cache_path, key, best, &gshape, &gcost, resident);
   }
+  b->resident_mode = resident;
   b->tune = best;
   int rc = gshape.empty() ? lbm_batch_set_groups(b, 0, nullptr, nullptr)
                           : apply_groups(b, gshape, gcost);

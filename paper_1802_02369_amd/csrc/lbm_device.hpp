@@ -56,6 +56,16 @@ struct TileRef {
   int32_t t;
 };
 
+// A lattice of a batch held in one workgroup's registers for a whole run
+// (see k_batch_resident): wavefronts wave0 .. wave0 + nw - 1 of its
+// workgroup.
+struct ResidentItem {
+  int32_t inst;
+  int32_t wave0;
+  int32_t nw;
+  int32_t pad;
+};
+
 // rho = rho0 f0 + rho0 f+ + rho0 f-, summed in the order of the first row of
 // eq. M-d1q3q3 without contraction.  X contains (gamma-1) ln rho, so a one-ulp
 // change of rho moves eps_eq by ~1e-16 in absolute terms; a fixed order keeps

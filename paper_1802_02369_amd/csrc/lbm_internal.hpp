@@ -40,6 +40,29 @@ int launch_batch_check(const Consts* cs, const int64_t* offs,
 int read_check_record(const unsigned long long* rec, hipStream_t s,
                       unsigned long long* out);
 
+// Resident lattices of a batch (k_batch_resident): P nodes per lane,
+// workgroups of kResidentWaves wavefronts, lattices of 2P to
+// 62 P kResidentWaves nodes.  Twelve wavefronts at three per SIMD (168
+// VGPRs) measured 278 GLUPS on the 4096-lattice batch (lengths 512 ..
+// 16384) against 272 for eight at two per SIMD and 265 on tiles alone.
+constexpr int kResP = 8;
+constexpr int kResidentWaves = 12;
+constexpr int64_t kResidentMin = 2 * kResP;
+constexpr int64_t kResidentMax = (int64_t)62 * kResP * kResidentWaves;
+// Copies the output nodes of the tiles [0, ntiles) of a table (OUT per
+// tile) from src to dst.
+int launch_batch_copy_tiles(const int64_t* offs, const TileRef* tiles,
+                            int64_t ntiles, int OUT, const double* src,
+                            double* dst, int64_t S, hipStream_t s);
+int launch_batch_resident(const Consts* cs, const int64_t* offs,
+                          const ResidentItem* items, const int32_t* wg_first,
+                          int64_t nwg, const double* fin, double* fout,
+                          int64_t S, int64_t T, int eq, hipStream_t s);
+int launch_batch_check_lattices(const Consts* cs, const int64_t* offs,
+                                const ResidentItem* items, int64_t nitems,
+                                const double* f, int64_t S, int64_t steps,
+                                unsigned long long* rec, hipStream_t s);
+
 int launch_equilibrium(const Consts& c, const double* rho, const double* J,
                        const double* zeta, double* f, int64_t n, hipStream_t s);
 int launch_step_plain(const Consts& c, const double* fin, double* fout,
@@ -109,14 +132,17 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 
 // Tuning cache: "<arch>/<kind>/<class>" -> shape, in a small JSON file.
 // Batch entries may carry shape groups with their measured time per computed
-// node-update (gshape, gcost); absent groups read back empty.
+// node-update (gshape, gcost; absent groups read back empty) and the
+// resident mode (-1: none stored, *resident left as it is).
 bool tune_cache_get(const char* path, const std::string& key, lbm_tuning* t,
                     std::vector<lbm_tuning>* gshape = nullptr,
-                    std::vector<double>* gcost = nullptr);
+                    std::vector<double>* gcost = nullptr,
+                    int* resident = nullptr);
 void tune_cache_put(const char* path, const std::string& key,
                     const lbm_tuning& t,
                     const std::vector<lbm_tuning>* gshape = nullptr,
-                    const std::vector<double>* gcost = nullptr);
+                    const std::vector<double>* gcost = nullptr,
+                    int resident = -1);
 std::string gpu_arch_name();
 
 // Validates a tuning record for a lattice (or batch) of minimum length nmin.
@@ -196,6 +222,17 @@ struct lbm_batch {
   const void* prep_ws = nullptr;
   lbm_tuning prep_tune{};
   int64_t prep_tiles = 0;
+  // Resident lattices (lbm_batch_set_resident): 1 (default) runs every
+  // lattice of kResidentMin .. kResidentMax nodes in one launch for the
+  // whole call (k_batch_resident), the others on tiles; 0 puts every
+  // lattice on tiles.  What lbm_batch_prepare built: the resident items and
+  // their workgroups.
+  int32_t resident_mode = 1;
+  int32_t prep_resident_mode = -1;
+  hipStream_t res_stream = nullptr;  // side stream of the resident launch
+  hipEvent_t res_events[2] = {};     // fork, join
+  std::vector<lbm::ResidentItem> prep_res_items;
+  std::vector<int32_t> prep_res_first;
   // Shape groups of lbm_batch_run (lbm_batch_set_groups): lattice i runs with
   // group_tune[group_of[i]], each group as its own launch sequence on its own
   // stream.  Empty: every lattice runs with tune.
@@ -216,6 +253,7 @@ struct lbm_batch {
   lbm_tuning g_tune{};
   std::vector<lbm_tuning> g_group_tune;
   std::vector<int32_t> g_group_of;
+  int32_t g_resident_mode = -1;
   // adjoint workspace uploaded by lbm_batch_forward_ckpt
   const void* adj_ws = nullptr;
   int64_t adj_nsteps = -1, adj_ckpt = -1;
@@ -243,10 +281,17 @@ struct lbm_batch {
   }
 
   // equilibrium class of the tile kernels: 0 if every lattice has eq_kind 0
-  int eq_class() const {
-    for (const lbm_params& q : params)
-      if (q.eq_kind != 0) return -1;
-    return 0;
+  // (set by lbm_batch_init; the constants do not change afterwards)
+  int32_t eq_cls = 0;
+  int eq_class() const { return eq_cls; }
+
+  // whether lattice i runs resident with the current settings: only in
+  // batches of section-8 lattices (the kernel that selects the equilibria
+  // per lattice needs more registers than three wavefronts per SIMD leave)
+  bool resident(int64_t i) const {
+    const int64_t L = offsets[i + 1] - offsets[i];
+    return resident_mode == 1 && eq_cls == 0 && L >= lbm::kResidentMin &&
+           L <= lbm::kResidentMax;
   }
 
   // tiles of lattice i for a tuning: ceil(L_i / OUT)
@@ -260,10 +305,11 @@ struct lbm_batch {
     return lbm::lattice_lane_nodes(offsets[i + 1] - offsets[i], t);
   }
 
-  // lane-nodes of the whole batch per step with tuning t
+  // lane-nodes of the tiled lattices of the batch per step with tuning t
   int64_t count_work(const lbm_tuning& t) const {
     int64_t s = 0;
-    for (int64_t i = 0; i < n_inst; ++i) s += lattice_work(i, t);
+    for (int64_t i = 0; i < n_inst; ++i)
+      if (!resident(i)) s += lattice_work(i, t);
     return s;
   }
 

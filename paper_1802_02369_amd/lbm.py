@@ -22,6 +22,7 @@ LBM_EUNSTABLE = -6
 LBM_CHECK_FINITE = 1  # bit of Params.flags
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_BLOCKED = 0, 1, 2
 MAX_GROUPS = 4
+RESIDENT_MIN, RESIDENT_MAX = 16, 5952  # lattice lengths of resident runs
 NOALLOC_MAX_NODES = 1 << 20
 WS_STEP, WS_TUNE = 0, 1
 
@@ -96,6 +97,8 @@ def lib():
                                       ctypes.POINTER(CTuning),
                                       ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_batch_total_nodes": ([_vp], _i64),
+            "lbm_batch_set_resident": ([_vp, ctypes.c_int], ctypes.c_int),
+            "lbm_batch_resident_lattices": ([_vp], _i64),
             "lbm_batch_workspace_bytes": ([_vp, ctypes.c_int], _sz),
             "lbm_batch_prepare": ([_vp, _vp, _sz], ctypes.c_int),
             "lbm_batch_set_equilibrium": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz],
@@ -487,6 +490,15 @@ class Batch:
             check(lib().lbm_batch_set_groups(
                 self._h, n, arr, go.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         self.prepare(device)
+
+    def set_resident(self, mode: int = 1, device="cuda"):
+        """1: lattices of RESIDENT_MIN..RESIDENT_MAX nodes run all the steps
+        of run() in one launch; 0: every lattice in tiles (same results)."""
+        check(lib().lbm_batch_set_resident(self._h, int(mode)))
+        self.prepare(device)
+
+    def resident_lattices(self) -> int:
+        return int(lib().lbm_batch_resident_lattices(self._h))
 
     def get_groups(self):
         """([(P, K, W), ...], group_of array), or ([], None) without groups."""

@@ -119,7 +119,8 @@ def test_shape_groups_bitwise_equal_single_shape(steps):
     """Lattices split over three tile shapes, each group a launch sequence
     on its own stream: the state equals the single-shape run bit for bit
     (every shape rounds the same), for direct launches and graph replays;
-    steps = 1 takes the odd-launch path (result copied back after the join)."""
+    steps = 1 takes the odd-launch path (each group's tiles copied back from
+    the workspace state)."""
     rng = np.random.default_rng(17)
     lens = [9000, 60, 3001, 700, 20000, 5, 2048, 130, 4096, 11111, 640, 333]
     names = ["paper", "odd", "linear", "paper", "odd", "nosource",
@@ -328,3 +329,100 @@ def test_autotune_shape_groups_wide_lengths(tmp_path):
     b2.autotune(f0.clone(), probe_steps=24, cache_path=cache)
     s2, go2 = b2.get_groups()
     assert s2 == shapes and ((go is None and go2 is None) or np.array_equal(go, go2))
+
+
+# Lengths around every boundary of the resident layout (496 nodes per
+# wavefront at P = 8, lattices of 16 .. 5952 nodes in workgroups of twelve
+# wavefronts): the limits, one node past a wavefront (the last holds fewer
+# than P nodes, so the periodic copy reaches back into the wavefront before
+# it), full wavefronts, and lattices that stay on tiles (3, 15, 5953, 9000).
+RES_LENS = [16, 5952, 497, 15, 17, 496, 499, 992, 995, 1000, 3969, 30, 1488,
+            2500, 3, 503, 9000, 24, 1991, 3001, 5953, 4961, 5457]
+# (section-8 equilibria only: a batch that selects the equilibria per
+# lattice runs every lattice on tiles)
+RES_NAMES = ["paper", "odd", "nosource", "paper", "nosource", "odd", "paper",
+             "odd", "odd", "nosource", "paper", "odd", "paper", "nosource",
+             "odd", "paper", "odd", "paper", "odd", "nosource", "paper", "odd",
+             "nosource"]
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 4, 5, 37, 100])
+def test_resident_bitwise_equals_tiles(steps):
+    """Resident lattices (all the steps of a run in one launch, state in
+    registers) end bitwise equal to the tiled run of the same batch, for
+    direct launches and graph replays, with and without shape groups, and
+    match the oracle.  The groups put one shape at K = 1, whose odd step
+    counts end in the workspace state and are copied back tile by tile
+    while the other group ends in place."""
+    rng = np.random.default_rng(300 + steps)
+    params = [oracle_params(p) for p in RES_NAMES]
+    states = [random_state(rng, L, p, amp=0.1, u=0.05, ds=0.1)
+              for L, p in zip(RES_LENS, params)]
+    offsets = np.concatenate([[0], np.cumsum(RES_LENS)])
+    say(f"resident vs tiles steps={steps}")
+    b = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    b.set_tuning(4, 16, 4)
+    b.set_resident(0)
+    assert b.resident_lattices() == 0
+    f0 = torch.from_numpy(pack(states)).to(dev())
+    ref = f0.clone()
+    b.run(ref, steps, use_graph=False)
+    b.set_resident(1)
+    want_res = sum(lbm().RESIDENT_MIN <= L <= lbm().RESIDENT_MAX for L in RES_LENS)
+    assert b.resident_lattices() == want_res == len(RES_LENS) - 4
+    f = f0.clone()
+    b.run(f, steps, use_graph=False)
+    bad = [i for i, (g, r) in enumerate(zip(unpack(f.cpu().numpy(), offsets),
+                                             unpack(ref.cpu().numpy(), offsets)))
+           if not np.array_equal(g, r)]
+    assert not bad, [(i, RES_LENS[i]) for i in bad]
+    for rep in range(3):
+        f = f0.clone()
+        _ = (f * 2).sum().item()  # eager work between replays
+        b.run(f, steps, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(f, ref), rep
+    shapes = [(8, 40, 4), (2, 1, 1)]
+    go = _groups_by_length(RES_LENS, shapes)
+    assert set(go) == {0, 1}
+    b.set_groups(shapes, go)
+    f = f0.clone()
+    b.run(f, steps, use_graph=True)
+    assert torch.equal(f, ref)
+    want = oracle_runs(states, params, steps)
+    for i, (g, w) in enumerate(zip(unpack(ref.cpu().numpy(), offsets), want)):
+        assert max_err(g, w) < TOL, (i, RES_LENS[i], RES_NAMES[i])
+
+
+def test_resident_only_batch_and_mode_switch():
+    """A batch whose lattices are all resident (no tiles at all) equals its
+    tiled run bitwise for even and odd step counts and through a graph; the
+    autotuner leaves it untouched; switching the mode re-captures."""
+    rng = np.random.default_rng(41)
+    lens = rng.integers(16, lbm().RESIDENT_MAX + 1, 64)
+    params = [oracle_params("paper", s_e=float(s)) for s in rng.uniform(1.2, 1.8, 64)]
+    states = [random_state(rng, L, p, amp=0.1, u=0.05, ds=0.1)
+              for L, p in zip(lens, params)]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    say(f"resident-only batch, {offsets[-1]} nodes")
+    b = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    assert b.resident_lattices() == 64
+    f0 = torch.from_numpy(pack(states)).to(dev())
+    g = f0.clone()
+    b.autotune(g, probe_steps=8)
+    assert torch.equal(g, f0)
+    for steps in (1, 6, 7):
+        b.set_resident(0)
+        ref = f0.clone()
+        b.run(ref, steps, use_graph=True)
+        b.set_resident(1)
+        for use_graph in (False, True):
+            f = f0.clone()
+            b.run(f, steps, use_graph=use_graph)
+            assert torch.equal(f, ref), (steps, use_graph)
+    with pytest.raises(lbm().LBMError):
+        b.set_resident(2)
+    # one lattice with linear equilibria puts the whole batch on tiles
+    mixed = [gpu_params(p) for p in params]
+    mixed[5] = gpu_params(oracle_params("linear"))
+    assert lbm().Batch(offsets, mixed).resident_lattices() == 0

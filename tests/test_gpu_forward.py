@@ -529,13 +529,14 @@ def test_check_finite_single_lattice(tuning):
     assert torch.equal(f, a)
 
 
-@pytest.mark.parametrize("groups", [False, True])
-def test_check_finite_batch(groups):
+@pytest.mark.parametrize("groups,resident", [(False, 0), (True, 0), (False, 1)])
+def test_check_finite_batch(groups, resident):
     """LBM_CHECK_FINITE in a batch, with and without shape groups, direct and
     captured in a graph: a NaN in a checked lattice gives LBM_ENONFINITE
-    naming that lattice and the steps of the first launch; a NaN in an
-    unchecked lattice is not reported; replays after a failing one start
-    from a clean record."""
+    naming that lattice and the steps of the first launch (the whole run for
+    resident lattices, which run it in one launch); a NaN in an unchecked
+    lattice is not reported; replays after a failing one start from a clean
+    record."""
     from paper_1802_02369_amd import workloads
     cfg = workloads.config_batched(n_inst=6, steps=20, lmin=300, lmax=3000)
     bt = cfg["batch"]
@@ -545,12 +546,14 @@ def test_check_finite_batch(groups):
         p.flags = lbm().LBM_CHECK_FINITE if i in (2, 4) else 0
         ps.append(p)
     b = lbm().Batch(bt.offsets, ps)
+    b.set_resident(resident)
+    assert b.resident_lattices() == (6 if resident else 0)
     b.set_tuning(2, 8, 4)
     if groups:
         b.set_groups([(2, 8, 4), (4, 5, 2)], [0, 1, 0, 1, 1, 0])
     fl = bt.fields
     f0 = b.equilibrium(*to_dev(fl.rho, fl.J, fl.zeta))
-    say(f"check finite, batch groups={groups}")
+    say(f"check finite, batch groups={groups} resident={resident}")
     for use_graph in (False, True):
         f = f0.clone()
         b.run(f, 20, use_graph=use_graph)           # valid: no error
@@ -565,7 +568,7 @@ def test_check_finite_batch(groups):
                 say(f"  graph={use_graph}: NaN in lattice {inst}: after {done} steps, lattice {lat_i}")
                 assert lat_i == inst
                 # 20 steps at K = 8 or 5 run as four launches of 5
-                assert done == 5
+                assert done == (20 if resident else 5)
             else:
                 b.run(f, 20, use_graph=use_graph)
         f = f0.clone()
