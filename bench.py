@@ -79,8 +79,13 @@ LEG_COUNTERS = os.path.join(ROOT, "profiles", "counters_legs.json")
 CPU_THREADS = min(16, os.cpu_count() or 1)
 # Algorithmic HBM bytes of one forward node-step of a gradient without
 # register blocking: forward 96 + recompute 96 + reverse 144 (read f(t) and
-# fbar(t+1), write fbar(t)).
+# fbar(t+1), write fbar(t)).  The blocked kernels keep the state and fbar in
+# registers for K steps and move a fraction of it, so their rate can exceed
+# 8 TB/s on this basis.
 GRAD_BYTES_PER_NODE_STEP = 336.0
+GRAD_BYTES_BASIS = ("bytes per forward node-step of the one-step gradient "
+                    "(no register blocking); the blocked kernels move fewer, "
+                    "see measured_gbs")
 
 
 def source_hash(files) -> str:
@@ -95,11 +100,12 @@ def source_hash(files) -> str:
 
 
 def leg_key(leg: str, tuning=None) -> str:
-    """Key of a leg's counter totals: tiled legs per tile shape."""
+    """Key of a leg's counter totals: tiled legs per tile shape (+res: with
+    resident lattices)."""
     if not tuning:
         return leg
     return f"{leg}@{tuning['nodes_per_lane']},{tuning['steps_per_launch']}," \
-           f"{tuning['waves_per_group']}"
+           f"{tuning['waves_per_group']}" + ("+res" if tuning.get("resident") else "")
 
 
 def leg_counters(leg: str, tuning=None):
@@ -117,12 +123,13 @@ def leg_counters(leg: str, tuning=None):
 
 
 def leg_roofline(leg: str, units_per_s: float, alg_bytes_per_unit: float,
-                 unit: str, tuning=None):
+                 unit: str, tuning=None, bytes_basis: str | None = None):
     """Roofline object of an extra leg: the vector-ALU issue fraction from
     the counted FP64 instructions per useful unit (every kernel of the leg,
     halo and recomputation included), and the HBM fraction of the
-    algorithmic bytes per unit against 8 TB/s; measured HBM bytes per unit
-    beside them."""
+    algorithmic bytes per unit against 8 TB/s (bytes_basis: what those bytes
+    count, when not the leg's own kernels); the counted HBM bytes per unit
+    and their fraction of 8 TB/s beside them."""
     c = leg_counters(leg, tuning)
     hbm = alg_bytes_per_unit * units_per_s / 1e9
     roof = {"bound": "alu", "unit": "T FP64 instr/s", "peak": LANE_INSTR_PEAK_T,
@@ -132,6 +139,8 @@ def leg_roofline(leg: str, units_per_s: float, alg_bytes_per_unit: float,
                     "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": hbm / HBM_PEAK_GBS},
             "counters_current": c is not None}
+    if bytes_basis:
+        roof["hbm"]["basis"] = bytes_basis
     if c is not None:
         # algorithmic: per computed node-update where the tiles' work is
         # known (the arithmetic of one node-update), else per useful unit
@@ -153,8 +162,22 @@ def leg_roofline(leg: str, units_per_s: float, alg_bytes_per_unit: float,
         if c.get("fetch_bytes") is not None and c.get("write_bytes") is not None:
             roof["traffic"] = (c["fetch_bytes"] + c["write_bytes"]) / c["units"]
             roof["traffic_unit"] = f"measured HBM bytes per {unit}"
+            roof["hbm"]["measured_gbs"] = roof["traffic"] * units_per_s / 1e9
+            roof["hbm"]["measured_frac"] = roof["hbm"]["measured_gbs"] / HBM_PEAK_GBS
         roof["wave_cycle_fractions"] = c.get("wave_cycle_fractions")
     return roof
+
+
+def _no_nan(x):
+    """The object with every non-finite float replaced by null (the line
+    stays strict JSON)."""
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    if isinstance(x, dict):
+        return {k: _no_nan(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_no_nan(v) for v in x]
+    return x
 
 
 def split_steps(nsteps: int, K: int) -> list:
@@ -379,6 +402,29 @@ def lattice_lane_nodes(L: int, P: int, K: int, W: int) -> int:
     return s
 
 
+RES_P, RES_WAVE_NODES = 8, 62 * 8   # resident layout: 8 nodes per lane
+
+
+def batch_split(lbm, lens, resident_on: bool):
+    """Lattices of a section-8 batch that run resident (all the steps of a
+    run in one launch) and those on tiles, as the library splits them."""
+    import numpy as np
+    lens = np.asarray(lens)
+    res = (lens >= lbm.RESIDENT_MIN) & (lens <= lbm.RESIDENT_MAX) & bool(resident_on)
+    return res
+
+
+def batch_computed(lens, res, P, K, W) -> int:
+    """Lane-nodes per step of a batch: the tiled lattices' tiles (shape P, K,
+    W) and the resident lattices' wavefronts (64 x 8 lane-nodes each)."""
+    s = 0
+    for L, r in zip(lens, res):
+        L = int(L)
+        s += (64 * RES_P * -(-L // RES_WAVE_NODES) if r
+              else lattice_lane_nodes(L, P, K, W))
+    return s
+
+
 def counter_run_single(torch, lbm, workloads, steps: int):
     """One run of `steps` steps of the single-lattice workload (default
     tiles), for the counter passes; useful and computed node-updates."""
@@ -423,18 +469,21 @@ def bench_batched(torch, lbm, workloads, stream, single_glups, tuning=None,
         cache = os.path.join(tempfile.gettempdir(), "lbm_tune_cache.json")
         # a longer probe ranks shapes whose times differ by a few per cent
         tune = b.autotune(f, probe_steps=160, cache_path=cache)
+    lens = np.diff(np.asarray(bt.offsets))
+    res = batch_split(lbm, lens, b.resident_lattices() > 0)
+    assert int(res.sum()) == b.resident_lattices()
     if counter_run:
         steps = counter_steps or 2 * tune["steps_per_launch"]
         calibration_copy(torch)
         b.run(f, steps, use_graph=False)
         torch.cuda.synchronize()
-        lens = np.diff(np.asarray(bt.offsets))
         P, K, W = (tune[k] for k in ("nodes_per_lane", "steps_per_launch",
                                      "waves_per_group"))
-        work = sum(lattice_lane_nodes(int(x), P, K, W) for x in lens)
+        work = batch_computed(lens, res, P, K, W)
         return {"leg": "batched", "units": b.n_total * steps,
-                "computed_units": work * steps,
-                "launches": len(split_steps(steps, K)), "tuning": tune}
+                "computed_units": work * steps, "resident": int(res.sum()),
+                "launches": len(split_steps(steps, K)),
+                "tuning": dict(tune, resident=True) if res.any() else tune}
     b.run(f, steps)  # warm-up, captures the graph
     torch.cuda.synchronize()
     ms = time_runs(lambda: b.run(f, steps), lambda: f.copy_(f0), 1, torch,
@@ -445,35 +494,41 @@ def bench_batched(torch, lbm, workloads, stream, single_glups, tuning=None,
     shapes, group_of = b.get_groups()
     groups = []
     if shapes:
-        lens = np.diff(np.asarray(bt.offsets))
         for k, (P, K, W) in enumerate(shapes):
-            sel = group_of == k
+            sel = (group_of == k) & ~res
             groups.append({"nodes_per_lane": P, "steps_per_launch": K,
                            "waves_per_group": W, "lattices": int(sel.sum()),
                            "nodes": int(lens[sel].sum())})
+    resident = {"lattices": int(res.sum()), "nodes": int(lens[res].sum()),
+                "max_length": lbm.RESIDENT_MAX}
     launches = (len(split_steps(steps, tune["steps_per_launch"])) if not shapes
                 else None)
     log(f"bench: batched {g:.2f} GLUPS, tuning {tune}, groups {groups}, "
-        f"finite: {ok}")
+        f"resident {resident}, finite: {ok}")
+    key = tune if not resident["lattices"] else dict(tune, resident=True)
     roof = leg_roofline("batched", g * 1e9, 0.0, "node-update",
-                        None if shapes else tune)
+                        None if shapes else key)
     if not shapes and not roof["counters_current"]:
-        roof.update(batched_roofline_from_arithmetic(bt, tune, steps, ms, g))
-    # algorithmic HBM bytes: 96 per node per launch (each launch reads and
-    # writes the whole state once)
+        roof.update(batched_roofline_from_arithmetic(bt, tune, steps, ms, g, res))
+    # algorithmic HBM bytes: 96 per node per launch for the tiled lattices
+    # (each launch reads and writes their state once), 96 per node per run
+    # for the resident ones
     if launches:
-        hbm = BYTES_PER_NODE_LAUNCH * b.n_total * launches / (ms * 1e-3) / 1e9
+        tiled = int(lens[~res].sum())
+        per_run = BYTES_PER_NODE_LAUNCH * (tiled * launches + resident["nodes"])
+        hbm = per_run / (ms * 1e-3) / 1e9
         roof["hbm"].update({"algorithmic_bytes_per_unit":
-                            BYTES_PER_NODE_LAUNCH * launches / steps,
+                            per_run / (b.n_total * steps),
                             "achieved": hbm, "frac": hbm / HBM_PEAK_GBS,
                             "launches": launches})
     return {"value": g, "unit": "GLUPS", "n_inst": bt.n_inst,
             "n_nodes": b.n_total, "time_steps": steps, "ms": ms,
-            "tuning": tune, "groups": groups, "graph": True, "valid": ok,
+            "tuning": tune, "groups": groups, "resident": resident,
+            "graph": True, "valid": ok,
             "vs_single_lattice": g / single_glups, "roofline": roof}
 
 
-def batched_roofline_from_arithmetic(bt, tune, steps, ms, glups):
+def batched_roofline_from_arithmetic(bt, tune, steps, ms, glups, res):
     """ALU roofline of a batched run whose tile shape has no counter run of
     its own: the FP64 (and VALU) instructions per computed node-update of a
     counted batched run (the same node arithmetic, whatever the tile shape)
@@ -496,7 +551,7 @@ def batched_roofline_from_arithmetic(bt, tune, steps, ms, glups):
     P, K, W = (tune[k] for k in ("nodes_per_lane", "steps_per_launch",
                                  "waves_per_group"))
     lens = np.diff(np.asarray(bt.offsets))
-    computed = sum(lattice_lane_nodes(int(x), P, K, W) for x in lens) * steps
+    computed = batch_computed(lens, res, P, K, W) * steps
     fi = e["fp64_instr"] / e["computed_units"]
     fv = e["valu_instr"] / e["computed_units"]
     ff = e["flops"] / e["computed_units"]
@@ -571,7 +626,8 @@ def bench_adjoint(torch, lbm, workloads, stream, counter_run=False):
                                "gradient_vs_one_step_forward": g / fwd["plain"],
                                "gradient_vs_default_forward": g / fwd["default"]},
             "roofline": leg_roofline("adjoint", g * 1e9, GRAD_BYTES_PER_NODE_STEP,
-                                     "forward node-step")}
+                                     "forward node-step",
+                                     bytes_basis=GRAD_BYTES_BASIS)}
 
 
 def bench_batched_adjoint(torch, lbm, workloads, stream, counter_run=False):
@@ -611,7 +667,8 @@ def bench_batched_adjoint(torch, lbm, workloads, stream, counter_run=False):
             "ckpt_every": ck, "ms_per_gradient": ms, "workspace_gb": ws_gb,
             "roofline": leg_roofline("batched_adjoint", g * 1e9,
                                      GRAD_BYTES_PER_NODE_STEP,
-                                     "forward node-step")}
+                                     "forward node-step",
+                                     bytes_basis=GRAD_BYTES_BASIS)}
 
 
 def copy_peak(torch, stream, nbytes: int, reps: int = 20):
@@ -714,7 +771,7 @@ def leg_kernel(leg: str, name: str) -> bool:
     (the setup kernels of the run are left out: the target run and field
     initialisation of the single-lattice path)."""
     if leg == "batched":
-        return "k_batch_tile" in name
+        return "k_batch_tile" in name or "k_batch_resident" in name
     if leg == "single":
         return "k_step_tile" in name
     return not any(k in name for k in ("k_step_tile", "k_step_plain",
@@ -805,20 +862,22 @@ def main():
     run_s = ms / args.steps * 1e-3
     # counted FP64 instructions (flops, VALU instructions) per computed
     # node-update of this kernel and tile shape, from the counter record
+    # (null figures when no counter run was taken on the current sources)
     c = leg_counters("single", tune)
-    nan = float("nan")
-    Fi = args.instr_per_node or (c["fp64_instr"] / c["computed_units"] if c else nan)
-    Ff = c["flops"] / c["computed_units"] if c else nan
-    Fv = c["valu_instr"] / c["computed_units"] if c else nan
+    Fi = args.instr_per_node or (c["fp64_instr"] / c["computed_units"] if c else None)
+    Ff = c["flops"] / c["computed_units"] if c else None
+    Fv = c["valu_instr"] / c["computed_units"] if c else None
     traffic = ((c["fetch_bytes"] + c["write_bytes"]) / c["launches"]
                if c and c.get("fetch_bytes") and c.get("write_bytes") else None)
     kname = f"k_step_tile<{P}, {Wg}, 0>"
     # algorithmic FP64 instructions per launch: per node-update figure times
     # the node-updates one launch delivers (halo recomputation is overhead)
-    achieved = Fi * n * T / L / (launch_ms * 1e-3) / 1e12
-    flops = Ff * n * T / L / (launch_ms * 1e-3) / 1e12
+    per_launch_s = n * T / L / (launch_ms * 1e-3) / 1e12
+    achieved = Fi * per_launch_s if Fi is not None else None
+    flops = Ff * per_launch_s if Ff is not None else None
     roof = {"bound": "alu", "achieved": achieved, "peak": LANE_INSTR_PEAK_T,
-            "unit": "T FP64 instr/s", "frac": achieved / LANE_INSTR_PEAK_T,
+            "unit": "T FP64 instr/s",
+            "frac": achieved / LANE_INSTR_PEAK_T if achieved is not None else None,
             "traffic": traffic,
             "kernel": kname,
             "launch_ms": launch_ms, "launches_per_run": L,
@@ -826,10 +885,11 @@ def main():
             "counters_current": c is not None,
             "flops": {"per_node_update": Ff, "achieved": flops,
                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                      "frac": flops / FP64_PEAK_TFLOPS},
+                      "frac": flops / FP64_PEAK_TFLOPS if flops is not None else None},
             # every VALU instruction (FP64, moves, DPP, compares) over the
             # issue peak, halo node-updates included: how busy the SIMDs are
-            "valu_issue_frac": Fv * computed / run_s / (LANE_INSTR_PEAK_T * 1e12),
+            "valu_issue_frac": (Fv * computed / run_s / (LANE_INSTR_PEAK_T * 1e12)
+                                if Fv is not None else None),
             "algorithmic_bytes_per_launch": BYTES_PER_NODE_LAUNCH * n,
             "hbm_gbs_algorithmic": BYTES_PER_NODE_LAUNCH * n / (launch_ms * 1e-3) / 1e9}
     out = {
@@ -892,7 +952,7 @@ def main():
             if leg in out:
                 log(f"bench: oracle CPU baseline of the {leg} leg")
                 out[leg]["cpu_baseline"] = fn()
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_no_nan(out)), flush=True)
 
 
 if __name__ == "__main__":
