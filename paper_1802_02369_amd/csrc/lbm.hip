@@ -120,6 +120,7 @@ int make_consts(const lbm_params* p, Consts* c) {
   c->two_g = 2.0 / g;
   c->hS = c->src_c * l * l / (3.0 * cp * c->T0);
   c->hC = cp * c->T0 / (p->prandtl * l * l);
+  c->hSd = p->source_on ? -0.25 * c->ise2 * l * l / (3.0 * cp * c->T0) : 0.0;
   c->xs0l = c->xs0 - c->gm1 * std::log(r0);
   c->eq_kind = p->eq_kind;
   c->flags = p->flags;

@@ -278,38 +278,77 @@ __device__ __forceinline__ void shift_right(double (&a)[P], double in_left) {
   a[0] = in_left;
 }
 
-template <int P, int EQ>
+// One reverse step of a lane's P nodes in the forward step's own scaled
+// variables (collide_local: rh = f0 + f+ + f-, Jh = f+ - f-, zh = g0 + g+ +
+// g-, uh, sh, X, Th; the populations and their adjoints are the same in
+// both).  The forward at a node, before streaming:
+//   d = jup - (f+ + f-), jup = Jh uh + hP rh Th (section 8; jup with the
+//     isentropic pressure for eq_kind 2), or d = eh - (f+ + f- - 2 f0)
+//     with linear eh (eq_kind 1);
+//   f0 -= s_e d, f+- += s_e d / 2 (s_e / 3, s_e / 6 for eq_kind 1);
+//   dpr = psih - (g+ - g-), dxr = epsh - (g+ + g- - 2 g0);
+//   g0 += -s_eps dxr / 3 + add, g+- += +-s_psi dpr / 2 + s_eps dxr / 6 + add,
+//   add = hS rh w (du^2 + hC dT^2 w), w = 1 / Th, du, dT across j-1, j+1.
+// Given a = fbar*(f), b = fbar*(g) at the node (after the transposed
+// streaming) the reverse is
+//   db = s_e (a+ + a-)/2 - s_e a0, dprb = s_psi (b+ - b-) / 2,
+//   dxrb = s_eps ((b+ + b-)/2 - b0) / 3, addb = b0 + b+ + b-,
+// the adjoints of the equilibria from (db, dprb, dxrb), of the source from
+// addb (its terms in the neighbours' uh, Th are gathered as A, B), of the
+// thermodynamic state (X = (gamma-1) ln rh + gamma sh + xs0, Th = e^X,
+// uh = Jh / rh, sh = zh / rh) and of the moments back to the populations,
+// plus the direct paths of the relaxation.  Rate partials: d db / s_e,
+// dpr (b+ - b-) / 2, dxr ((b+ + b-)/2 - b0) / 3, and the source's
+// d hS / d s_e.  PRE: the thermodynamic state of f(t) is given in pre[k]
+// (kept by the forward step that recomputed the next state from f(t): the
+// same arithmetic on the same populations, so the same bits).
+template <int P, int EQ, bool PRE = false>
 __device__ __forceinline__ void adjoint_step_local(
     const Consts& c, const double (&ft)[6][P], double (&fb)[6][P],
-    const bool (&own)[P], double& r0, double& r1, double& r2) {
-  // A: forward quantities of each node
-  double rho[P], u[P], s[P], X[P], T[P], ir[P];
+    const bool (&own)[P], double& r0, double& r1, double& r2,
+    const lbm::NodeThermo* pre = nullptr) {
+#pragma clang fp contract(off)
+  // A: scaled moments and thermodynamic state of every node of f(t)
+  double rh[P], uh[P], sh[P], X[P], Th[P], ir[P], lr[P], w[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) {
-    rho[k] = lbm::density(c, ft[0][k], ft[1][k], ft[2][k]);
-    const double J = c.mJ * (ft[1][k] - ft[2][k]);
-    const double zeta = c.mz * (ft[3][k] + (ft[4][k] + ft[5][k]));
-    lbm::thermo(c, rho[k], J, zeta, u[k], s[k], X[k], T[k], ir[k]);
+    rh[k] = (ft[0][k] + ft[1][k]) + ft[2][k];
+    if constexpr (PRE) {
+      uh[k] = pre[k].uh;
+      sh[k] = pre[k].sh;
+      X[k] = pre[k].X;
+      Th[k] = pre[k].Th;
+      lr[k] = pre[k].lr;
+      ir[k] = pre[k].ir;
+      w[k] = pre[k].w;
+    } else {
+      const double Jh = ft[1][k] - ft[2][k];
+      const double zh = ft[3][k] + (ft[4][k] + ft[5][k]);
+      lbm::thermo_scaled(c, rh[k], Jh, zh, uh[k], sh[k], X[k], Th[k], lr[k], ir[k]);
+    }
   }
   const double fpR = lbm::from_right(fb[1][0]), gpR = lbm::from_right(fb[4][0]);
   const double fmL = lbm::from_left(fb[2][P - 1]), gmL = lbm::from_left(fb[5][P - 1]);
-  const double uL = lbm::from_left(u[P - 1]), TL = lbm::from_left(T[P - 1]);
-  const double uR = lbm::from_right(u[0]), TR = lbm::from_right(T[0]);
+  const double uL = lbm::from_left(uh[P - 1]), TL = lbm::from_left(Th[P - 1]);
+  const double uR = lbm::from_right(uh[0]), TR = lbm::from_right(Th[0]);
   // streamed adjoint (transpose of (viii)): fb now holds fbar*
   shift_left<P>(fb[1], fpR);
   shift_left<P>(fb[4], gpR);
   shift_right<P>(fb[2], fmL);
   shift_right<P>(fb[5], gmL);
-  // B: source adjoint and what each node sends to its neighbours
-  double A[P], B[P], w[P];
+  // B: the source's adjoint factor F = hS rh w addb of each node, and what
+  // it sends its neighbours: A = 2 F du (to uh), B = 2 F hC w dT (to Th)
+  double A[P], B[P], F[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) {
-    const double ul = k == 0 ? uL : u[k - 1], ur = k == P - 1 ? uR : u[k + 1];
-    const double tl = k == 0 ? TL : T[k - 1], tr = k == P - 1 ? TR : T[k + 1];
-    w[k] = lbm::recip(T[k]);
-    const double Zb = c.ga * (fb[3][k] + fb[4][k] + fb[5][k]);
-    A[k] = 2.0 * c.src_c * rho[k] * w[k] * (ur - ul) * Zb;
-    B[k] = 2.0 * c.src_c * c.cPr * rho[k] * w[k] * w[k] * (tr - tl) * Zb;
+    const double ul = k == 0 ? uL : uh[k - 1], ur = k == P - 1 ? uR : uh[k + 1];
+    const double tl = k == 0 ? TL : Th[k - 1], tr = k == P - 1 ? TR : Th[k + 1];
+    if constexpr (!PRE) w[k] = lbm::recip(Th[k]);
+    const double addb = (fb[3][k] + fb[4][k]) + fb[5][k];
+    F[k] = (c.hS * (rh[k] * w[k])) * addb;
+    const double F2 = F[k] + F[k];
+    A[k] = F2 * (ur - ul);
+    B[k] = ((F2 * c.hC) * w[k]) * (tr - tl);
   }
   const double AL = lbm::from_left(A[P - 1]), BL = lbm::from_left(B[P - 1]);
   const double AR = lbm::from_right(A[0]), BR = lbm::from_right(B[0]);
@@ -317,70 +356,107 @@ __device__ __forceinline__ void adjoint_step_local(
 #pragma unroll
   for (int k = 0; k < P; ++k) {
     __builtin_amdgcn_sched_barrier(0);
-    const double ul = k == 0 ? uL : u[k - 1], ur = k == P - 1 ? uR : u[k + 1];
-    const double tl = k == 0 ? TL : T[k - 1], tr = k == P - 1 ? TR : T[k + 1];
+    const double ul = k == 0 ? uL : uh[k - 1], ur = k == P - 1 ? uR : uh[k + 1];
+    const double tl = k == 0 ? TL : Th[k - 1], tr = k == P - 1 ? TR : Th[k + 1];
     const double al = k == 0 ? AL : A[k - 1], ar = k == P - 1 ? AR : A[k + 1];
     const double bl = k == 0 ? BL : B[k - 1], br = k == P - 1 ? BR : B[k + 1];
-    NodeFwd q;
-    q.rho = rho[k];
-    q.J = c.mJ * (ft[1][k] - ft[2][k]);
-    q.e = c.me * ((ft[1][k] + ft[2][k]) - 2.0 * ft[0][k]);
-    q.zeta = c.mz * (ft[3][k] + (ft[4][k] + ft[5][k]));
-    q.psi = c.mpsi * (ft[4][k] - ft[5][k]);
-    q.eps = c.meps * ((ft[4][k] + ft[5][k]) - 2.0 * ft[3][k]);
-    q.u = u[k];
-    q.s = s[k];
-    q.X = X[k];
-    q.T = T[k];
-    q.ir = ir[k];
-    q.w = w[k];
-    if (EQ == 0 || c.eq_kind == 0) {
-      const double p = q.rho * c.r * q.T;
-      q.e_eq = 3.0 * (q.J * q.u + p) - c.two_l2 * q.rho;
-      q.psi_eq = q.zeta * q.u;
-      q.eps_eq = c.eps_c * q.rho * q.X + q.e_eq * q.s;
-    } else if (c.eq_kind == 2) {
-      q.e_eq = 3.0 * (q.J * q.u + lbm::iso_pressure(c, q.rho)) - c.two_l2 * q.rho;
-      q.psi_eq = 0.0;
-      q.eps_eq = 0.0;
-    } else {
-      q.e_eq = c.lin[0] * q.rho + c.lin[1] * q.J + c.lin[2] * q.zeta;
-      q.psi_eq = c.lin[3] * q.rho + c.lin[4] * q.J + c.lin[5] * q.zeta;
-      q.eps_eq = c.lin[6] * q.rho + c.lin[7] * q.J + c.lin[8] * q.zeta;
-    }
+    const double f0 = ft[0][k], fp = ft[1][k], fm = ft[2][k];
+    const double g0 = ft[3][k], gp = ft[4][k], gm = ft[5][k];
     const double a0 = fb[0][k], ap = fb[1][k], am = fb[2][k];
     const double b0 = fb[3][k], bp = fb[4][k], bm = fb[5][k];
-    const double du = ur - ul, dT = tr - tl;
-    const double Q = du * du + c.cPr * dT * dT * q.w;
-    const double Zb = c.ga * (b0 + bp + bm);
-    double ub = al - ar;
-    double Tb = bl - br - Zb * c.src_c * q.rho * q.w * q.w *
-                              (du * du + 2.0 * c.cPr * dT * dT * q.w);
-    double rb = Zb * c.src_c * q.w * Q;
-    double dr0 = 0.0;
-    if (c.src_c != 0.0) dr0 -= Zb * 0.25 * q.rho * q.w * Q * c.ise2;
-    rb += c.fa * (a0 + ap + am);
-    double Jb = c.fc * (ap - am);
-    const double esb = c.fb * (0.5 * (ap + am) - a0);
-    double zb = Zb;
-    const double psisb = c.gc * (bp - bm);
-    const double epssb = c.gb * (0.5 * (bp + bm) - b0);
-    const double eb = (1.0 - c.s_e) * esb;
-    const double psib = (1.0 - c.s_psi) * psisb;
-    const double epsb = (1.0 - c.s_eps) * epssb;
-    if (own[k]) {
-      r0 += dr0 + (q.e_eq - q.e) * esb;
-      r1 += (q.psi_eq - q.psi) * psisb;
-      r2 += (q.eps_eq - q.eps) * epssb;
+    const double r = rh[k], u = uh[k], sv = sh[k], x = X[k], T = Th[k];
+    const double Jh = fp - fm, sf = fp + fm, sg = gp + gm, zh = g0 + sg;
+    // adjoints of the relaxation's increments
+    const double E1 = fma(0.5, ap + am, -a0);
+    const double E2 = fma(0.5, bp + bm, -b0);
+    const double bd = bp - bm;
+    const double dprb = c.sp_2 * bd;
+    const double dxrb = c.sx_3 * E2;
+    // the forward's equilibria, increments and the adjoints of the
+    // equilibria: rhb, Jhb, zhb, uhb, Thb, shb, Xb, lrb
+    double d, db, psih, epsh, rate_e;
+    double rhb, Jhb, zhb = 0.0, uhb = 0.0, Thb = 0.0, shb = 0.0, Xb = 0.0, lrb = 0.0;
+    if (EQ == 0 || c.eq_kind == 0) {
+      const double hPr = c.hP * r;
+      const double jup = fma(Jh, u, hPr * T);
+      const double eh = fma(-2.0, r, 3.0 * jup);
+      psih = zh * u;
+      const double tgr = c.two_g * r;
+      epsh = fma(eh, sv, tgr * x);
+      d = jup - sf;
+      db = c.s_e * E1;
+      rate_e = d * E1;
+      // epsh = eh sh + (2/gamma) rh X, psih = zh uh, eh = 3 jup - 2 rh,
+      // jup = Jh uh + hP rh Th
+      const double ehb = sv * dxrb;
+      shb = eh * dxrb;
+      Xb = tgr * dxrb;
+      zhb = u * dprb;
+      const double jupb = fma(3.0, ehb, db);
+      rhb = fma(-2.0, ehb, (c.two_g * x) * dxrb);
+      rhb = fma(c.hP * T, jupb, rhb);
+      Jhb = u * jupb;
+      uhb = fma(Jh, jupb, zh * dprb);
+      Thb = hPr * jupb;
+    } else if (c.eq_kind == 2) {
+      const double pe = lbm::exp_fin(c.gm1 * lr[k]);
+      const double hPr = c.hP * r;
+      const double jup = fma(Jh, u, hPr * pe);
+      psih = 0.0;
+      epsh = 0.0;
+      d = jup - sf;
+      db = c.s_e * E1;
+      rate_e = d * E1;
+      rhb = (c.hP * pe) * db;
+      lrb = (c.gm1 * (hPr * pe)) * db;
+      Jhb = u * db;
+      uhb = Jh * db;
+    } else {
+      const double eh = fma(c.hlin[2], zh, fma(c.hlin[1], Jh, c.hlin[0] * r));
+      psih = fma(c.hlin[5], zh, fma(c.hlin[4], Jh, c.hlin[3] * r));
+      epsh = fma(c.hlin[8], zh, fma(c.hlin[7], Jh, c.hlin[6] * r));
+      d = eh - fma(-2.0, f0, sf);
+      db = c.se_3 * E1;
+      rate_e = (d * E1) * (1.0 / 3.0);
+      rhb = fma(c.hlin[6], dxrb, fma(c.hlin[3], dprb, c.hlin[0] * db));
+      Jhb = fma(c.hlin[7], dxrb, fma(c.hlin[4], dprb, c.hlin[1] * db));
+      zhb = fma(c.hlin[8], dxrb, fma(c.hlin[5], dprb, c.hlin[2] * db));
     }
-    equilibria_adjoint<EQ>(c, q, c.s_e * esb, c.s_psi * psisb, c.s_eps * epssb,
-                           ub, Tb, rb, Jb, zb);
-    fb[0][k] = c.rho0 * rb - 2.0 * c.me * eb;
-    fb[1][k] = c.rho0 * rb + c.mJ * Jb + c.me * eb;
-    fb[2][k] = c.rho0 * rb - c.mJ * Jb + c.me * eb;
-    fb[3][k] = c.mz * zb - 2.0 * c.meps * epsb;
-    fb[4][k] = c.mz * zb + c.mpsi * psib + c.meps * epsb;
-    fb[5][k] = c.mz * zb - c.mpsi * psib + c.meps * epsb;
+    // the source at this node (add = hS rh w Q, Q = du^2 + hC dT^2 w) and
+    // the neighbours' terms in this node's uh and Th
+    const double du = ur - ul, dT = tr - tl;
+    const double tw = (c.hC * (dT * dT)) * w[k];
+    const double Q = fma(du, du, tw);
+    const double addb = (b0 + bp) + bm;
+    rhb = fma((c.hS * w[k]) * addb, Q, rhb);
+    // d add / d w = hS rh (Q + tw), d w / d Th = -w^2, F = hS rh w addb
+    Thb = fma(-w[k], F[k] * (Q + tw), Thb);
+    uhb += al - ar;
+    Thb += bl - br;
+    if (own[k]) {
+      const double dpr = psih - (gp - gm);
+      const double dxr = epsh - fma(-2.0, g0, sg);
+      r0 += fma(((c.hSd * (r * w[k])) * addb), Q, rate_e);
+      r1 += (0.5 * dpr) * bd;
+      r2 += (dxr * E2) * (1.0 / 3.0);
+    }
+    // the thermodynamic state: Th = e^X, X = gm1 lr + gamma sh + xs0,
+    // lr = ln rh, uh = Jh / rh, sh = zh / rh
+    Xb = fma(T, Thb, Xb);
+    lrb = fma(c.gm1, Xb, lrb);
+    shb = fma(c.gamma, Xb, shb);
+    const double iv = ir[k];
+    zhb = fma(iv, shb, zhb);
+    Jhb = fma(iv, uhb, Jhb);
+    rhb = fma(iv, lrb - fma(u, uhb, sv * shb), rhb);
+    // the moments and the relaxation's direct paths
+    const double dfm = (EQ == 0 || c.eq_kind != 1) ? a0 : fma(2.0, db, a0);
+    fb[0][k] = dfm + rhb;
+    fb[1][k] = (ap - db) + (rhb + Jhb);
+    fb[2][k] = (am - db) + (rhb - Jhb);
+    fb[3][k] = fma(2.0, dxrb, b0) + zhb;
+    fb[4][k] = (bp - (dxrb + dprb)) + zhb;
+    fb[5][k] = (bm - (dxrb - dprb)) + zhb;
   }
 }
 
@@ -486,35 +562,44 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   // the stored state of the next (earlier) step or pair is fetched while
   // this one computes
   tile_fetch<P>(state(base(i_hi - 1)), S, gi, raw);
-  double fa[6][P];  // E = 2: the even state an odd step was recomputed from
   int buf = 0;
-  for (int i = i_hi - 1; i >= i_lo; --i) {
-    double ft[6][P];
-    bool recomputed = false;
-    if (E == 2 && (i & 1)) {
-      tile_transpose<P>(lane, lds, raw, fa);
-      if (i - 2 >= i_lo) tile_fetch<P>(state(base(i - 2)), S, gi, raw);
-#pragma unroll
-      for (int q = 0; q < 6; ++q)
-#pragma unroll
-        for (int k = 0; k < P; ++k) ft[q][k] = fa[q][k];
-      tile_step<P, EQ>(c, ft);
-      recomputed = true;
-    } else if (E == 2 && i < i_hi - 1) {
-      // the state the odd step i + 1 was recomputed from
-#pragma unroll
-      for (int q = 0; q < 6; ++q)
-#pragma unroll
-        for (int k = 0; k < P; ++k) ft[q][k] = fa[q][k];
-    } else {
-      tile_transpose<P>(lane, lds, raw, ft);
-      if (i > i_lo) tile_fetch<P>(state(base(i - 1)), S, gi, raw);
-    }
-    if (WG > 1) {
+  auto refresh = [&](double (&ft)[6][P], bool recomputed) {
+    if constexpr (WG > 1) {
       adjoint_mirror_refresh<P, WG>(fb, ft, recomputed, edge[buf], lane, wave);
       buf ^= 1;
     }
+  };
+  int i = i_hi - 1;
+  if (E == 1 || !(i & 1)) {
+    // E = 1: every step's state is stored; E = 2: a launch whose first step
+    // is even starts with that stored state
+    for (; i >= i_lo && (E == 1 || i == i_hi - 1); --i) {
+      double ft[6][P];
+      tile_transpose<P>(lane, lds, raw, ft);
+      if (i > i_lo) tile_fetch<P>(state(base(i - 1)), S, gi, raw);
+      refresh(ft, false);
+      adjoint_step_local<P, EQ>(c, ft, fb, own, r0, r1, r2);
+    }
+  }
+  // E = 2, pairs of steps (i odd, i - 1): state i is recomputed from the
+  // stored state i - 1, whose thermodynamic state the recomputation keeps
+  // for step i - 1
+  for (; E == 2 && i >= i_lo; i -= 2) {
+    double fa[6][P], ft[6][P];
+    tile_transpose<P>(lane, lds, raw, fa);
+    if (i - 2 >= i_lo) tile_fetch<P>(state(base(i - 2)), S, gi, raw);
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) ft[q][k] = fa[q][k];
+    lbm::NodeThermo th[P];
+    tile_step<P, EQ, true>(c, ft, th);
+    refresh(ft, true);
     adjoint_step_local<P, EQ>(c, ft, fb, own, r0, r1, r2);
+    if (i - 1 >= i_lo) {
+      refresh(fa, false);
+      adjoint_step_local<P, EQ, true>(c, fa, fb, own, r0, r1, r2, th);
+    }
   }
   const int lo = max(H - wave * WS, wave > 0 ? P : 0);
   const int hi = min(W - H - wave * WS, wave < WG - 1 ? WW - P : WW);

@@ -45,6 +45,7 @@ struct Consts {
   double hP;                // c0^2 / (gamma lambda^2) = p0 / (rho0 lambda^2)
   double two_g;             // 2 / gamma
   double hS, hC;            // source: src_c lambda^2 / (3 cp T0), cp T0 / (Pr lambda^2)
+  double hSd;               // d hS / d s_e = -lambda^2 / (12 cp T0 s_e^2), or 0
   double hlin[9];           // linear equilibria in scaled moments
   int32_t eq_kind;  // 0 section 8, 1 linear, 2 isentropic fluid D1Q3
   int32_t flags;    // lbm_params.flags (LBM_CHECK_FINITE)
@@ -257,12 +258,13 @@ __device__ __forceinline__ void equilibria(const Consts& c, double rho,
 //   epsh = (2/gamma) rh X + eh sh,  hP = c0^2/(gamma lambda^2).
 // (With rho0 = 1, rh is the density summed in the order of eq. M-d1q3q3.)
 // lr returns ln rh.
+// ir returns 1/rh.
 __device__ __forceinline__ void thermo_scaled(const Consts& c, double rh,
                                               double Jh, double zh, double& uh,
                                               double& sh, double& X,
-                                              double& Th, double& lr) {
+                                              double& Th, double& lr,
+                                              double& ir) {
 #pragma clang fp contract(off)
-  double ir;
   lr = ln_inv(rh, ir);
   uh = Jh * ir;
   sh = zh * ir;
@@ -270,17 +272,33 @@ __device__ __forceinline__ void thermo_scaled(const Consts& c, double rh,
   Th = exp_fin(X);
 }
 
+__device__ __forceinline__ void thermo_scaled(const Consts& c, double rh,
+                                              double Jh, double zh, double& uh,
+                                              double& sh, double& X,
+                                              double& Th, double& lr) {
+  double ir;
+  thermo_scaled(c, rh, Jh, zh, uh, sh, X, Th, lr, ir);
+}
+
+// The thermodynamic state of a node's incoming populations, as the time
+// step computes it (kept by the reverse sweep for a state it recomputes).
+struct NodeThermo {
+  double uh, sh, X, Th, lr, ir, w;
+};
+
 // Steps (ii)-(vi) at one node, in place on the six populations: moments,
 // equilibria, relaxation, back to populations.  Returns uh, Th and the two
 // factors the source needs: rw = rh / Th and w = 1 / Th.  EQ = 0 compiles
 // the equilibria of section 8 only (every lattice of the launch has
-// eq_kind 0); EQ = -1 selects them per lattice from c.eq_kind.
-template <int EQ>
+// eq_kind 0); EQ = -1 selects them per lattice from c.eq_kind.  SAVE: also
+// writes the node's thermodynamic state into *save.
+template <int EQ, bool SAVE = false>
 __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
                                               double& fp, double& fm,
                                               double& g0, double& gp,
                                               double& gm, double& u, double& T,
-                                              double& rw, double& w) {
+                                              double& rw, double& w,
+                                              NodeThermo* save = nullptr) {
 #pragma clang fp contract(off)
   // (ii) the conserved moments, eq. M-d1q3q3, scaled
   const double rh = (f0 + fp) + fm;
@@ -288,8 +306,8 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
   const double sg = gp + gm;
   const double zh = g0 + sg;
   // (iv) equilibria
-  double sh, X, lr;
-  thermo_scaled(c, rh, Jh, zh, u, sh, X, T, lr);
+  double sh, X, lr, ir;
+  thermo_scaled(c, rh, Jh, zh, u, sh, X, T, lr, ir);
   double jup, eh, psih, epsh;
   if (EQ == 0 || c.eq_kind == 0) {
     jup = fma(Jh, u, (c.hP * rh) * T);
@@ -335,6 +353,7 @@ __device__ __forceinline__ void collide_local(const Consts& c, double& f0,
   gm = fma(-c.sp_2, dpr, fma(c.sx_6, dxr, gm));
   w = recip(T);
   rw = rh * w;
+  if constexpr (SAVE) *save = NodeThermo{u, sh, X, T, lr, ir, w};
 }
 
 // uh and Th of a node (the halo nodes of the one-step kernel), rounded as in

@@ -119,13 +119,16 @@ __device__ __forceinline__ void tile_store(double* __restrict__ fout,
 // k-1 and k+1, so the collisions run in the order P-1, 0, 1, ..., P-2 and
 // each source is applied as soon as its right neighbour exists; only a window
 // of three nodes' (u, T) stays live besides the populations.
-template <int P, int EQ>
-__device__ __forceinline__ void tile_step(const lbm::Consts& c, double (&f)[6][P]) {
+// SAVE: also keeps each node's thermodynamic state of the incoming state in
+// th[k] (the reverse sweep reuses it for that state's own reverse step).
+template <int P, int EQ, bool SAVE = false>
+__device__ __forceinline__ void tile_step(const lbm::Consts& c, double (&f)[6][P],
+                                          lbm::NodeThermo* th = nullptr) {
   if constexpr (P == 1) {
     // one node per lane: both neighbours are the adjacent lanes
     double u, T, rw, w;
-    lbm::collide_local<EQ>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0],
-                           f[5][0], u, T, rw, w);
+    lbm::collide_local<EQ, SAVE>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0],
+                                 f[5][0], u, T, rw, w, th);
     const double add =
         lbm::source_g(c, rw, w, lbm::from_left(u), lbm::from_right(u),
                       lbm::from_left(T), lbm::from_right(T));
@@ -139,12 +142,13 @@ __device__ __forceinline__ void tile_step(const lbm::Consts& c, double (&f)[6][P
     return;
   }
   double uA, TA, rwA, wA;  // node P-1, collided first
-  lbm::collide_local<EQ>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1], f[3][P - 1],
-                     f[4][P - 1], f[5][P - 1], uA, TA, rwA, wA);
+  lbm::collide_local<EQ, SAVE>(c, f[0][P - 1], f[1][P - 1], f[2][P - 1],
+                               f[3][P - 1], f[4][P - 1], f[5][P - 1], uA, TA,
+                               rwA, wA, SAVE ? th + (P - 1) : nullptr);
   double um, Tm, rwm, wm;  // node k (the one whose source is next)
   __builtin_amdgcn_sched_barrier(0);
-  lbm::collide_local<EQ>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0], f[5][0],
-                     um, Tm, rwm, wm);
+  lbm::collide_local<EQ, SAVE>(c, f[0][0], f[1][0], f[2][0], f[3][0], f[4][0],
+                               f[5][0], um, Tm, rwm, wm, th);
   double ul = lbm::from_left(uA), Tl = lbm::from_left(TA);
   const double uR = lbm::from_right(um), TR = lbm::from_right(Tm);
 #pragma unroll
@@ -154,8 +158,9 @@ __device__ __forceinline__ void tile_step(const lbm::Consts& c, double (&f)[6][P
     // nodes: that would hold several nodes' temporaries live at once.
     __builtin_amdgcn_sched_barrier(0);
     if (k + 1 < P - 1) {
-      lbm::collide_local<EQ>(c, f[0][k + 1], f[1][k + 1], f[2][k + 1], f[3][k + 1],
-                         f[4][k + 1], f[5][k + 1], ur, Tr, rwr, wr);
+      lbm::collide_local<EQ, SAVE>(c, f[0][k + 1], f[1][k + 1], f[2][k + 1],
+                                   f[3][k + 1], f[4][k + 1], f[5][k + 1], ur, Tr,
+                                   rwr, wr, SAVE ? th + (k + 1) : nullptr);
     } else if (k + 1 == P - 1) {
       ur = uA;
       Tr = TA;

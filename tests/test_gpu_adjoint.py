@@ -61,8 +61,13 @@ def test_one_adjoint_step(pname, n, adj):
     fb = T(fbn)
     r = lat.adjoint(aws, 1, 1, fb, use_graph=False)
     assert max_err(fb.cpu().numpy(), want_fb) < TOL
-    scale = np.abs(want_r).max()
-    np.testing.assert_allclose(r, want_r, rtol=1e-11, atol=1e-12 * scale)
+    # Each rate partial is a sum over the nodes of (deviation of a moment
+    # from its equilibrium) x (an adjoint): the deviation is a difference of
+    # O(1) populations, so each term carries a few ulp of the populations
+    # times |fbar| of absolute rounding, whatever the partial's size; the
+    # absolute bar is 8 ulp of that per node.
+    atol = 8 * n * np.finfo(float).eps * np.abs(f0).max() * np.abs(fbn).max()
+    np.testing.assert_allclose(r, want_r, rtol=1e-11, atol=atol)
 
 
 @pytest.mark.parametrize("kernel", ["plain", "blocked", "blocked_p4w2k5",
@@ -361,7 +366,14 @@ def test_blocked_reverse_large_batch_matches_one_step_reverse():
     """A batch large enough for the blocked reverse sweep to run on one
     stream (its launches fill the chip: 256 lattices, 2.06M nodes): the
     gradients equal those of the one-step reverse kernel, which the oracle
-    tests pin on smaller batches."""
+    tests pin on smaller batches, and the rate gradients of two of its
+    lattices match the oracle.  These small-amplitude lattices have rate
+    gradients of 1e-10 .. 1e-7 (s_eps: 1e-17 .. 1e-14) that are sums over
+    nodes and steps with cancellation: both kernels sit up to a few 1e-10
+    (s_eps: a few 1e-9) from the oracle, which bounds their agreement; the
+    same holds for dL/dzeta(0) (measured 4e-11 and 5e-10 of its largest
+    value from the oracle on lattices 0 and 1, for either kernel; dL/drho(0)
+    2e-14, dL/dJ(0) 5e-13)."""
     from paper_1802_02369_amd import workloads
     cfg = workloads.config_batched_adjoint(n_inst=256, steps=40, ckpt=7,
                                            lmin=7000, lmax=9000)
@@ -386,9 +398,35 @@ def test_blocked_reverse_large_batch_matches_one_step_reverse():
     rb, gb = out["blocked"]
     rp, gp = out["plain"]
     assert np.isfinite(rb).all()
-    np.testing.assert_allclose(rb, rp, rtol=1e-10, atol=1e-13 * np.abs(rp).max())
-    for x, y in zip(gb, gp):
-        assert np.abs(x - y).max() <= 1e-11 * np.abs(y).max()
+    np.testing.assert_allclose(rb[:, :2], rp[:, :2], rtol=2e-9,
+                               atol=1e-13 * np.abs(rp).max())
+    np.testing.assert_allclose(rb[:, 2], rp[:, 2], rtol=1e-8,
+                               atol=1e-13 * np.abs(rp[:, 2]).max())
+    for k, (x, y) in enumerate(zip(gb, gp)):
+        say(f"  initial-field adjoint {k}: max |tile - one-step| / max |one-step| "
+            f"{np.abs(x - y).max() / np.abs(y).max():.2e}")
+    for i in (0, 1):
+        o0, o1 = bt.offsets[i], bt.offsets[i + 1]
+        po = oracle_params("paper", s_e=float(bt.s_e[i]))
+        want = oracle.gradient(fl.rho[o0:o1], fl.J[o0:o1], fl.zeta[o0:o1], steps,
+                               np.full(o1 - o0, po.rho0), po, ckpt=ckpt)
+        err_b = np.abs(rb[i] - want[4]) / np.abs(want[4])
+        err_p = np.abs(rp[i] - want[4]) / np.abs(want[4])
+        say(f"  lattice {i}: rate gradients vs oracle, reverse tile {err_b}, one-step {err_p}")
+        for k in range(3):
+            w = want[1 + k]
+            eb = np.abs(gb[k][o0:o1] - w).max() / np.abs(w).max()
+            ep = np.abs(gp[k][o0:o1] - w).max() / np.abs(w).max()
+            say(f"  lattice {i}: initial-field adjoint {k} vs oracle: tile {eb:.2e}, one-step {ep:.2e}")
+            assert eb < FIELD_BARS[k] and ep < FIELD_BARS[k], (i, k)
+        assert (err_b < [2e-9, 2e-9, 1e-8]).all() and (err_p < [2e-9, 2e-9, 1e-8]).all()
+    for k, (x, y) in enumerate(zip(gb, gp)):
+        assert np.abs(x - y).max() <= FIELD_BARS[k] * np.abs(y).max(), k
+
+
+# dL/drho(0), dL/dJ(0), dL/dzeta(0) of the small-amplitude batched-gradient
+# lattices, relative to the largest value: see the test above
+FIELD_BARS = (1e-12, 1e-11, 2e-9)
 
 
 def _stride_run(make, stride, steps, ckpt, fields):
