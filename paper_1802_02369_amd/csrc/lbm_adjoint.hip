@@ -299,14 +299,15 @@ __device__ __forceinline__ void shift_right(double (&a)[P], double in_left) {
 // uh = Jh / rh, sh = zh / rh) and of the moments back to the populations,
 // plus the direct paths of the relaxation.  Rate partials: d db / s_e,
 // dpr (b+ - b-) / 2, dxr ((b+ + b-)/2 - b0) / 3, and the source's
-// d hS / d s_e.  PRE: the thermodynamic state of f(t) is given in pre[k]
+// d hS / d s_e, accumulated without their constant factors over the
+// owned nodes: acc = {sum d E1, sum F Q, sum dpr (b+ - b-), sum dxr E2}
+// (see rate_partials).  PRE: the thermodynamic state of f(t) is given in pre[k]
 // (kept by the forward step that recomputed the next state from f(t): the
 // same arithmetic on the same populations, so the same bits).
 template <int P, int EQ, bool PRE = false>
 __device__ __forceinline__ void adjoint_step_local(
     const Consts& c, const double (&ft)[6][P], double (&fb)[6][P],
-    const bool (&own)[P], double& r0, double& r1, double& r2,
-    const lbm::NodeThermo* pre = nullptr) {
+    const bool (&own)[P], double (&acc)[4], const lbm::NodeThermo* pre = nullptr) {
 #pragma clang fp contract(off)
   // A: scaled moments and thermodynamic state of every node of f(t)
   double rh[P], uh[P], sh[P], X[P], Th[P], ir[P], lr[P], w[P];
@@ -374,7 +375,7 @@ __device__ __forceinline__ void adjoint_step_local(
     const double dxrb = c.sx_3 * E2;
     // the forward's equilibria, increments and the adjoints of the
     // equilibria: rhb, Jhb, zhb, uhb, Thb, shb, Xb, lrb
-    double d, db, psih, epsh, rate_e;
+    double d, db, psih, epsh;
     double rhb, Jhb, zhb = 0.0, uhb = 0.0, Thb = 0.0, shb = 0.0, Xb = 0.0, lrb = 0.0;
     if (EQ == 0 || c.eq_kind == 0) {
       const double hPr = c.hP * r;
@@ -385,7 +386,6 @@ __device__ __forceinline__ void adjoint_step_local(
       epsh = fma(eh, sv, tgr * x);
       d = jup - sf;
       db = c.s_e * E1;
-      rate_e = d * E1;
       // epsh = eh sh + (2/gamma) rh X, psih = zh uh, eh = 3 jup - 2 rh,
       // jup = Jh uh + hP rh Th
       const double ehb = sv * dxrb;
@@ -406,7 +406,6 @@ __device__ __forceinline__ void adjoint_step_local(
       epsh = 0.0;
       d = jup - sf;
       db = c.s_e * E1;
-      rate_e = d * E1;
       rhb = (c.hP * pe) * db;
       lrb = (c.gm1 * (hPr * pe)) * db;
       Jhb = u * db;
@@ -417,7 +416,6 @@ __device__ __forceinline__ void adjoint_step_local(
       epsh = fma(c.hlin[8], zh, fma(c.hlin[7], Jh, c.hlin[6] * r));
       d = eh - fma(-2.0, f0, sf);
       db = c.se_3 * E1;
-      rate_e = (d * E1) * (1.0 / 3.0);
       rhb = fma(c.hlin[6], dxrb, fma(c.hlin[3], dprb, c.hlin[0] * db));
       Jhb = fma(c.hlin[7], dxrb, fma(c.hlin[4], dprb, c.hlin[1] * db));
       zhb = fma(c.hlin[8], dxrb, fma(c.hlin[5], dprb, c.hlin[2] * db));
@@ -434,11 +432,10 @@ __device__ __forceinline__ void adjoint_step_local(
     uhb += al - ar;
     Thb += bl - br;
     if (own[k]) {
-      const double dpr = psih - (gp - gm);
-      const double dxr = epsh - fma(-2.0, g0, sg);
-      r0 += fma(((c.hSd * (r * w[k])) * addb), Q, rate_e);
-      r1 += (0.5 * dpr) * bd;
-      r2 += (dxr * E2) * (1.0 / 3.0);
+      acc[0] = fma(d, E1, acc[0]);
+      acc[1] = fma(F[k], Q, acc[1]);
+      acc[2] = fma(psih - (gp - gm), bd, acc[2]);
+      acc[3] = fma(epsh - fma(-2.0, g0, sg), E2, acc[3]);
     }
     // the thermodynamic state: Th = e^X, X = gm1 lr + gamma sh + xs0,
     // lr = ln rh, uh = Jh / rh, sh = zh / rh
@@ -451,13 +448,29 @@ __device__ __forceinline__ void adjoint_step_local(
     rhb = fma(iv, lrb - fma(u, uhb, sv * shb), rhb);
     // the moments and the relaxation's direct paths
     const double dfm = (EQ == 0 || c.eq_kind != 1) ? a0 : fma(2.0, db, a0);
+    const double rd = rhb - db, zx = zhb - dxrb;
     fb[0][k] = dfm + rhb;
-    fb[1][k] = (ap - db) + (rhb + Jhb);
-    fb[2][k] = (am - db) + (rhb - Jhb);
+    fb[1][k] = (ap + rd) + Jhb;
+    fb[2][k] = (am + rd) - Jhb;
     fb[3][k] = fma(2.0, dxrb, b0) + zhb;
-    fb[4][k] = (bp - (dxrb + dprb)) + zhb;
-    fb[5][k] = (bm - (dxrb - dprb)) + zhb;
+    fb[4][k] = (bp + zx) - dprb;
+    fb[5][k] = (bm + zx) + dprb;
   }
+}
+
+// The three rate partials from the sums adjoint_step_local accumulates:
+// d/ds_e = sum d E1 (x 1/3 for the linear equilibria, whose increment is
+// s_e d / 3) + (d hS / d s_e) / hS sum F Q, d/ds_psi = sum dpr (b+ - b-) / 2,
+// d/ds_eps = sum dxr E2 / 3.
+__device__ __forceinline__ void rate_partials(const Consts& c,
+                                              const double (&acc)[4],
+                                              double& r0, double& r1,
+                                              double& r2) {
+#pragma clang fp contract(off)
+  const double se = c.eq_kind == 1 ? acc[0] * (1.0 / 3.0) : acc[0];
+  r0 = c.hS != 0.0 ? fma(c.hSd / c.hS, acc[1], se) : se;
+  r1 = 0.5 * acc[2];
+  r2 = acc[3] * (1.0 / 3.0);
 }
 
 // Mirror lanes of the reverse tile before a step: lanes 1 and 62 publish
@@ -558,7 +571,7 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
   };
   // the stored state step i starts from
   auto base = [](int i) { return E == 2 ? (i & ~1) : i; };
-  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   // the stored state of the next (earlier) step or pair is fetched while
   // this one computes
   tile_fetch<P>(state(base(i_hi - 1)), S, gi, raw);
@@ -578,7 +591,7 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
       tile_transpose<P>(lane, lds, raw, ft);
       if (i > i_lo) tile_fetch<P>(state(base(i - 1)), S, gi, raw);
       refresh(ft, false);
-      adjoint_step_local<P, EQ>(c, ft, fb, own, r0, r1, r2);
+      adjoint_step_local<P, EQ>(c, ft, fb, own, acc);
     }
   }
   // E = 2, pairs of steps (i odd, i - 1): state i is recomputed from the
@@ -595,15 +608,17 @@ __global__ __launch_bounds__(64 * WG) void k_adjoint_tile(
     lbm::NodeThermo th[P];
     tile_step<P, EQ, true>(c, ft, th);
     refresh(ft, true);
-    adjoint_step_local<P, EQ>(c, ft, fb, own, r0, r1, r2);
+    adjoint_step_local<P, EQ>(c, ft, fb, own, acc);
     if (i - 1 >= i_lo) {
       refresh(fa, false);
-      adjoint_step_local<P, EQ, true>(c, fa, fb, own, r0, r1, r2, th);
+      adjoint_step_local<P, EQ, true>(c, fa, fb, own, acc, th);
     }
   }
   const int lo = max(H - wave * WS, wave > 0 ? P : 0);
   const int hi = min(W - H - wave * WS, wave < WG - 1 ? WW - P : WW);
   tile_store<P>(fbo + off, S, n, wstart, lo, hi, lane, lds, fb);
+  double r0, r1, r2;
+  rate_partials(c, acc, r0, r1, r2);
   const int t = threadIdx.x;
   red[0][t] = r0;
   red[1][t] = r1;
@@ -1028,7 +1043,8 @@ int enqueue_adjoint(lbm_batch* b, void* ws, int64_t nsteps, int64_t C,
   if (rc) return rc;
   double* cur = fbar;
   double* oth = at<double>(ws, L.pp);
-  const int Prec = b->tune.nodes_per_lane, Wrec = b->tune.waves_per_group;
+  const lbm_tuning rt = rec_tuning(b->tune);
+  const int Prec = rt.nodes_per_lane, Wrec = rt.waves_per_group;
   const int Krec = b->tune.steps_per_launch;
   // stride of the stored segment states
   const int E = plan.plain ? 1 : plan.rev.E;
