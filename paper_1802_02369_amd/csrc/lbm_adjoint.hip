@@ -804,6 +804,9 @@ struct AdjLayout {
 // The recompute runs with the forward tile shape.
 lbm_tuning rec_tuning(const lbm_tuning& t) { return t; }
 
+// Tile shape of the checkpointed forward run.
+lbm_tuning fwd_tuning(const lbm_batch* b) { return b->tune; }
+
 // Tile shape of the blocked reverse kernel for a forward tuning and a stride
 // E of the stored segment states.  Its tiles span P (62 W + 2) nodes
 // (neighbouring wavefronts share two lanes) with halo H = 2K, or 2K + 2 at
@@ -912,7 +915,7 @@ AdjPlan resolved_plan(const lbm_batch* b) {
 AdjLayout adj_layout(const lbm_batch* b, int64_t nsteps, int64_t C,
                      const AdjPlan& P) {
   AdjLayout L{};
-  L.n_fwd = b->count_tiles(b->tune);
+  L.n_fwd = b->count_tiles(fwd_tuning(b));
   L.n_rec = b->count_tiles(rec_tuning(b->tune));
   L.n_rev = tiles_of(b, P.rev.out());
   L.n_adj = adj_tile_count(b);
@@ -977,11 +980,12 @@ int fwd_steps(lbm_batch* b, const Consts* cs, const int64_t* offs,
   double* a = f;
   double* w = pp;
   int64_t launches = 0;
-  const int H = 2 * b->tune.steps_per_launch;
-  for (int k : split_steps(steps, b->tune.steps_per_launch)) {
+  const lbm_tuning t = fwd_tuning(b);
+  const int H = 2 * t.steps_per_launch;
+  for (int k : split_steps(steps, t.steps_per_launch)) {
     int rc = launch_batch_tile(cs, offs, tiles, ntiles, a, w, b->n_total,
-                               b->tune.nodes_per_lane, H, k,
-                               b->tune.waves_per_group, b->eq_class(), s);
+                               t.nodes_per_lane, H, k, t.waves_per_group,
+                               b->eq_class(), s);
     if (rc) return rc;
     std::swap(a, w);
     ++launches;
@@ -1249,7 +1253,8 @@ int lbm_batch_forward_ckpt(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
     // tables of this workspace layout: forward and recompute tiles (the
     // forward tile shape), tiles of the blocked and of the one-step reverse
     // kernels, and each lattice's first tile in the two reverse tables
-    const auto fwd = tile_table(b, tile_width(b->tune) - 4 * b->tune.steps_per_launch);
+    const lbm_tuning ft = fwd_tuning(b);
+    const auto fwd = tile_table(b, tile_width(ft) - 4 * ft.steps_per_launch);
     const auto rec = tile_table(
         b, tile_width(rec_tuning(b->tune)) - 4 * b->tune.steps_per_launch);
     const auto rev = tile_table(b, plan.rev.out());
