@@ -376,11 +376,12 @@ LBM_API int lbm_batch_get_groups(const lbm_batch* b, int32_t* n_groups,
                                  lbm_tuning* shapes, int32_t* group_of);
 /* Resident lattices of lbm_batch_run.  With mode 1 (the default) every
  * lattice of LBM_RESIDENT_MIN..LBM_RESIDENT_MAX nodes runs all nsteps steps
- * inside one launch: its state is loaded once into registers (8 nodes per
- * lane, one wavefront per 496 nodes, lattices packed into workgroups of 12
- * wavefronts), advanced step after step with the periodic wrap and the
- * neighbouring wavefronts' edge nodes exchanged through LDS every 4 steps,
- * and stored once (96 bytes of HBM per node for the whole run).  That launch
+ * inside one launch (up to 65536 steps per launch): its state is loaded once
+ * into registers (8 nodes per lane, one wavefront per 496 nodes, lattices
+ * packed into workgroups of 12 wavefronts), advanced step after step with
+ * the periodic wrap and the neighbouring wavefronts' edge nodes exchanged
+ * through LDS every 4 steps, and stored once (96 bytes of HBM per node for
+ * the whole run).  That launch
  * runs on a side stream of the batch, forked from its stream and joined back
  * to it (also inside the graph of use_graph = 1), beside the tiled launches
  * of the other lattices; shape groups apply to those only.  Mode 0 runs

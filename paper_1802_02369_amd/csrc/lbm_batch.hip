@@ -153,13 +153,19 @@ int enqueue_batch(lbm_batch* b, double* f, void* ws, int64_t nsteps,
     const Consts* cs = at<Consts>(ws, L.consts);
     const int64_t* offs = at<int64_t>(ws, L.offs);
     const ResidentItem* items = at<ResidentItem>(ws, L.res_items);
-    rc = launch_batch_resident(cs, offs, items, at<int32_t>(ws, L.res_first), nwg,
-                               f, f, b->n_total, nsteps, b->eq_class(),
-                               b->res_stream);
-    if (!rc && b->check_finite())
-      rc = launch_batch_check_lattices(cs, offs, items, nres, f, b->n_total,
-                                       nsteps, at<unsigned long long>(ws, L.rec),
-                                       b->res_stream);
+    // at most kResidentMaxSteps steps per launch, so that no launch holds
+    // the chip for long; each chunk is checked when asked
+    for (int64_t done = 0; done < nsteps && !rc;) {
+      const int64_t T = std::min<int64_t>(kResidentMaxSteps, nsteps - done);
+      rc = launch_batch_resident(cs, offs, items, at<int32_t>(ws, L.res_first),
+                                 nwg, f, f, b->n_total, T, b->eq_class(),
+                                 b->res_stream);
+      done += T;
+      if (!rc && b->check_finite())
+        rc = launch_batch_check_lattices(cs, offs, items, nres, f, b->n_total,
+                                         done, at<unsigned long long>(ws, L.rec),
+                                         b->res_stream);
+    }
     // join even after a failure, so that a capture ends
     const int r1 = hip_check(hipEventRecord(b->res_events[1], b->res_stream),
                              "hipEventRecord");

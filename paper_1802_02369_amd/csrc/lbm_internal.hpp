@@ -49,6 +49,8 @@ constexpr int kResP = 8;
 constexpr int kResidentWaves = 12;
 constexpr int64_t kResidentMin = 2 * kResP;
 constexpr int64_t kResidentMax = (int64_t)62 * kResP * kResidentWaves;
+// steps of one resident launch (about 2 s on the 4096-lattice batch)
+constexpr int64_t kResidentMaxSteps = int64_t(1) << 16;
 // Copies the output nodes of the tiles [0, ntiles) of a table (OUT per
 // tile) from src to dst.
 int launch_batch_copy_tiles(const int64_t* offs, const TileRef* tiles,
