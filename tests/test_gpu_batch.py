@@ -426,3 +426,28 @@ def test_resident_only_batch_and_mode_switch():
     mixed = [gpu_params(p) for p in params]
     mixed[5] = gpu_params(oracle_params("linear"))
     assert lbm().Batch(offsets, mixed).resident_lattices() == 0
+
+
+def test_resident_run_longer_than_one_launch():
+    """A run of more steps than one resident launch holds (65536) chains
+    launches and equals the tiled run bitwise."""
+    rng = np.random.default_rng(77)
+    lens = [16, 100, 997]
+    params = [oracle_params(p) for p in ("paper", "odd", "nosource")]
+    states = [random_state(rng, L, p, amp=0.02, u=0.01, ds=0.02)
+              for L, p in zip(lens, params)]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    steps = (1 << 16) + 3
+    say(f"resident run of {steps} steps")
+    b = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    b.set_tuning(2, 16, 1)
+    f0 = torch.from_numpy(pack(states)).to(dev())
+    b.set_resident(0)
+    ref = f0.clone()
+    b.run(ref, steps, use_graph=False)
+    b.set_resident(1)
+    assert b.resident_lattices() == 3
+    f = f0.clone()
+    b.run(f, steps, use_graph=False)
+    assert torch.isfinite(ref).all()
+    assert torch.equal(f, ref)
