@@ -88,14 +88,23 @@ GRAD_BYTES_BASIS = ("bytes per forward node-step of the one-step gradient "
                     "see measured_gbs")
 
 
+def source_code(text: str) -> str:
+    """A source file's code: comments removed, whitespace runs collapsed
+    (the kernels' sources hold no comment markers inside string literals)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", " ", text).strip()
+
+
 def source_hash(files) -> str:
-    """Hash of kernel sources; counter figures taken on other sources are
-    not reported."""
+    """Hash of the kernel sources' code; counter figures taken on other code
+    are not reported (comments do not count)."""
     import hashlib
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_1802_02369_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1802_02369_amd", "csrc", f)) as fh:
+            h.update(source_code(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

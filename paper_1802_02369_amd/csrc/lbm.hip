@@ -469,12 +469,12 @@ __global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0 && !EVE
 // those copies and the mirror lanes are refreshed from the lanes that own
 // the nodes, through LDS with one workgroup barrier (every lattice of a
 // workgroup runs the same steps, so all its wavefronts meet at each).  A
-// step has radius 2,
-// so the wrong values that come in from beyond a copy (or from the unused
-// positions past L+P) move two nodes per step and stay inside the copy
-// until the refresh, as for the mirror lanes.  Several lattices share a
-// workgroup of kResWaves wavefronts (items[wg_first[b] .. wg_first[b+1]),
-// each on its own wavefronts); wavefronts without a lattice end at once.
+// step has radius 2, so the wrong values that come in from beyond a copy
+// (or from the unused positions past L+P) move two nodes per step and stay
+// inside the copy until the refresh, as for the mirror lanes.  Several
+// lattices share a workgroup of kResWaves wavefronts (items[wg_first[b] ..
+// wg_first[b+1]), each on its own wavefronts); wavefronts without a
+// lattice end at once.
 // Every node-update rounds as in the other kernels: results are bitwise
 // those of the tiled path.
 constexpr int kResWaves = lbm::kResidentWaves;
