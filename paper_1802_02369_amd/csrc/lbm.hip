@@ -479,13 +479,22 @@ __global__ __launch_bounds__(64 * WG, tile_waves_per_simd(P, WG, EQ == 0 && !EVE
 // those of the tiled path.
 constexpr int kResWaves = lbm::kResidentWaves;
 
+// The copies of the periodic wrap, in P-node blocks: every lane holds the
+// P positions p0 .. p0+P-1 with p0 a multiple of P, so with o = L mod P
+// the nodes L-P .. L-1 are the last P - o nodes of the owner lane at
+// L-P-o followed by the first o of the owner lane at L-o, and the
+// positions L .. L+P-1 are the last P - o of the lane at L-o (every lane
+// holding that block: a mirror lane as well) followed by the first o of
+// the lane at L-o+P.  Those owners write their whole P nodes into a 2P-node
+// buffer read at offset o, which keeps the exchange free of per-node
+// conditions.
 template <int P>
 __device__ __forceinline__ void resident_refresh(
-    double (&f)[6][P], double (*edge)[2][6 * P], double (*wrap)[2][6 * P],
-    int lane, int wave, int lw, int nw, int w0, int L) {
-  // positions of this lane's nodes: p0 .. p0 + P - 1
-  const int p0 = 62 * P * lw + P * (lane - 1);
-  const bool owner = (lane >= 1 && lane <= 62) || (lane == 63 && lw == nw - 1);
+    double (&f)[6][P], double (*edge)[2][6 * P], double (*head)[6 * P],
+    double (*tail)[12 * P], int lane, int wave, int lw, int nw, int w0,
+    int L) {
+  const int p0 = 62 * P * lw + P * (lane - 1);  // position of node 0 of the lane
+  const int o = L % P;                          // uniform over the lattice
   if (lane == 1 || lane == 62) {
     double* d = edge[wave][lane == 62];
 #pragma unroll
@@ -497,17 +506,15 @@ __device__ __forceinline__ void resident_refresh(
 #pragma unroll
     for (int q = 0; q < 6; ++q)
 #pragma unroll
-      for (int k = 0; k < P; ++k) wrap[w0][0][q * P + k] = f[q][k];
+      for (int k = 0; k < P; ++k) head[w0][q * P + k] = f[q][k];
   }
-  if (owner && p0 + P > L - P && p0 < L) {  // nodes L-P .. L-1
+  const bool owner = lane >= 1 && lane <= 62;
+  if (owner && (p0 == L - P - o || (o != 0 && p0 == L - o))) {  // nodes L-P .. L-1
+    double* d = tail[w0] + (p0 == L - o ? P : 0);
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-      const int p = p0 + k;
-      if (p >= L - P && p < L) {
+    for (int q = 0; q < 6; ++q)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) wrap[w0][1][q * P + (p - (L - P))] = f[q][k];
-      }
-    }
+      for (int k = 0; k < P; ++k) d[q * 2 * P + k] = f[q][k];
   }
   __syncthreads();
   if (lane == 0 && lw > 0) {
@@ -524,24 +531,24 @@ __device__ __forceinline__ void resident_refresh(
 #pragma unroll
     for (int q = 0; q < 6; ++q)
 #pragma unroll
-      for (int k = 0; k < P; ++k) f[q][k] = wrap[w0][1][q * P + k];
+      for (int k = 0; k < P; ++k) f[q][k] = tail[w0][q * 2 * P + o + k];
   }
-  // nodes 0 .. P-1 again, after the mirror reads: positions L .. L+P-1 lie
-  // in the last wavefront, or partly in the right mirror lane of the one
-  // before it when the last holds fewer than P nodes
-  if (p0 + P > L && p0 < L + P) {
+  // positions L .. L+P-1 (nodes 0 .. P-1 again), after the mirror reads
+  if (p0 == L - o) {
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-      const int p = p0 + k;
-      if (p >= L && p < L + P) {
+    for (int q = 0; q < 6; ++q)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) f[q][k] = wrap[w0][0][q * P + (p - L)];
-      }
-    }
+      for (int k = 0; k < P; ++k)
+        if (k >= o) f[q][k] = head[w0][q * P + k - o];
+  } else if (o != 0 && p0 == L - o + P) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+        if (k < o) f[q][k] = head[w0][q * P + P - o + k];
   }
 }
 
-// three wavefronts per SIMD: one workgroup of twelve per CU
 template <int P, int EQ>
 __global__ __launch_bounds__(64 * kResWaves, 3) void k_batch_resident(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
@@ -553,7 +560,8 @@ __global__ __launch_bounds__(64 * kResWaves, 3) void k_batch_resident(
   constexpr int WS = 62 * P;
   __shared__ double stage[WG * (WW + 64)];
   __shared__ double edge[2][WG][2][6 * P];
-  __shared__ double wrap[2][WG][2][6 * P];
+  __shared__ double head[2][WG][6 * P];
+  __shared__ double tail[2][WG][12 * P];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // this wavefront's lattice (uniform over the wavefront)
@@ -578,8 +586,8 @@ __global__ __launch_bounds__(64 * kResWaves, 3) void k_batch_resident(
   for (int64_t step = 0; step < T; ++step) {
     tile_step<P, EQ>(c, f);
     if (++since == P / 2 && step + 1 < T) {
-      resident_refresh<P>(f, edge[buf], wrap[buf], lane, wave, lw, it.nw,
-                          it.wave0, L);
+      resident_refresh<P>(f, edge[buf], head[buf], tail[buf], lane, wave, lw,
+                          it.nw, it.wave0, L);
       buf ^= 1;
       since = 0;
     }

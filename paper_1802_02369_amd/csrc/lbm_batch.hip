@@ -1095,7 +1095,7 @@ int lbm_batch_autotune(lbm_batch* b, double* f, void* ws, size_t ws_bytes,
         std::vector<float> tm;
         lbm_tuning unused = t;
         const int r = autotune_impl(
-            b->stream, f, backup, sbytes, std::max<int64_t>(8 * probe_steps, 256),
+            b->stream, f, backup, sbytes, std::max<int64_t>(8 * probe_steps, 1024),
             {t},
             [&](const lbm_tuning&) {
               const int r2 = gs.empty() ? lbm_batch_set_groups(b, 0, nullptr, nullptr)
