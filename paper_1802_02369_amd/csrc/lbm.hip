@@ -553,8 +553,9 @@ template <int P, int EQ>
 __global__ __launch_bounds__(64 * kResWaves, 3) void k_batch_resident(
     const Consts* __restrict__ cs, const int64_t* __restrict__ offs,
     const lbm::ResidentItem* __restrict__ items,
-    const int32_t* __restrict__ wg_first, const double* __restrict__ fin,
-    double* __restrict__ fout, int64_t S, int64_t T) {
+    const int32_t* __restrict__ wg_first, const double* fin, double* fout,
+    int64_t S, int64_t T) {
+  // fin and fout may be the same state (the run is in place): no restrict
   constexpr int WG = kResWaves;
   constexpr int WW = 64 * P;
   constexpr int WS = 62 * P;
