@@ -271,11 +271,15 @@ def test_autotune_restores_state_and_caches(tmp_path):
     assert len(entries) == 1
     (key, val), = entries.items()
     assert key.split("/")[1] == "batch"
+    # lattices of 300 .. 3000 nodes may run resident: the search timed both
+    # modes and stored the one it kept
+    assert key.split("/")[-2] == "res" and val["resident"] in (0, 1)
     assert (val["P"], val["K"], val["W"]) == (t1["nodes_per_lane"], t1["steps_per_launch"],
                                              t1["waves_per_group"])
     b2 = lbm().Batch(offsets, [gpu_params(p) for p in params])
     t2 = b2.autotune(f, probe_steps=16, cache_path=cache)
     assert t2 == t1
+    assert b2.resident_lattices() == b.resident_lattices() == (40 if val["resident"] else 0)
     g1, g2 = b.get_groups(), b2.get_groups()
     assert g1[0] == g2[0] and (g1[1] is None) == (g2[1] is None)
     if g1[1] is not None:
