@@ -627,6 +627,20 @@ def bench_adjoint(torch, lbm, workloads, stream, counter_run=False):
         fwd[name] = n * steps / (fms * 1e-3) / 1e9
     log(f"bench: N={n} forward alone: default tiles {fwd['default']:.2f}, "
         f"one-step kernel {fwd['plain']:.2f} GLUPS")
+    # A lattice this small leaves the chip mostly idle: each step is a chain
+    # of dependent arithmetic per lane, so the time per step, not the issue
+    # rate, bounds it.
+    t = lat.get_tuning()
+    span = t["nodes_per_lane"] * (62 * t["waves_per_group"] + 2) \
+        if t["nodes_per_lane"] > 1 else 64
+    tiles = -(-n // (span - 4 * t["steps_per_launch"]))
+    roof = leg_roofline("adjoint", g * 1e9, GRAD_BYTES_PER_NODE_STEP,
+                        "forward node-step", bytes_basis=GRAD_BYTES_BASIS)
+    roof["latency"] = {
+        "us_per_time_step": ms * 1e3 / steps,
+        "forward_alone_us_per_time_step": n / (fwd["default"] * 1e9) * 1e6,
+        "forward_wavefronts_per_launch": tiles * t["waves_per_group"],
+        "chip_wavefronts_at_two_per_simd": 2048}
     return {"value": g, "unit": "G forward node-steps/s (whole gradient)",
             "n_nodes": n, "time_steps": steps, "ckpt_every": ck,
             "ms_per_gradient": ms, "workspace_gb": aws.numel() * 8 / 1e9,
@@ -634,9 +648,7 @@ def bench_adjoint(torch, lbm, workloads, stream, counter_run=False):
                                "one_step_kernel_glups": fwd["plain"],
                                "gradient_vs_one_step_forward": g / fwd["plain"],
                                "gradient_vs_default_forward": g / fwd["default"]},
-            "roofline": leg_roofline("adjoint", g * 1e9, GRAD_BYTES_PER_NODE_STEP,
-                                     "forward node-step",
-                                     bytes_basis=GRAD_BYTES_BASIS)}
+            "roofline": roof}
 
 
 def bench_batched_adjoint(torch, lbm, workloads, stream, counter_run=False):
