@@ -811,14 +811,14 @@ lbm_tuning fwd_tuning(const lbm_batch* b) { return b->tune; }
 // E of the stored segment states.  Its tiles span P (62 W + 2) nodes
 // (neighbouring wavefronts share two lanes) with halo H = 2K, or 2K + 2 at
 // E = 2 (see k_adjoint_tile).  P = 2 keeps two wavefronts per SIMD (the
-// reverse step needs 190-225 VGPRs at P = 2, over 256 at P = 4), with the
+// reverse step needs 183-241 VGPRs at P = 2, over 256 at P = 4), with the
 // wavefronts that give about the forward tile's width, at least the
 // forward's and at most 4: two workgroups per CU, so that one computes while
 // the other waits at a step's barrier (measured with the earlier two
 // barriers per step: the 1024-lattice gradient's reverse phase took 442 ms
 // at 4 wavefronts, 472 at 8, 512 at 2); a halo too wide for those tiles
 // falls back to P = 4 with 8 wavefronts and E = 1.  A forward of one node
-// per lane (small problems) keeps P = 1, W = 1, E = 1 (about 120 VGPRs).
+// per lane (small problems) keeps P = 1, W = 1, E = 1 (about 110 VGPRs).
 struct RevShape {
   int P, W, H, E;
   int64_t out() const { return (int64_t)tile_nodes(P, W) - 2 * (int64_t)H; }
