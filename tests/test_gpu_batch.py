@@ -457,3 +457,36 @@ def test_resident_run_longer_than_one_launch():
     b.run(f, steps, use_graph=False)
     assert torch.isfinite(ref).all()
     assert torch.equal(f, ref)
+
+
+def test_resident_check_finite_per_launch():
+    """LBM_CHECK_FINITE on a resident lattice of a run longer than one
+    resident launch: a NaN in its state is reported after the first launch's
+    65536 steps, naming that lattice; without the NaN the run is bitwise the
+    unchecked one."""
+    import re
+    rng = np.random.default_rng(78)
+    lens = [40, 300]
+    params = [oracle_params(p) for p in ("paper", "odd")]
+    states = [random_state(rng, L, p, amp=0.02, u=0.01, ds=0.02)
+              for L, p in zip(lens, params)]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    steps = (1 << 16) + 5
+    gp = [gpu_params(p) for p in params]
+    gp[1].flags = lbm().LBM_CHECK_FINITE
+    b = lbm().Batch(offsets, gp)
+    assert b.resident_lattices() == 2
+    f0 = torch.from_numpy(pack(states)).to(dev())
+    ref = f0.clone()
+    lbm().Batch(offsets, [gpu_params(p) for p in params]).run(ref, steps, use_graph=False)
+    f = f0.clone()
+    b.run(f, steps, use_graph=False)
+    assert torch.equal(f, ref)
+    f = f0.clone()
+    f[2, int(offsets[1]) + 11] = float("nan")
+    say("resident check after one launch")
+    with pytest.raises(lbm().LBMError) as e:
+        b.run(f, steps, use_graph=False)
+    assert e.value.code == lbm().LBM_ENONFINITE
+    m = re.search(r"after (\d+) time steps: first failing lattice (\d+)", str(e.value))
+    assert m and int(m.group(1)) == 1 << 16 and int(m.group(2)) == 1, str(e.value)
