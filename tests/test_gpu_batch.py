@@ -490,3 +490,32 @@ def test_resident_check_finite_per_launch():
     assert e.value.code == lbm().LBM_ENONFINITE
     m = re.search(r"after (\d+) time steps: first failing lattice (\d+)", str(e.value))
     assert m and int(m.group(1)) == 1 << 16 and int(m.group(2)) == 1, str(e.value)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_resident_random_batches(seed):
+    """Seeded random batches (lengths 3 .. 7000, some of them resident,
+    random step counts, the section-8 parameter sets): resident and tiled
+    runs bitwise equal."""
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.integers(1, 40))
+    lens = [int(x) for x in np.exp(rng.uniform(np.log(3), np.log(7000), n)).round()]
+    names = [("paper", "odd", "nosource")[int(i)] for i in rng.integers(0, 3, n)]
+    params = [oracle_params(p, s_e=float(s)) for p, s in zip(names, rng.uniform(1.1, 1.8, n))]
+    states = [random_state(rng, L, p, amp=0.05, u=0.02, ds=0.05)
+              for L, p in zip(lens, params)]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    steps = int(rng.integers(1, 120))
+    shape = [(8, 40, 4), (4, 24, 4), (2, 16, 4), (8, 8, 2)][seed % 4]
+    say(f"random batch seed={seed}: {n} lattices, {steps} steps, shape {shape}")
+    b = lbm().Batch(offsets, [gpu_params(p) for p in params])
+    b.set_tuning(*shape)
+    f0 = torch.from_numpy(pack(states)).to(dev())
+    b.set_resident(0)
+    ref = f0.clone()
+    b.run(ref, steps, use_graph=False)
+    b.set_resident(1)
+    f = f0.clone()
+    b.run(f, steps, use_graph=bool(seed & 1))
+    assert torch.isfinite(ref).all()
+    assert torch.equal(f, ref), (b.resident_lattices(), lens)
